@@ -1,0 +1,396 @@
+"""Pins of the CPU FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names what it pins: closed forms of eq. (1.2) / (1.3), library routines
+for the special cases (numpy FFT, scipy I0), brute force with explicit matrices on
+tiny inputs, invariants of the transform, and the error values printed in the
+paper (tests/golden/paper_errors.json, each with its citation).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import oracle as O
+from paper_1810_09891_amd import workloads as W
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_errors.json")))
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+# --------------------------------------------------------------------------- I0 and FFT
+
+
+def test_i0_power_series_matches_scipy():
+    """I0 of the window's Fourier transform: power series vs scipy.special.i0."""
+    for x in np.concatenate([np.linspace(0, 5, 51), np.linspace(5, 80, 76)]):
+        ref = scipy.special.i0(x)
+        assert abs(O.bessel_i0(x) - ref) <= 4e-15 * ref, x
+
+
+@pytest.mark.parametrize("n", [1, 2, 8, 64, 1024, 6, 12, 30, 154])
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_fft_1d_matches_numpy(n, sign):
+    """Unnormalised 1-D DFT, sign - (Algorithm 2.1) and + (Algorithm 2.2), vs numpy."""
+    r = np.random.default_rng(n)
+    a = r.standard_normal(n) + 1j * r.standard_normal(n)
+    ref = np.fft.fft(a) if sign < 0 else np.fft.ifft(a) * n
+    assert rel(O.fft_1d(a, sign), ref) < 1e-14
+    assert rel(O.dft_naive(a, sign), ref) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(8, 16), (4, 8, 2), (32,), (6, 10)])
+def test_fft_d_matches_numpy(shape):
+    r = np.random.default_rng(len(shape))
+    a = r.standard_normal(shape) + 1j * r.standard_normal(shape)
+    assert rel(O.fft_d(a, -1), np.fft.fftn(a)) < 1e-14
+    assert rel(O.fft_d(a, +1), np.fft.ifftn(a) * a.size) < 1e-14
+
+
+# --------------------------------------------------------------------------- NDFT
+
+
+def _centred_k(N):
+    return np.stack(np.meshgrid(*[np.arange(-v // 2, v // 2) for v in N], indexing="ij"), -1).reshape(-1, len(N))
+
+
+@pytest.mark.parametrize("N", [(16,), (8, 6), (4, 6, 2)])
+def test_ndft_single_coefficient_closed_form(N):
+    """eq. (1.2) with fhat = e_{k0}: f_j = exp(-2 pi i k0.x_j) (sign and centred index)."""
+    d = len(N)
+    r = np.random.default_rng(1)
+    x = r.random((37, d)) - 0.5
+    ks = _centred_k(N)
+    for idx in [0, ks.shape[0] // 2, ks.shape[0] - 1, 3]:
+        fh = np.zeros(ks.shape[0], complex)
+        fh[idx] = 1.0
+        f = O.ndft_trafo(x, fh.reshape(N))
+        ref = np.exp(-2j * np.pi * (x @ ks[idx].astype(float)))
+        assert np.max(np.abs(f - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("N", [(16,), (8, 6), (4, 6, 2)])
+def test_ndft_adjoint_single_node_closed_form(N):
+    """eq. (1.3) with f = e_{j0}: hhat_k = exp(+2 pi i k.x_{j0})."""
+    d = len(N)
+    r = np.random.default_rng(2)
+    x = r.random((9, d)) - 0.5
+    ks = _centred_k(N)
+    for j0 in [0, 4, 8]:
+        f = np.zeros(9, complex)
+        f[j0] = 1.0
+        h = O.ndft_adjoint(x, f, N).reshape(-1)
+        ref = np.exp(2j * np.pi * (ks.astype(float) @ x[j0]))
+        assert np.max(np.abs(h - ref)) < 1e-14
+
+
+def test_ndft_matches_dense_fourier_matrix():
+    """Direct sums vs the dense Fourier matrix of the paper's check (Sec. 4.2), d = 2."""
+    N = (12, 10)
+    r = np.random.default_rng(3)
+    x = r.random((50, 2)) - 0.5
+    fh = W.cgauss(r, N)
+    F = np.exp(-2j * np.pi * (x @ _centred_k(N).T.astype(float)))
+    assert rel(O.ndft_trafo(x, fh), F @ fh.reshape(-1)) < 1e-14
+    f = W.cgauss(r, (50,))
+    assert rel(O.ndft_adjoint(x, f, N).reshape(-1), F.conj().T @ f) < 1e-14
+
+
+def test_ndft_is_one_periodic():
+    """The sum is 1-periodic in every coordinate (nodes on the torus, eq. (1.2))."""
+    N = (8, 8)
+    r = np.random.default_rng(4)
+    x = r.random((20, 2)) - 0.5
+    fh = W.cgauss(r, N)
+    shift = np.array([[1.0, -2.0]])
+    assert rel(O.ndft_trafo(x + shift, fh), O.ndft_trafo(x, fh)) < 1e-13
+
+
+# --------------------------------------------------------------------------- NFFT vs NDFT
+
+
+CASES = [
+    (1, (32,), 40),
+    (2, (16, 8), 60),
+    (3, (8, 4, 6), 50),
+]
+
+
+@pytest.mark.parametrize("d,N,M", CASES)
+@pytest.mark.parametrize("kind", ["uniform", "clustered", "wide"])
+def test_nfft_matches_ndft_at_m8(d, N, M, kind):
+    """Algorithm 2.1 / 2.2 with m = 8, n = 2N reach the direct sums to ~1e-14: this
+    fixes the window pair, the deconvolution, the FFT sign, the stencil and the wrap."""
+    c = W.small_case(d, N, M, seed=d, kind=kind)
+    n = tuple(2 * v for v in N)
+    f_ref = O.ndft_trafo(c["x"], c["fhat"])
+    f = O.nfft_trafo(c["x"], c["fhat"], n, 8)
+    assert O.err_l2(f_ref, f) < 5e-14
+    h_ref = O.ndft_adjoint(c["x"], c["f"], N)
+    h = O.nfft_adjoint(c["x"], c["f"], N, n, 8)
+    assert O.err_l2(h_ref, h) < 5e-14
+
+
+def test_nfft_error_falls_with_m():
+    """The window error decreases monotonically in m (Fig. 4.4), down to rounding."""
+    c = W.small_case(2, (16, 16), 200, seed=5)
+    f_ref = O.ndft_trafo(c["x"], c["fhat"])
+    errs = [O.err_l2(f_ref, O.nfft_trafo(c["x"], c["fhat"], (32, 32), m)) for m in range(1, 9)]
+    assert all(errs[i + 1] < errs[i] for i in range(6)), errs
+    assert errs[0] > 1e-3 and errs[-1] < 1e-13
+
+
+@pytest.mark.parametrize("d,N,M", CASES)
+@pytest.mark.parametrize("m", [1, 2, 4, 7])
+def test_nfft_adjoint_identity(d, N, M, m):
+    """<A fhat, f> = <fhat, A^H f>: Algorithm 2.2 is the exact adjoint of Algorithm 2.1."""
+    c = W.small_case(d, N, M, seed=10 + m)
+    n = tuple(2 * v for v in N)
+    lhs = np.vdot(c["f"], O.nfft_trafo(c["x"], c["fhat"], n, m))
+    rhs = np.vdot(O.nfft_adjoint(c["x"], c["f"], N, n, m), c["fhat"])
+    assert abs(lhs - rhs) <= 1e-14 * abs(lhs) * 10
+
+
+# --------------------------------------------------------------------------- brute force
+
+
+def _kb_window_numpy(z, m, b):
+    """Kaiser-Bessel window with its analytic continuation, via numpy's complex sqrt:
+    sinh(b sqrt(m^2-z^2))/(pi sqrt(m^2-z^2)) is real for either sign of m^2-z^2."""
+    a = (m * m - z * z).astype(complex)
+    s = np.sqrt(a)
+    out = np.where(np.abs(s) > 0, np.sinh(b * s) / (np.pi * np.where(np.abs(s) > 0, s, 1.0)), b / np.pi)
+    return out.real
+
+
+def _brute_matrices(N, n, m, x):
+    """Explicit D (|I_n| x |I_N|), F (unnormalised DFT, sign -) and B (M x |I_n|)."""
+    d = len(N)
+    ks = _centred_k(N)
+    nn = int(np.prod(n))
+    D = np.zeros((nn, ks.shape[0]))
+    for col, k in enumerate(ks):
+        pos = np.ravel_multi_index(tuple(int(v) % nt for v, nt in zip(k, n)), n)
+        c = nn
+        for t in range(d):
+            b = np.pi * (2 - N[t] / n[t])
+            arg = m * np.sqrt(b * b - (2 * np.pi * k[t] / n[t]) ** 2)
+            c *= scipy.special.i0(arg) / n[t]
+        D[pos, col] = 1.0 / c
+    ls = np.stack(np.meshgrid(*[np.arange(v) for v in n], indexing="ij"), -1).reshape(-1, d)
+    F = np.ones((nn, nn), complex)
+    for t in range(d):
+        F *= np.exp(-2j * np.pi * np.outer(ls[:, t], ls[:, t]) / n[t])
+    B = np.zeros((x.shape[0], nn))
+    for j in range(x.shape[0]):
+        for pos, l in enumerate(ls):
+            w = 1.0
+            for t in range(d):
+                b = np.pi * (2 - N[t] / n[t])
+                y = n[t] * x[j, t]
+                u = np.floor(y)
+                # the stencil point l_t - u_t + m in {0..2m+1}, modulo n_t
+                s = int((l[t] - u + m) % n[t])
+                if s > 2 * m + 1:
+                    w = 0.0
+                    break
+                w *= _kb_window_numpy(np.array([y - (u + s - m)]), m, b)[0]
+            B[j, pos] = w
+    return D, F, B
+
+
+@pytest.mark.parametrize("N,n,m,M", [((8,), (16,), 2, 5), ((4, 8), (8, 16), 2, 7), ((4, 2, 4), (8, 4, 8), 1, 6)])
+def test_nfft_equals_explicit_matrix_product(N, n, m, M):
+    """A = B F D and A^H = D^T F^H B^T with matrices assembled entry by entry."""
+    c = W.small_case(len(N), N, M, seed=20)
+    x = c["x"]
+    x[0, 0] = -0.5  # a node on the left edge of the torus
+    D, F, B = _brute_matrices(N, n, m, x)
+    A = B @ F @ D
+    assert rel(O.nfft_trafo(x, c["fhat"], n, m), A @ c["fhat"].reshape(-1)) < 1e-13
+    assert rel(O.nfft_adjoint(x, c["f"], N, n, m).reshape(-1), A.conj().T @ c["f"]) < 1e-13
+    g = O.nfft_grid(c["fhat"], n, m).reshape(-1)
+    assert rel(g, F @ D @ c["fhat"].reshape(-1)) < 1e-13
+    assert rel(O.nfft_spread(x, c["f"], N, n, m).reshape(-1), B.T @ c["f"]) < 1e-13
+
+
+# --------------------------------------------------------------------------- invariants
+
+
+def test_nfft_shift_by_grid_step():
+    """Moving every node by s/n is the same as multiplying fhat_k by exp(-2 pi i k.s/n)."""
+    N, n, m = (16, 8), (32, 16), 6
+    c = W.small_case(2, N, 80, seed=30)
+    s = np.array([3, -5])
+    ks = _centred_k(N)
+    phase = np.exp(-2j * np.pi * (ks @ (s / np.array(n)))).reshape(N)
+    a = O.nfft_trafo(c["x"] + s / np.array(n), c["fhat"], n, m)
+    b = O.nfft_trafo(c["x"], c["fhat"] * phase, n, m)
+    assert rel(a, b) < 1e-13
+
+
+def test_nfft_periodic_and_edge_nodes():
+    """Nodes at -1/2, just below +1/2 and shifted by whole periods (torus, eq. (1.2))."""
+    N, n, m = (16,), (32,), 8
+    x = np.array([[-0.5], [0.5 - 2.0 ** -52], [0.0], [0.25], [-0.25 + 2.0 ** -40]])
+    r = np.random.default_rng(31)
+    fh = W.cgauss(r, N)
+    f_ref = O.ndft_trafo(x, fh)
+    assert O.err_l2(f_ref, O.nfft_trafo(x, fh, n, m)) < 1e-14
+    assert O.err_l2(f_ref, O.nfft_trafo(x + 1.0, fh, n, m)) < 1e-13
+    assert O.err_l2(f_ref, O.nfft_trafo(x - 3.0, fh, n, m)) < 1e-13
+
+
+# --------------------------------------------------------------------------- paper values
+
+
+def _paper_errors(d, ms, n_of_N=None):
+    w = W.paper_workload(d)
+    f_ref = O.ndft_trafo(w["x"], w["fhat"])
+    l1 = np.abs(w["fhat"]).sum()
+    out = {}
+    for m in ms:
+        n = tuple(2 * v for v in w["N"]) if n_of_N is None else n_of_N
+        f = O.nfft_trafo(w["x"], w["fhat"], n, m)
+        out[m] = (O.err_l2(f_ref, f), O.err_inf(f_ref, f, l1))
+    return out
+
+
+def _within(a, b, factor):
+    return b / factor <= a <= b * factor
+
+
+def test_paper_table_4_1():
+    """Table 4.1: E_2 and E_inf at the default parameters (n = 2N, m = 8), d = 1, 2, 3."""
+    for d in (1, 2, 3):
+        e2, einf = _paper_errors(d, [8])[8]
+        g = GOLDEN["table_4_1"]["d%d" % d]
+        assert _within(e2, g["E2"], 2.5), (d, e2, g)
+        assert _within(einf, g["Einf"], 2.5), (d, einf, g)
+
+
+def test_paper_fig_4_4_d1():
+    """Fig. 4.4(a) d = 1: E_2 against m = 2..10 at n = 2N (window reading of the paper)."""
+    errs = _paper_errors(1, range(2, 11))
+    for m, (e2, _) in errs.items():
+        assert _within(e2, GOLDEN["fig_4_4_E2"]["d1"][str(m)], 2.0), (m, e2)
+
+
+@pytest.mark.slow
+def test_paper_fig_4_4_d2():
+    """Fig. 4.4(a)/(b) d = 2 at m = 2, 4, 6 (E_2 and E_inf)."""
+    errs = _paper_errors(2, [2, 4, 6])
+    for m, (e2, einf) in errs.items():
+        assert _within(e2, GOLDEN["fig_4_4_E2"]["d2"][str(m)], 2.0), (m, e2)
+        assert _within(einf, GOLDEN["fig_4_4_Einf"]["d2"][str(m)], 2.5), (m, einf)
+
+
+@pytest.mark.slow
+def test_paper_fig_4_4_d3():
+    """Fig. 4.4(a)/(b) d = 3 at m = 2, 4 (E_2 and E_inf)."""
+    errs = _paper_errors(3, [2, 4])
+    for m, (e2, einf) in errs.items():
+        assert _within(e2, GOLDEN["fig_4_4_E2"]["d3"][str(m)], 2.0), (m, e2)
+        assert _within(einf, GOLDEN["fig_4_4_Einf"]["d3"][str(m)], 2.5), (m, einf)
+
+
+def test_paper_fig_4_1_n_sweep():
+    """Fig. 4.1(a): d = 1, m = 8, E_2 against the FFT length n, including lengths
+    that are not powers of two (oracle FFT falls back to the direct DFT there)."""
+    w = W.paper_workload(1)
+    f_ref = O.ndft_trafo(w["x"], w["fhat"])
+    for key, ref in GOLDEN["fig_4_1_E2"].items():
+        if key.startswith("_"):
+            continue
+        e2 = O.err_l2(f_ref, O.nfft_trafo(w["x"], w["fhat"], (int(key),), 8))
+        assert _within(e2, ref, 2.0), (key, e2, ref)
+
+
+@pytest.mark.slow
+def test_paper_fig_4_2_n_sweep():
+    """Fig. 4.2(a): d = 2, m = 8, E_2 against n = 130, 154, 180, 256."""
+    w = W.paper_workload(2)
+    f_ref = O.ndft_trafo(w["x"], w["fhat"])
+    for key, ref in GOLDEN["fig_4_2_E2"].items():
+        if key.startswith("_"):
+            continue
+        nv = int(key)
+        e2 = O.err_l2(f_ref, O.nfft_trafo(w["x"], w["fhat"], (nv, nv), 8))
+        assert _within(e2, ref, 2.0), (key, e2, ref)
+
+
+# --------------------------------------------------------------------------- derivatives
+
+
+def test_kb_derivative_matches_finite_differences():
+    """d phi/dz of the window (both branches and the branch point) vs central differences."""
+    for m in (2, 6, 8):
+        b = O.kb_b(64, 128)
+        for z in np.concatenate([np.linspace(-m - 0.99, m + 0.99, 41), [m - 1e-9, -m + 1e-9, m + 1e-9]]):
+            h = 1e-6
+            fd = (O.kb_phi(z + h, m, b) - O.kb_phi(z - h, m, b)) / (2 * h)
+            scale = max(abs(fd), abs(O.kb_phi(z, m, b)), 1e-300)
+            assert abs(O.kb_dphi(z, m, b) - fd) <= 1e-6 * scale, (m, z)
+
+
+def test_ndft_gradient_matches_finite_differences():
+    """Closed-form gradient of L = ||A(x) fhat - y||^2 (direct sum) vs central differences."""
+    N = (8, 6)
+    r = np.random.default_rng(40)
+    x = r.random((12, 2)) - 0.5
+    fh = W.cgauss(r, N)
+    y = W.cgauss(r, (12,))
+
+    def loss(xx):
+        return np.sum(np.abs(O.ndft_trafo(xx, fh) - y) ** 2)
+
+    g = O.ndft_grad_x(x, fh, O.ndft_trafo(x, fh) - y)
+    h = 1e-7
+    for j in range(12):
+        for t in range(2):
+            xp = x.copy()
+            xm = x.copy()
+            xp[j, t] += h
+            xm[j, t] -= h
+            fd = (loss(xp) - loss(xm)) / (2 * h)
+            assert abs(fd - g[j, t]) <= 1e-6 * max(1.0, abs(g[j, t])), (j, t, fd, g[j, t])
+
+
+def test_nfft_interp_dx_matches_finite_differences():
+    """d f_j / d x_{j,t} through the window vs central differences of the NFFT
+    (the step h keeps floor(n x) fixed, so the stencil does not switch)."""
+    N, n, m = (16, 8), (32, 16), 6
+    c = W.small_case(2, N, 30, seed=41)
+    x = c["x"]
+    # keep every coordinate at least 1e-3 grid steps away from a cell boundary
+    y = x * np.array(n)
+    frac = y - np.floor(y)
+    x = np.where(frac < 1e-3, x + 2e-3 / np.array(n), x)
+    x = np.where(frac > 1 - 1e-3, x - 2e-3 / np.array(n), x)
+    g = O.nfft_grid(c["fhat"], n, m)
+    dx = O.nfft_interp_dx(x, g, N, m)
+    h = 1e-8
+    for t in range(2):
+        xp = x.copy()
+        xm = x.copy()
+        xp[:, t] += h
+        xm[:, t] -= h
+        fd = (O.nfft_interp(xp, g, N, m) - O.nfft_interp(xm, g, N, m)) / (2 * h)
+        assert rel(dx[:, t], fd) < 1e-6
+    # and it approximates the exact derivative of the trigonometric polynomial
+    ks = _centred_k(N)
+    for t in range(2):
+        exact = np.exp(-2j * np.pi * (x @ ks.T.astype(float))) @ (c["fhat"].reshape(-1) * (-2j * np.pi * ks[:, t]))
+        assert rel(dx[:, t], exact) < 1e-9
+
+
+def test_error_measures():
+    """E_2 (eq. (2.15)) and E_inf (eq. (2.16)) on hand-checkable vectors."""
+    ref = np.array([3.0, 4.0j])
+    approx = np.array([3.0, 0.0])
+    assert abs(O.err_l2(ref, approx) - 4.0 / 5.0) < 1e-16
+    assert abs(O.err_inf(ref, approx, 8.0) - 0.5) < 1e-16

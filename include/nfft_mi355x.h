@@ -1,0 +1,223 @@
+/*
+ * nfft_mi355x.h -- C ABI of the MI355X (gfx950) NFFT library.
+ *
+ * The library evaluates the multivariate trigonometric polynomial
+ *     f_j = sum_{k in I_N} fhat_k exp(-2 pi i k . x_j),      j = 0..M-1
+ * (arXiv:1810.09891, Sec. 1 eq. (1.2) and Sec. 2 eq. (2.1)) and its adjoint
+ *     hhat_k = sum_j f_j exp(+2 pi i k . x_j),                k in I_N
+ * (Sec. 1 eq. (1.3)), with I_N = {-N_t/2, ..., N_t/2-1}^d (Sec. 2 eq. (2.2)), by the
+ * NFFT of Algorithm 2.1 (deconvolve, oversampled FFT, window interpolation) and the
+ * adjoint NFFT of Algorithm 2.2 (window spreading, oversampled FFT, deconvolution),
+ * with the Kaiser-Bessel window named in Sec. 4.  The direct sums are available too.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  * Pointers marked [device] are HIP device memory owned by the caller; pointers
+ *    marked [host] are host memory read before the call returns.  The library never
+ *    allocates or frees device memory: all scratch lives in a caller-provided
+ *    workspace (nfft_workspace_bytes / nfft_set_workspace).
+ *  * Every call that does device work enqueues it on the given stream and returns
+ *    without waiting; results are ready when that stream reaches them.
+ *  * Complex data are interleaved (re, im): float2 for NFFT_C64 plans, double2 for
+ *    NFFT_C128 plans.  Node coordinates are always double.
+ *  * Coefficient arrays fhat / hhat have shape N[0] x ... x N[d-1], row-major (last
+ *    index fastest) and centred: position i_t holds frequency k_t = i_t - N_t/2.
+ *  * Node arrays x have shape M x d, row-major; node values f have length M in the
+ *    caller's node order.  Nodes may lie anywhere on the real line; the transform is
+ *    1-periodic in every coordinate (the torus of Sec. 1).
+ *  * Oversampled grids g have shape n[0] x ... x n[d-1], row-major; position l_t holds
+ *    grid index l_t (frequency or spatial index taken modulo n_t).
+ *  * Every function returns an nfft_status.  Argument and state errors are detected
+ *    on the host before anything is enqueued; NFFT_ERR_HIP reports a failed launch.
+ *    Device faults surface at the caller's next synchronisation.
+ *  * A plan is used by one stream at a time; different plans may run concurrently
+ *    on different streams.
+ */
+#ifndef NFFT_MI355X_H
+#define NFFT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nfft_plan_s *nfft_plan;
+typedef struct nfft_batch_s *nfft_batch;
+
+/* Arithmetic type of a plan: complex64 (float data, FP32 window and accumulation,
+ * FP64 node index and deconvolution table) or complex128 (FP64 throughout). */
+typedef enum { NFFT_C64 = 1, NFFT_C128 = 2 } nfft_dtype;
+
+typedef enum {
+    NFFT_OK = 0,
+    NFFT_ERR_ARG = -1,         /* invalid argument (size, pointer, parameter)        */
+    NFFT_ERR_STATE = -2,       /* call out of order (no workspace, no nodes, ...)    */
+    NFFT_ERR_WORKSPACE = -3,   /* workspace missing, too small or misaligned         */
+    NFFT_ERR_HIP = -4,         /* a HIP call or kernel launch failed                 */
+    NFFT_ERR_UNSUPPORTED = -5  /* valid by the paper, not implemented by this library */
+} nfft_status;
+
+/* Plan flags.
+ *  NFFT_SORT_NODES: sort nodes into bins of grid cells before interpolation and
+ *    spreading (the node sorting flag of Sec. 3.1, Table 3.2).  Always on; accepted
+ *    for compatibility.
+ *  NFFT_KEEP_GRID: keep the oversampled grid of the last nfft_trafo in the workspace
+ *    (separate from the grid nfft_adjoint uses), as nfft_grad_x needs it. */
+enum { NFFT_SORT_NODES = 1u << 0, NFFT_KEEP_GRID = 1u << 1 };
+
+/* Read-only description of a plan (filled by nfft_plan_get_info). */
+typedef struct {
+    int d;                  /* dimension, 1..3                                   */
+    int m;                  /* window size (stencil of 2m+2 points per dimension)  */
+    int dtype;              /* nfft_dtype                                        */
+    uint32_t flags;
+    int64_t N[3];           /* bandwidths (unused entries 1)                     */
+    int64_t n[3];           /* FFT lengths (unused entries 1)                    */
+    int64_t M;              /* number of nodes                                   */
+    int64_t bin[3];         /* bin edge, grid cells per dimension                */
+    int64_t nbins;          /* number of bins                                    */
+    int64_t chunk_cap;      /* maximum nodes per work item                       */
+    int64_t max_chunks;     /* upper bound on work items for any node set        */
+    size_t workspace_bytes; /* bytes nfft_set_workspace needs                    */
+    size_t lds_bytes;       /* LDS bytes per workgroup of the window kernels       */
+    double grid_scale;      /* prod_t e^{b_t m}: factor carried by the grids of the
+                               single-step entry points (see there)               */
+} nfft_plan_info;
+
+/* ---------------------------------------------------------------- plans */
+
+/* Create a plan for d-variate transforms with bandwidths N[0..d-1] (even, >= 2;
+ * Sec. 3.1, Table 3.1), M >= 1 nodes, FFT lengths n[0..d-1] and window size m.
+ *   N      [host] d entries.
+ *   n      [host] d entries, or NULL for n_t = 2^(ceil(log2 N_t)+1) (Sec. 2 and Sec. 3.1).
+ *          Each n_t must be even and > N_t (Sec. 3.1); this library needs n_t to be a
+ *          power of two no larger than 4096 (else NFFT_ERR_UNSUPPORTED).
+ *   m      window size >= 1 with 2m+2 <= n_t (m << n_t, Sec. 2 eq. (2.10)); 0 selects the
+ *          default m = 8 (Sec. 3.1).  Values up to 12 are supported when the window
+ *          tile fits the LDS of one workgroup (else NFFT_ERR_UNSUPPORTED).
+ *   dtype  NFFT_C64 or NFFT_C128.
+ * Host only: no device work, no device memory.  *out receives the plan. */
+int nfft_plan_create(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
+                     nfft_dtype dtype, uint32_t flags);
+
+/* Destroy a plan.  Host only; frees nothing the caller owns (not the workspace). */
+int nfft_plan_destroy(nfft_plan p);
+
+/* Fill *info (host struct). */
+int nfft_plan_get_info(nfft_plan p, nfft_plan_info *info);
+
+/* Bytes of device workspace the plan needs (host only). */
+int nfft_workspace_bytes(nfft_plan p, size_t *bytes);
+
+/* Attach a caller-owned device workspace of `bytes` bytes, 256-byte aligned.  The
+ * plan keeps the pointer until the next nfft_set_workspace or nfft_plan_destroy;
+ * the caller keeps the memory alive meanwhile.  Attaching a workspace forgets the
+ * nodes (nfft_set_nodes must follow).  NFFT_ERR_WORKSPACE if too small or misaligned. */
+int nfft_set_workspace(nfft_plan p, void *ws, size_t bytes);
+
+/* Set the M nodes x [device, M x d doubles] and run the node precomputation (the
+ * p.x = A step of Sec. 4.2): per node and dimension u = floor(n_t x) and
+ * delta = n_t x - u in FP64 (stencil index set, Sec. 2 eq. (2.13)), then a counting
+ * sort of the nodes into bins of grid cells.  The derived data and a copy of x (read
+ * by the direct sums) live in the workspace; the caller's x is not referenced after
+ * the enqueued work has run.  Non-finite coordinates give non-finite results for those
+ * nodes (and, in the adjoint, for the grid cells they touch). */
+int nfft_set_nodes(nfft_plan p, const double *x, hipStream_t stream);
+
+/* ---------------------------------------------------------------- transforms */
+
+/* NFFT, Algorithm 2.1: f [device, M] = A fhat for fhat [device, shape N].
+ * NFFT_ERR_STATE before nfft_set_nodes. */
+int nfft_trafo(nfft_plan p, const void *fhat, void *f, hipStream_t stream);
+
+/* Adjoint NFFT, Algorithm 2.2: hhat [device, shape N] = A^H f for f [device, M]. */
+int nfft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t stream);
+
+/* Direct sums eq. (1.2) / (1.3) on the device, O(M |I_N|) work: f = NDFT(fhat) and
+ * hhat = NDFT^H(f).  Phases k.x are formed in FP64 and reduced before the
+ * exponential; the sums accumulate in the plan's precision.  Need nfft_set_nodes
+ * (they read the nodes' FP64 coordinates kept by it). */
+int ndft_trafo(nfft_plan p, const void *fhat, void *f, hipStream_t stream);
+int ndft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t stream);
+
+/* Gradient of the NFFT output with respect to the nodes, contracted with an upstream
+ * vector v [device, M complex]:
+ *     grad_x[j][t] = Re( conj(v_j) * d f_j / d x_{j,t} ),
+ * where f = nfft_trafo(fhat) and the derivative is taken through the window of
+ * Algorithm 2.1 step 3 (d/dx_t phi(n_t x_t - l_t) = n_t phi'(.)).  grad_x [device,
+ * M x d] is float for NFFT_C64 plans and double for NFFT_C128 plans.  Needs
+ * NFFT_KEEP_GRID and a preceding nfft_trafo on the same nodes (its grid is used);
+ * else NFFT_ERR_STATE. */
+int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t stream);
+
+/* ---------------------------------------------------------------- single steps */
+/* The transforms above are compositions of these steps; they are exposed so each step
+ * can be checked and timed on its own.  g is a caller grid [device, shape n].
+ *
+ * Grid scaling: the library evaluates the Kaiser-Bessel window divided by e^{b_t m} in
+ * every dimension (b_t = pi (2 - N_t/n_t)), which keeps FP32 window values accurate,
+ * and carries the inverse factor in the deconvolution.  The grids these steps exchange
+ * are therefore the grids of Algorithms 2.1 / 2.2 multiplied by S = prod_t e^{b_t m}
+ * (forward, nfft_step_grid) or divided by S (adjoint, nfft_step_spread), and
+ * nfft_step_interp / nfft_step_coeffs expect grids scaled the same way.  S is reported
+ * as nfft_plan_info.grid_scale.  Composed, the steps give exactly nfft_trafo and
+ * nfft_adjoint. */
+
+/* Steps 1-2 of Algorithm 2.1: g = S F D fhat (deconvolution with zero padding onto I_n,
+ * eq. (2.9), then the d-variate FFT with sign -, unnormalised). */
+int nfft_step_grid(nfft_plan p, const void *fhat, void *g, hipStream_t stream);
+
+/* Step 3 of Algorithm 2.1: f_j = S^{-1} sum over the 2m+2 stencil points per dimension
+ * of g_l * prod_t phi_t(n_t x_{j,t} - l_t) (eq. (2.12)-(2.13)). */
+int nfft_step_interp(nfft_plan p, const void *g, void *f, hipStream_t stream);
+
+/* Step 1 of Algorithm 2.2: g_l = S^{-1} sum_j f_j prod_t phi_t(n_t x_{j,t} - l_t) (the
+ * transposed index set of Sec. 2).  Every cell of g is written. */
+int nfft_step_spread(nfft_plan p, const void *f, void *g, hipStream_t stream);
+
+/* Steps 2-3 of Algorithm 2.2: hhat = S D^H F^H g (FFT with sign +, unnormalised, only
+ * frequencies in I_N kept, then the deconvolution). */
+int nfft_step_coeffs(nfft_plan p, const void *g, void *hhat, hipStream_t stream);
+
+/* ---------------------------------------------------------------- timing */
+
+/* Kernel timing with HIP events recorded around every kernel the plan launches, on
+ * the stream of the launching call.  Enable before the calls to be timed; read after
+ * synchronising that stream.  names[i] / total_ms[i] / launches[i] are filled for up
+ * to `cap` kernels (host arrays); *count receives the number of distinct kernels.
+ * Reading resets the counters. */
+int nfft_profile_enable(nfft_plan p, int on);
+int nfft_profile_read(nfft_plan p, const char **names, double *total_ms, int64_t *launches, int cap,
+                      int *count);
+
+/* ---------------------------------------------------------------- batches */
+
+/* A batch runs many independent plans (each with its own nodes, set through
+ * nfft_set_nodes on its own workspace) with one persistent launch per step kind.
+ *   plans      [host] `count` plans, all NFFT_C64 or all NFFT_C128, each with a
+ *              workspace attached.
+ *   tune_cache [host] path of a text file caching autotuned launch parameters, or NULL.
+ * nfft_batch_workspace_bytes / nfft_batch_set_workspace attach the batch's own small
+ * device table.  nfft_batch_trafo / nfft_batch_adjoint take host arrays of `count`
+ * device pointers.  nfft_batch_autotune times candidate launch shapes on `stream`,
+ * synchronising it, and records the fastest (in the cache file when one is given). */
+int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const char *tune_cache);
+int nfft_batch_workspace_bytes(nfft_batch b, size_t *bytes);
+int nfft_batch_set_workspace(nfft_batch b, void *ws, size_t bytes);
+int nfft_batch_autotune(nfft_batch b, hipStream_t stream);
+int nfft_batch_trafo(nfft_batch b, const void *const *fhat, void *const *f, hipStream_t stream);
+int nfft_batch_adjoint(nfft_batch b, const void *const *f, void *const *hhat, hipStream_t stream);
+int nfft_batch_destroy(nfft_batch b);
+
+/* Human-readable name of a status code (static string). */
+const char *nfft_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFFT_MI355X_H */

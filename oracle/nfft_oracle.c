@@ -602,3 +602,23 @@ int or_get_threads(void) { return omp_get_max_threads(); }
 void or_set_threads(int nt) { (void)nt; }
 int or_get_threads(void) { return 1; }
 #endif
+
+/* hhat_k of eq. (1.3) for the `nsel` centred row-major positions listed in sel
+ * (for checks of single outputs of a large transform). */
+void or_ndft_adjoint_at(int d, const long *N, long M, const double *x, const cplx *f, long nsel, const long *sel,
+                        cplx *out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long q = 0; q < nsel; ++q) {
+        long k[3];
+        centred_k(d, N, sel[q], k);
+        cplx acc = 0.0;
+        for (long j = 0; j < M; ++j) {
+            cplx e = 1.0;
+            for (int t = 0; t < d; ++t)
+                e *= expo1(k[t], x[j * d + t], +1);
+            acc += f[j] * e;
+        }
+        out[q] = acc;
+    }
+}

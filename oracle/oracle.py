@@ -55,6 +55,7 @@ def _load():
             "or_ndft_trafo": (None, [Ii, P, L, P, P, P]),
             "or_ndft_adjoint": (None, [Ii, P, L, P, P, P]),
             "or_ndft_grad_x": (None, [Ii, P, L, P, P, P, P]),
+            "or_ndft_adjoint_at": (None, [Ii, P, L, P, P, L, P, P]),
             "or_nfft_deconv": (None, [Ii, P, P, Ii, P, P]),
             "or_nfft_deconv_adj": (None, [Ii, P, P, Ii, P, P]),
             "or_nfft_interp": (None, [Ii, P, P, Ii, L, P, P, P]),
@@ -161,6 +162,18 @@ def ndft_adjoint(x, f, N):
     M, d = x.shape
     out = np.empty(tuple(N), dtype=np.complex128)
     _load().or_ndft_adjoint(d, _p(N), M, _p(x), _p(f), _p(out))
+    return out
+
+
+def ndft_adjoint_at(x, f, N, flat_idx):
+    """hhat at the given flat (centred, row-major) coefficient positions."""
+    x = _f64(x)
+    f = _c128(f)
+    N = _dims(N)
+    sel = _dims(flat_idx)
+    M, d = x.shape
+    out = np.empty(sel.size, dtype=np.complex128)
+    _load().or_ndft_adjoint_at(d, _p(N), M, _p(x), _p(f), sel.size, _p(sel), _p(out))
     return out
 
 

@@ -1,1 +1,10 @@
-"""MI355X-native NFFT (placeholder: the HIP binding is added with the library)."""
+"""MI355X-native NFFT: the transforms of arXiv:1810.09891 (Algorithm 2.1 / 2.2) as
+hand-written HIP kernels for gfx950 behind a C ABI (include/nfft_mi355x.h).
+
+    from paper_1810_09891_amd import Plan
+    p = Plan((512, 512), M, m=8, dtype=torch.complex64).set_nodes(x)
+    f = p.trafo(fhat)        # NFFT
+    h = p.adjoint(f)         # adjoint NFFT
+"""
+from .nfft import Plan, default_n  # noqa: F401
+from ._lib import NFFT_KEEP_GRID, NFFT_SORT_NODES, NfftError, load  # noqa: F401

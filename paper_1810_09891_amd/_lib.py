@@ -1,0 +1,118 @@
+"""ctypes loader of ``lib/libnfft_mi355x.so`` with the signatures of ``include/nfft_mi355x.h``.
+
+Argument marshalling only: every step of the transforms runs in the HIP library.  If the
+library has not been built, loading raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libnfft_mi355x.so")
+
+NFFT_C64 = 1
+NFFT_C128 = 2
+NFFT_SORT_NODES = 1 << 0
+NFFT_KEEP_GRID = 1 << 1
+
+STATUS = {
+    0: "NFFT_OK",
+    -1: "NFFT_ERR_ARG",
+    -2: "NFFT_ERR_STATE",
+    -3: "NFFT_ERR_WORKSPACE",
+    -4: "NFFT_ERR_HIP",
+    -5: "NFFT_ERR_UNSUPPORTED",
+}
+
+# every exported entry point of include/nfft_mi355x.h
+ABI_SYMBOLS = [
+    "nfft_plan_create", "nfft_plan_destroy", "nfft_plan_get_info", "nfft_workspace_bytes",
+    "nfft_set_workspace", "nfft_set_nodes", "nfft_trafo", "nfft_adjoint", "ndft_trafo",
+    "ndft_adjoint", "nfft_grad_x", "nfft_step_grid", "nfft_step_interp", "nfft_step_spread",
+    "nfft_step_coeffs", "nfft_profile_enable", "nfft_profile_read", "nfft_batch_create",
+    "nfft_batch_workspace_bytes", "nfft_batch_set_workspace", "nfft_batch_autotune",
+    "nfft_batch_trafo", "nfft_batch_adjoint", "nfft_batch_destroy", "nfft_status_string",
+]
+
+
+class NfftError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(status, "?"), status))
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("m", ctypes.c_int),
+        ("dtype", ctypes.c_int),
+        ("flags", ctypes.c_uint32),
+        ("N", ctypes.c_int64 * 3),
+        ("n", ctypes.c_int64 * 3),
+        ("M", ctypes.c_int64),
+        ("bin", ctypes.c_int64 * 3),
+        ("nbins", ctypes.c_int64),
+        ("chunk_cap", ctypes.c_int64),
+        ("max_chunks", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("lds_bytes", ctypes.c_size_t),
+        ("grid_scale", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "the HIP library %s is missing: build it with paper_1810_09891_amd.build.build() "
+            "(there is no fallback path)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    sig = {
+        "nfft_plan_create": [ctypes.POINTER(P), I, ctypes.POINTER(I64), I64, ctypes.POINTER(I64), I, I,
+                             ctypes.c_uint32],
+        "nfft_plan_destroy": [P],
+        "nfft_plan_get_info": [P, ctypes.POINTER(PlanInfo)],
+        "nfft_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "nfft_set_workspace": [P, P, ctypes.c_size_t],
+        "nfft_set_nodes": [P, P, P],
+        "nfft_trafo": [P, P, P, P],
+        "nfft_adjoint": [P, P, P, P],
+        "ndft_trafo": [P, P, P, P],
+        "ndft_adjoint": [P, P, P, P],
+        "nfft_grad_x": [P, P, P, P],
+        "nfft_step_grid": [P, P, P, P],
+        "nfft_step_interp": [P, P, P, P],
+        "nfft_step_spread": [P, P, P, P],
+        "nfft_step_coeffs": [P, P, P, P],
+        "nfft_profile_enable": [P, I],
+        "nfft_profile_read": [P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(I64), I, ctypes.POINTER(I)],
+        "nfft_batch_create": [ctypes.POINTER(P), I, ctypes.POINTER(P), ctypes.c_char_p],
+        "nfft_batch_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "nfft_batch_set_workspace": [P, P, ctypes.c_size_t],
+        "nfft_batch_autotune": [P, P],
+        "nfft_batch_trafo": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
+        "nfft_batch_adjoint": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
+        "nfft_batch_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = I
+    lib.nfft_status_string.argtypes = [I]
+    lib.nfft_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status, what):
+    if status != 0:
+        raise NfftError(status, what)

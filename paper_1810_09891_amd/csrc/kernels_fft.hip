@@ -1,0 +1,323 @@
+// The d-variate FFT of Algorithm 2.1 step 2 (sign -) and Algorithm 2.2 step 2 (sign +),
+// unnormalised, as one kernel pass per dimension over the oversampled grid, in place.
+//
+// A workgroup loads `nl` lines of length L = n_t into LDS, transforms them with a
+// Stockham autosort FFT (radix 8, 4 and 2 stages, in place between barriers) and writes
+// them back.  Only nonzero data is read and only needed data is written:
+//  * forward, dimension d-1 first: the deconvolution of Algorithm 2.1 step 1 (eq. (2.9))
+//    is fused into the load -- the pass reads the coefficient rows, multiplies them by
+//    the FP64 factors prod_t w_t[k_t] = prod_t e^{b_t m} / I0(...), and zero-pads them
+//    onto the n_{d-1} line at positions k mod n; only the prod_{q<d-1} N_q rows holding
+//    coefficients are transformed;
+//  * forward, later passes over dimension t read only the N_t nonzero entries of each
+//    line and transform only lines whose indices in dimensions q < t are in I_N;
+//  * adjoint passes run t = 0, 1, ..., d-1 and keep only the N_t entries with k in I_N;
+//    the last pass applies the deconvolution of Algorithm 2.2 step 3 and writes the
+//    centred coefficient array.
+#include "launch.hpp"
+
+namespace nfft {
+
+namespace {
+
+// multiplication by SIGN * i
+template <typename C, int SIGN> __device__ __forceinline__ C rot(C z)
+{
+    return SIGN < 0 ? C{z.y, -z.x} : C{-z.y, z.x};
+}
+
+template <typename C, int SIGN> __device__ __forceinline__ void dft2(C *v)
+{
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename C, int SIGN> __device__ __forceinline__ void dft4(C &a0, C &a1, C &a2, C &a3)
+{
+    C t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = rot<C, SIGN>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+template <typename C, int SIGN> __device__ __forceinline__ void dft4v(C *v) { dft4<C, SIGN>(v[0], v[1], v[2], v[3]); }
+
+// X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k with E, O the 4-point DFTs of the even
+// and odd inputs, W8 = e^{SIGN 2 pi i / 8}.
+template <typename C, int SIGN> __device__ __forceinline__ void dft8v(C *v)
+{
+    using T = decltype(v[0].x);
+    const T h = T(0.707106781186547524400844362104849039);
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<C, SIGN>(e0, e1, e2, e3);
+    dft4<C, SIGN>(o0, o1, o2, o3);
+    // W8^1 z = h (z + SIGN i z); W8^2 z = SIGN i z; W8^3 z = h (SIGN i z - z)
+    C r1 = rot<C, SIGN>(o1);
+    o1 = cscale(cadd(o1, r1), h);
+    o2 = rot<C, SIGN>(o2);
+    C r3 = rot<C, SIGN>(o3);
+    o3 = cscale(csub(r3, o3), h);
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+template <typename C, int SIGN, int R> __device__ __forceinline__ void dftR(C *v)
+{
+    if constexpr (R == 2)
+        dft2<C, SIGN>(v);
+    else if constexpr (R == 4)
+        dft4v<C, SIGN>(v);
+    else
+        dft8v<C, SIGN>(v);
+}
+
+// One radix-R Stockham stage over nl lines of length L held in LDS (pitch elements per
+// line).  Ns = product of the radices of the earlier stages.  Job (line, j), j < L/R,
+// reads x[j + r L/R], multiplies input r by w^{(j mod Ns) r / (Ns R)} with
+// w = e^{SIGN 2 pi i}, transforms, and writes y[(j / Ns) Ns R + (j mod Ns) + r Ns].
+template <typename T, int VPT, int SIGN, int R>
+__device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, int pitch, int lgNs,
+                                          const Cplx<T> *tw)
+{
+    using C = Cplx<T>;
+    constexpr int J = VPT >= R ? VPT / R : 1;
+    constexpr int lgR = R == 8 ? 3 : R == 4 ? 2 : 1;
+    const int lgJobs = lgL - lgR;  // jobs per line = L / R
+    const int jobs = nl << lgJobs;
+    const int Ns = 1 << lgNs;
+    const int twStep = lgL - lgNs - lgR;  // L / (Ns R) = 2^twStep
+    C v[J][R];
+    int base[J];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        int b = threadIdx.x + q * kBlock;
+        base[q] = -1;
+        if (b < jobs) {
+            int line = b >> lgJobs;
+            int j = b & ((1 << lgJobs) - 1);
+            const C *src = lds + line * pitch + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[q][r] = src[r << lgJobs];
+            int jm = j & (Ns - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C w = tw[(jm * r) << twStep];
+                if (SIGN > 0)
+                    w.y = -w.y;
+                v[q][r] = cmul(v[q][r], w);
+            }
+            dftR<C, SIGN, R>(v[q]);
+            base[q] = line * pitch + ((j >> lgNs) << (lgNs + lgR)) + jm;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        if (base[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                lds[base[q] + r * Ns] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Position of centred coefficient index p (k = p - N/2) on a line of length n.
+__device__ __forceinline__ int coef_to_pos(int p, int N, int n) { return p < N / 2 ? p - N / 2 + n : p - N / 2; }
+// Inverse: centred index of line position i, or -1 when k = i (mod n) is not in I_N.
+__device__ __forceinline__ int pos_to_coef(int i, int N, int n)
+{
+    if (i < N / 2)
+        return i + N / 2;
+    if (i >= n - N / 2)
+        return i - n + N / 2;
+    return -1;
+}
+
+// Per-line data of a line group, computed once per group by the first nl threads.
+// Rows (t = d-1): row index r over the pruned dimensions q < d-1.  Columns (t < d-1):
+// outer index over dimensions q not in {t, d-1} (pruned when q < t), times a block of
+// nl consecutive positions of dimension d-1.  gbase < 0 marks a line past the end.
+__device__ __forceinline__ void line_info(const FftPass &p, int g, int c, int64_t &gbase, int &cbase,
+                                          double &fac)
+{
+    gbase = 0;
+    cbase = 0;
+    fac = 1.0;
+    if (p.rows) {
+        int r = g * p.nl + c;
+        if (r >= p.nrows) {
+            gbase = -1;
+            return;
+        }
+        cbase = r * p.N[p.d - 1];
+        int rr = r;
+        for (int q = p.d - 2; q >= 0; --q) {
+            int pq = rr % p.N[q];
+            rr /= p.N[q];
+            gbase += (int64_t)coef_to_pos(pq, p.N[q], p.n[q]) * p.stride[q];
+            if (p.in_mode == 0 || p.out_mode == 2)
+                fac *= p.w[q][pq];
+        }
+        return;
+    }
+    int o = g / p.ncb;
+    int cb = g - o * p.ncb;
+    gbase = (int64_t)cb * p.nl + c;  // stride of dimension d-1 is 1
+    for (int q = p.d - 2; q >= 0; --q) {
+        if (q == p.t)
+            continue;
+        int ext = q < p.t ? p.N[q] : p.n[q];
+        int iq = o % ext;
+        o /= ext;
+        if (q < p.t)
+            iq = coef_to_pos(iq, p.N[q], p.n[q]);
+        gbase += (int64_t)iq * p.stride[q];
+    }
+}
+
+constexpr int kMaxLines = 256;
+
+template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass p)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int64_t s_gbase[kMaxLines];
+    __shared__ int s_cbase[kMaxLines];
+    __shared__ double s_fac[kMaxLines];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    C *grid = static_cast<C *>(p.grid);
+    const C *tw = static_cast<const C *>(p.tw);
+    const int L = p.L, nl = p.nl, pitch = p.pitch;
+    const int lgL = 31 - __clz(L);
+    const int lgnl = 31 - __clz(nl);
+    const int total = nl * L;
+    const int t = p.t;
+    const int Nt = p.N[t];
+    const int64_t st = p.stride[t];
+    const double *wt = p.w[t];
+    const C *fin = static_cast<const C *>(p.fin);
+    C *fout = static_cast<C *>(p.fout);
+
+    for (int g = blockIdx.x; g < (int)p.ngroups; g += gridDim.x) {
+        if (threadIdx.x < nl)
+            line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
+        __syncthreads();
+        // ---------------- load
+        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+            int c, i;
+            if (p.rows) {
+                c = idx >> lgL;
+                i = idx & (L - 1);
+            } else {
+                c = idx & (nl - 1);
+                i = idx >> lgnl;
+            }
+            const int64_t gb = s_gbase[c];
+            C val = C{T(0), T(0)};
+            if (gb >= 0) {
+                if (p.in_mode == 0) {
+                    int pc = pos_to_coef(i, Nt, L);
+                    if (pc >= 0) {
+                        C a = fin[s_cbase[c] + pc];
+                        double f = s_fac[c] * wt[pc];
+                        val = C{(T)((double)a.x * f), (T)((double)a.y * f)};
+                    }
+                } else if (p.in_mode == 1) {
+                    if (pos_to_coef(i, Nt, L) >= 0)
+                        val = grid[gb + i * st];
+                } else {
+                    val = grid[gb + i * st];
+                }
+            }
+            lds[c * pitch + i] = val;
+        }
+        __syncthreads();
+
+        // ---------------- transform: radix 8 stages, then one radix 4 or 2 stage
+        int lgNs = 0;
+        while (lgL - lgNs >= 3) {
+            fft_stage<T, VPT, SIGN, 8>(lds, L, lgL, nl, pitch, lgNs, tw);
+            lgNs += 3;
+        }
+        if (lgL - lgNs == 2) {
+            fft_stage<T, VPT, SIGN, 4>(lds, L, lgL, nl, pitch, lgNs, tw);
+        } else if (lgL - lgNs == 1) {
+            fft_stage<T, VPT, SIGN, 2>(lds, L, lgL, nl, pitch, lgNs, tw);
+        }
+
+        // ---------------- store
+        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+            int c, i;
+            if (p.rows) {
+                c = idx >> lgL;
+                i = idx & (L - 1);
+            } else {
+                c = idx & (nl - 1);
+                i = idx >> lgnl;
+            }
+            const int64_t gb = s_gbase[c];
+            if (gb < 0)
+                continue;
+            C val = lds[c * pitch + i];
+            if (p.out_mode == 0) {
+                grid[gb + i * st] = val;
+            } else {
+                int pc = pos_to_coef(i, Nt, L);
+                if (pc < 0)
+                    continue;
+                if (p.out_mode == 1) {
+                    grid[gb + i * st] = val;
+                } else {
+                    double f = s_fac[c] * wt[pc];
+                    fout[s_cbase[c] + pc] = C{(T)((double)val.x * f), (T)((double)val.y * f)};
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int blocks, hipStream_t s)
+{
+    size_t lds = (size_t)p.nl * p.pitch * sizeof(Cplx<T>);
+    dim3 grid(blocks), block(kBlock);
+#define NFFT_FFT_CALL(V)                                                                               \
+    {                                                                                                  \
+        auto kf = k_fft_pass<T, V, SIGN>;                                                              \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kf, grid, block, lds, s, p);                                                \
+    }
+    switch (p.vpt) {
+    case 1: NFFT_FFT_CALL(1); break;
+    case 2: NFFT_FFT_CALL(2); break;
+    case 4: NFFT_FFT_CALL(4); break;
+    case 8: NFFT_FFT_CALL(8); break;
+    case 16: NFFT_FFT_CALL(16); break;
+    case 32: NFFT_FFT_CALL(32); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef NFFT_FFT_CALL
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fft_pass(const FftPass &p, bool dbl, int blocks, hipStream_t s)
+{
+    if (dbl)
+        return p.sign < 0 ? launch_typed<double, -1>(p, blocks, s) : launch_typed<double, 1>(p, blocks, s);
+    return p.sign < 0 ? launch_typed<float, -1>(p, blocks, s) : launch_typed<float, 1>(p, blocks, s);
+}
+
+}  // namespace nfft

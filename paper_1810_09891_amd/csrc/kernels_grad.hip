@@ -1,0 +1,166 @@
+// Gradient of the interpolation (Algorithm 2.1 step 3) with respect to the nodes.
+// Geometry as in window_common.hpp.
+#include "window_common.hpp"
+
+namespace nfft {
+
+namespace {
+
+using namespace window;
+
+// ------------------------------------------------------------------ gradient
+
+// grad[j][t] = Re(conj(v_j) * n_t * sum_s g[u+s] phi_t'(.) prod_{t' != t} phi_t'(.)).
+template <typename T, int D, int WM>
+__global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
+                                                   const Cplx<T> *__restrict__ v, T *__restrict__ grad)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *tile = reinterpret_cast<C *>(smem_raw);
+    const int nchunks = nd.counters[0];
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int bin = nd.chunk_bin[c];
+        const int first = nd.chunk_first[c];
+        const int len = nd.chunk_len[c];
+        int bc[kMaxDim];
+        bin_coords<T, D>(g, bin, bc);
+        stage_tile<T, D>(g, bc, grid, tile);
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int node = first + i;
+            int ul[kMaxDim];
+            T dl[kMaxDim];
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
+                dl[t] = static_cast<const T *>(nd.delta[t])[node];
+            }
+            T wl[WM], dwl[WM];
+            window_row_d<T, WM>(dl[D - 1], g, D - 1, wl, dwl);
+            C acc[kMaxDim];
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                acc[t] = C{T(0), T(0)};
+            if constexpr (D == 1) {
+                const C *row = tile + ul[0];
+#pragma unroll
+                for (int s = 0; s < WM; ++s) {
+                    C gv = row[s];
+                    acc[0].x += dwl[s] * gv.x;
+                    acc[0].y += dwl[s] * gv.y;
+                }
+            } else if constexpr (D == 2) {
+                const T m = (T)g.m, b0 = (T)g.b[0], e0 = (T)g.emb[0];
+                for (int s0 = 0; s0 < g.W; ++s0) {
+                    const T w0 = kb_point<T>(dl[0], s0, g.W, m, b0, e0);
+                    const T dw0 = kb_point_d<T>(dl[0], s0, g.W, m, b0, e0);
+                    const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
+                    T rx = 0, ry = 0, dx = 0, dy = 0;
+#pragma unroll
+                    for (int s1 = 0; s1 < WM; ++s1) {
+                        C gv = row[s1];
+                        rx += wl[s1] * gv.x;
+                        ry += wl[s1] * gv.y;
+                        dx += dwl[s1] * gv.x;
+                        dy += dwl[s1] * gv.y;
+                    }
+                    acc[0].x += dw0 * rx;
+                    acc[0].y += dw0 * ry;
+                    acc[1].x += w0 * dx;
+                    acc[1].y += w0 * dy;
+                }
+            } else {
+                T wmid[WM], dwmid[WM];
+                window_row_d<T, WM>(dl[1], g, 1, wmid, dwmid);
+                const T m = (T)g.m, b0 = (T)g.b[0], e0 = (T)g.emb[0];
+                const int P1 = g.P[1], P2 = g.P[2];
+                for (int s0 = 0; s0 < g.W; ++s0) {
+                    const T w0 = kb_point<T>(dl[0], s0, g.W, m, b0, e0);
+                    const T dw0 = kb_point_d<T>(dl[0], s0, g.W, m, b0, e0);
+                    const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
+                    T px = 0, py = 0, qx = 0, qy = 0, hx = 0, hy = 0;
+#pragma unroll
+                    for (int s1 = 0; s1 < WM; ++s1) {
+                        const C *row = plane + s1 * P2;
+                        T rx = 0, ry = 0, dx = 0, dy = 0;
+#pragma unroll
+                        for (int s2 = 0; s2 < WM; ++s2) {
+                            C gv = row[s2];
+                            rx += wl[s2] * gv.x;
+                            ry += wl[s2] * gv.y;
+                            dx += dwl[s2] * gv.x;
+                            dy += dwl[s2] * gv.y;
+                        }
+                        px += wmid[s1] * rx;  // plain in dims 1, 2
+                        py += wmid[s1] * ry;
+                        qx += dwmid[s1] * rx;  // derivative in dim 1
+                        qy += dwmid[s1] * ry;
+                        hx += wmid[s1] * dx;  // derivative in dim 2
+                        hy += wmid[s1] * dy;
+                    }
+                    acc[0].x += dw0 * px;
+                    acc[0].y += dw0 * py;
+                    acc[1].x += w0 * qx;
+                    acc[1].y += w0 * qy;
+                    acc[2].x += w0 * hx;
+                    acc[2].y += w0 * hy;
+                }
+            }
+            const int j = nd.perm[node];
+            const C vj = v[j];
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                grad[(int64_t)j * D + t] = (T)g.n[t] * (vj.x * acc[t].x + vj.y * acc[t].y);
+        }
+        __syncthreads();
+    }
+}
+
+#define NFFT_WM_SWITCH(WMV, CALL)                                                                       \
+    switch (WMV) {                                                                                     \
+    case 6: CALL(6); break;                                                                            \
+    case 10: CALL(10); break;                                                                          \
+    case 14: CALL(14); break;                                                                          \
+    case 18: CALL(18); break;                                                                          \
+    case 22: CALL(22); break;                                                                          \
+    case 26: CALL(26); break;                                                                          \
+    default: return hipErrorInvalidValue;                                                              \
+    }
+
+#define NFFT_DT_SWITCH(FN, ...)                                                                        \
+    switch (g.d * 2 + (dbl ? 1 : 0)) {                                                                 \
+    case 2: return FN<float, 1>(__VA_ARGS__);                                                          \
+    case 3: return FN<double, 1>(__VA_ARGS__);                                                         \
+    case 4: return FN<float, 2>(__VA_ARGS__);                                                          \
+    case 5: return FN<double, 2>(__VA_ARGS__);                                                         \
+    case 6: return FN<float, 3>(__VA_ARGS__);                                                          \
+    case 7: return FN<double, 3>(__VA_ARGS__);                                                         \
+    default: return hipErrorInvalidValue;                                                              \
+    }
+
+template <typename T, int D>
+hipError_t grad_typed(const Geom &g, const Nodes &nd, const void *grid, const void *v, void *grad, int blocks,
+                      size_t lds, hipStream_t s)
+{
+    using C = Cplx<T>;
+#define CALL(W_)                                                                                       \
+    {                                                                                                  \
+        auto kf = k_grad_x<T, D, W_>;                                                                  \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, g, nd, static_cast<const C *>(grid), \
+                           static_cast<const C *>(v), static_cast<T *>(grad));                         \
+    }
+    NFFT_WM_SWITCH(g.WM, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_grad_x(const Geom &g, const Nodes &nd, bool dbl, const void *grid, const void *v, void *grad,
+                         int blocks, size_t lds, hipStream_t s)
+{
+    NFFT_DT_SWITCH(grad_typed, g, nd, grid, v, grad, blocks, lds, s)
+}
+
+}  // namespace nfft

@@ -1,0 +1,183 @@
+// Window kernels: interpolation (Algorithm 2.1 step 3), spreading (Algorithm 2.2 step 1)
+// and the gradient of the interpolation with respect to the nodes.
+//
+// Nodes are sorted into bins of B_0 x ... x B_{d-1} grid cells and cut into work items of
+// at most chunk_cap nodes of one bin.  The stencil of a node with u = floor(n x) covers
+// the 2m+2 grid indices u-m .. u+m+1 per dimension (eq. (2.13), read with 2m+2 points), so
+// every stencil of a bin lies in its padded tile: origin b*B - m, edge P = B + WM - 1
+// (WM >= 2m+2 is the compiled stencil width, extra points carry weight zero).
+//
+//  * interpolation: a workgroup stages the padded tile of its bin from the grid into LDS
+//    with coalesced row reads (indices taken mod n, Sec. 2 eq. (2.5)), then each thread
+//    takes one node and sums its (2m+2)^d stencil from LDS as nested tensor-product sums
+//    (the structure the PRE_PSI flag of Table 3.2 exploits);
+//  * spreading: a workgroup accumulates the contributions of its nodes into a padded tile
+//    in LDS (LDS atomics, no global atomics) and writes the tile to its own slot of a
+//    scratch buffer; a fold kernel then writes every grid cell once as the sum, in a fixed
+//    order, of the tile slots that cover it.
+#include "window_common.hpp"
+
+namespace nfft {
+
+namespace {
+
+using namespace window;
+
+// ------------------------------------------------------------------ interpolation
+
+template <typename T, int D, int WM>
+__global__ __launch_bounds__(kBlock) void k_interp(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
+                                                   Cplx<T> *__restrict__ f)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *tile = reinterpret_cast<C *>(smem_raw);
+    const T *psi = static_cast<const T *>(nd.psi);
+    const int W = g.W;
+    const int dW = D * W;
+    const int nchunks = nd.counters[0];
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int bin = nd.chunk_bin[c];
+        const int first = nd.chunk_first[c];
+        const int len = nd.chunk_len[c];
+        int bc[kMaxDim];
+        bin_coords<T, D>(g, bin, bc);
+        stage_tile<T, D>(g, bc, grid, tile);
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int node = first + i;
+            const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
+            int ul[kMaxDim];
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
+            T wl[WM];  // innermost dimension
+#pragma unroll
+            for (int s = 0; s < WM; ++s)
+                wl[s] = s < W ? pw[(D - 1) * W + s] : T(0);
+            T ax = 0, ay = 0;
+            if constexpr (D == 1) {
+                const C *row = tile + ul[0];
+#pragma unroll
+                for (int s = 0; s < WM; ++s) {
+                    C v = row[s];
+                    ax += wl[s] * v.x;
+                    ay += wl[s] * v.y;
+                }
+            } else if constexpr (D == 2) {
+                for (int s0 = 0; s0 < W; ++s0) {
+                    const T w0 = pw[s0];
+                    const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
+                    T rx = 0, ry = 0;
+#pragma unroll
+                    for (int s1 = 0; s1 < WM; ++s1) {
+                        C v = row[s1];
+                        rx += wl[s1] * v.x;
+                        ry += wl[s1] * v.y;
+                    }
+                    ax += w0 * rx;
+                    ay += w0 * ry;
+                }
+            } else {
+                T wmid[WM];
+#pragma unroll
+                for (int s = 0; s < WM; ++s)
+                    wmid[s] = s < W ? pw[W + s] : T(0);
+                const int P1 = g.P[1], P2 = g.P[2];
+                for (int s0 = 0; s0 < W; ++s0) {
+                    const T w0 = pw[s0];
+                    const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
+                    T px = 0, py = 0;
+#pragma unroll
+                    for (int s1 = 0; s1 < WM; ++s1) {
+                        const C *row = plane + s1 * P2;
+                        T rx = 0, ry = 0;
+#pragma unroll
+                        for (int s2 = 0; s2 < WM; ++s2) {
+                            C v = row[s2];
+                            rx += wl[s2] * v.x;
+                            ry += wl[s2] * v.y;
+                        }
+                        px += wmid[s1] * rx;
+                        py += wmid[s1] * ry;
+                    }
+                    ax += w0 * px;
+                    ay += w0 * py;
+                }
+            }
+            f[nd.perm[node]] = C{ax, ay};
+        }
+        __syncthreads();
+    }
+}
+
+#define NFFT_WM_SWITCH(WMV, CALL)                                                                       \
+    switch (WMV) {                                                                                     \
+    case 6: CALL(6); break;                                                                            \
+    case 10: CALL(10); break;                                                                          \
+    case 14: CALL(14); break;                                                                          \
+    case 18: CALL(18); break;                                                                          \
+    case 22: CALL(22); break;                                                                          \
+    case 26: CALL(26); break;                                                                          \
+    default: return hipErrorInvalidValue;                                                              \
+    }
+
+#define NFFT_DT_SWITCH(FN, ...)                                                                        \
+    switch (g.d * 2 + (dbl ? 1 : 0)) {                                                                 \
+    case 2: return FN<float, 1>(__VA_ARGS__);                                                          \
+    case 3: return FN<double, 1>(__VA_ARGS__);                                                         \
+    case 4: return FN<float, 2>(__VA_ARGS__);                                                          \
+    case 5: return FN<double, 2>(__VA_ARGS__);                                                         \
+    case 6: return FN<float, 3>(__VA_ARGS__);                                                          \
+    case 7: return FN<double, 3>(__VA_ARGS__);                                                         \
+    default: return hipErrorInvalidValue;                                                              \
+    }
+
+template <typename T, int D>
+hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *f, int blocks, size_t lds,
+                        hipStream_t s)
+{
+    using C = Cplx<T>;
+#define CALL(W_)                                                                                       \
+    {                                                                                                  \
+        auto kf = k_interp<T, D, W_>;                                                                  \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, g, nd, static_cast<const C *>(grid), \
+                           static_cast<C *>(f));                                                       \
+    }
+    NFFT_WM_SWITCH(g.WM, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+}  // namespace
+
+size_t interp_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8); }
+size_t spread_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8) * (g.d < 3 ? 4 : 1); }
+
+int fold_max_pairs(const Geom &g, int t)
+{
+    // brute force over the grid indices of dimension t (host copy of cover_pairs)
+    int B = 1 << g.lgB[t], n = g.n[t], worst = 0;
+    for (int l = 0; l < n; ++l) {
+        int cnt = 0;
+        for (int k = -1; k <= 1; ++k) {
+            int lu = l + k * n + g.m;
+            for (int b = 0; b < g.nb[t]; ++b) {
+                int o = lu - b * B;
+                if (o >= 0 && o < g.P[t])
+                    ++cnt;
+            }
+        }
+        if (cnt > worst)
+            worst = cnt;
+    }
+    return worst;
+}
+
+hipError_t launch_interp(const Geom &g, const Nodes &nd, bool dbl, const void *grid, void *f, int blocks,
+                         size_t lds, hipStream_t s)
+{
+    NFFT_DT_SWITCH(interp_typed, g, nd, grid, f, blocks, lds, s)
+}
+
+}  // namespace nfft

@@ -1,0 +1,242 @@
+// Node precomputation (the node setting step that Sec. 4.2 times as "precomputation"):
+// per node and dimension, in FP64, y = n_t x_t, u = floor(y) mod n_t and delta = y - floor(y)
+// (the stencil index set of Sec. 2 eq. (2.13) starts at u - m), then a counting sort of
+// the nodes into bins of B_0 x ... x B_{d-1} grid cells and the list of work items
+// (chunks of at most chunk_cap nodes of one bin) the window kernels iterate over.
+#include <math.h>
+
+#include "launch.hpp"
+
+namespace nfft {
+
+namespace {
+
+__global__ void k_node_reset(int32_t *bin_count, int nbins, int32_t *counters)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbins)
+        bin_count[i] = 0;
+    if (i < 2)
+        counters[i] = 0;
+}
+
+// Grid index and offset of coordinate x in a dimension of length n.  Returns false for
+// non-finite input (index 0, offset NaN).  n * x is exact for a power-of-two n, floor is
+// exact, and y - floor(y) is exact, so u and delta are the exact values.  fmod is exact
+// too, so the index is right for any finite x.
+__device__ __forceinline__ bool node_index(double x, int n, int &u, double &delta)
+{
+    double y = (double)n * x;
+    if (!isfinite(y)) {
+        u = 0;
+        delta = __builtin_nan("");
+        return false;
+    }
+    double fl = floor(y);
+    delta = y - fl;
+    double r = fmod(fl, (double)n);
+    if (r < 0.0)
+        r += (double)n;
+    u = (int)r;
+    if (u >= n)  // r == n cannot occur for exact fmod, kept as a guard
+        u -= n;
+    return true;
+}
+
+template <int D> __global__ __launch_bounds__(kBlock) void k_node_key(Geom g, Nodes nd, double *xcopy)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nd.M)
+        return;
+    int bin = 0;
+    bool finite = true;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        double x = nd.x[j * D + t];
+        xcopy[j * D + t] = x;
+        int u;
+        double delta;
+        finite &= node_index(x, g.n[t], u, delta);
+        bin = bin * g.nb[t] + (u >> g.lgB[t]);
+    }
+    if (!finite)
+        atomicOr(&nd.counters[1], 1);
+    nd.key[j] = bin;
+    nd.rank[j] = atomicAdd(&nd.bin_count[bin], 1);
+}
+
+// One workgroup of 1024 threads: exclusive scans of the bin counts (-> bin_start) and of
+// the work items per bin, ceil(count / cap) (-> bin_chunk); counters[0] = total items.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_node_scan(Nodes nd, int nbins)
+{
+    __shared__ int64_t s_a[kScanThreads];
+    __shared__ int64_t s_b[kScanThreads];
+    const int tid = threadIdx.x;
+    const int per = (nbins + kScanThreads - 1) / kScanThreads;
+    const int lo = tid * per;
+    const int hi = min(nbins, lo + per);
+    int64_t sa = 0, sb = 0;
+    for (int i = lo; i < hi; ++i) {
+        int c = nd.bin_count[i];
+        sa += c;
+        sb += (c + nd.chunk_cap - 1) / nd.chunk_cap;
+    }
+    s_a[tid] = sa;
+    s_b[tid] = sb;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 partial sums
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int64_t va = tid >= off ? s_a[tid - off] : 0;
+        int64_t vb = tid >= off ? s_b[tid - off] : 0;
+        __syncthreads();
+        s_a[tid] += va;
+        s_b[tid] += vb;
+        __syncthreads();
+    }
+    int64_t ra = s_a[tid] - sa;  // exclusive prefix of this segment
+    int64_t rb = s_b[tid] - sb;
+    for (int i = lo; i < hi; ++i) {
+        int c = nd.bin_count[i];
+        nd.bin_start[i] = (int32_t)ra;
+        nd.bin_chunk[i] = (int32_t)rb;
+        ra += c;
+        rb += (c + nd.chunk_cap - 1) / nd.chunk_cap;
+    }
+    if (tid == kScanThreads - 1) {
+        nd.bin_start[nbins] = (int32_t)s_a[tid];
+        nd.bin_chunk[nbins] = (int32_t)s_b[tid];
+        nd.counters[0] = (int32_t)s_b[tid];
+    }
+}
+
+template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_node_scatter(Geom g, Nodes nd)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nd.M)
+        return;
+    int bin = nd.key[j];
+    int pos = nd.bin_start[bin] + nd.rank[j];
+    nd.perm[pos] = (int32_t)j;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        int u;
+        double delta;
+        node_index(nd.x[j * D + t], g.n[t], u, delta);
+        nd.u[t][pos] = u;
+        static_cast<T *>(nd.delta[t])[pos] = (T)delta;
+    }
+}
+
+// Window factors of every sorted node (the tensor-product precomputation of Table 3.2,
+// PRE_PSI): psi[node][t][s] = normalised window phi_t(delta_t - (s - m)), s < 2m+2.  One
+// thread per factor, so the writes are coalesced.
+template <typename T> __global__ __launch_bounds__(kBlock) void k_node_psi(Geom g, Nodes nd)
+{
+    const int W = g.W;
+    const int dW = g.d * W;
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nd.M * dW)
+        return;
+    int64_t node = q / dW;
+    int r = (int)(q - node * dW);
+    int t = r / W;
+    int s = r - t * W;
+    T delta = static_cast<const T *>(nd.delta[t])[node];
+    static_cast<T *>(nd.psi)[q] = kb_point<T>(delta, s, W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
+}
+
+// One thread per bin writes the bin's work items.
+__global__ __launch_bounds__(kBlock) void k_node_chunks(Nodes nd, int nbins)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins)
+        return;
+    int count = nd.bin_count[b];
+    int first = nd.bin_start[b];
+    int c0 = nd.bin_chunk[b];
+    for (int i = 0; i * nd.chunk_cap < count; ++i) {
+        nd.chunk_bin[c0 + i] = b;
+        nd.chunk_first[c0 + i] = first + i * nd.chunk_cap;
+        nd.chunk_len[c0 + i] = min(nd.chunk_cap, count - i * nd.chunk_cap);
+    }
+}
+
+__global__ void k_fill_zero(uint32_t *p, int64_t words)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride)
+        p[i] = 0u;
+}
+
+inline int blocks_for(int64_t n, int per = kBlock) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_node_reset(const Geom &g, const Nodes &nd, hipStream_t s)
+{
+    int n = g.nbins > 2 ? g.nbins : 2;
+    hipLaunchKernelGGL(k_node_reset, dim3(blocks_for(n)), dim3(kBlock), 0, s, nd.bin_count, g.nbins,
+                       nd.counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_key(const Geom &g, const Nodes &nd, double *xcopy, hipStream_t s)
+{
+    dim3 grid(blocks_for(nd.M)), block(kBlock);
+    switch (g.d) {
+    case 1: hipLaunchKernelGGL(k_node_key<1>, grid, block, 0, s, g, nd, xcopy); break;
+    case 2: hipLaunchKernelGGL(k_node_key<2>, grid, block, 0, s, g, nd, xcopy); break;
+    case 3: hipLaunchKernelGGL(k_node_key<3>, grid, block, 0, s, g, nd, xcopy); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_node_scan(const Geom &g, const Nodes &nd, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_node_scan, dim3(1), dim3(kScanThreads), 0, s, nd, g.nbins);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_scatter(const Geom &g, const Nodes &nd, bool dbl, hipStream_t s)
+{
+    dim3 grid(blocks_for(nd.M)), block(kBlock);
+    switch (g.d * 2 + (dbl ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_node_scatter<1, float>), grid, block, 0, s, g, nd); break;
+    case 3: hipLaunchKernelGGL((k_node_scatter<1, double>), grid, block, 0, s, g, nd); break;
+    case 4: hipLaunchKernelGGL((k_node_scatter<2, float>), grid, block, 0, s, g, nd); break;
+    case 5: hipLaunchKernelGGL((k_node_scatter<2, double>), grid, block, 0, s, g, nd); break;
+    case 6: hipLaunchKernelGGL((k_node_scatter<3, float>), grid, block, 0, s, g, nd); break;
+    case 7: hipLaunchKernelGGL((k_node_scatter<3, double>), grid, block, 0, s, g, nd); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_node_chunks, dim3(blocks_for(g.nbins)), block, 0, s, nd, g.nbins);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t nf = nd.M * g.d * g.W;
+    if (dbl)
+        hipLaunchKernelGGL(k_node_psi<double>, dim3(blocks_for(nf)), block, 0, s, g, nd);
+    else
+        hipLaunchKernelGGL(k_node_psi<float>, dim3(blocks_for(nf)), block, 0, s, g, nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    int64_t words = (int64_t)(bytes / 4);
+    if (words == 0)
+        return hipSuccess;
+    int blocks = blocks_for(words);
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(kBlock), 0, s, static_cast<uint32_t *>(p), words);
+    return hipGetLastError();
+}
+
+}  // namespace nfft

@@ -1,0 +1,84 @@
+// Host-side launchers of the NFFT kernels (one definition per kernel file).  Every
+// launcher enqueues on `stream` and returns hipGetLastError() of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nfft_device.hpp"
+
+namespace nfft {
+
+// ------------------------------------------------------------------ node precompute
+
+// bin_count[0..nbins) = 0, counters[0..1] = 0.
+hipError_t launch_node_reset(const Geom &g, const Nodes &nd, hipStream_t s);
+// key, rank, bin_count, copy of x; non-finite flag in counters[1].
+hipError_t launch_node_key(const Geom &g, const Nodes &nd, double *xcopy, hipStream_t s);
+// bin_start, bin_chunk (exclusive scans), counters[0] = number of work items.
+hipError_t launch_node_scan(const Geom &g, const Nodes &nd, hipStream_t s);
+// sorted u, delta, perm; work-item lists.
+hipError_t launch_node_scatter(const Geom &g, const Nodes &nd, bool dbl, hipStream_t s);
+
+// ------------------------------------------------------------------ FFT passes
+
+struct FftPass {
+    void *grid;          // complex grid (in place)
+    const void *fin;     // coefficients read by the first forward pass (mode 0)
+    void *fout;          // coefficients written by the last adjoint pass (mode 2)
+    const double *w[kMaxDim];  // deconvolution factors per dimension, centred index
+    const void *tw;      // e^{-2 pi i k / L}, k < L, for the transformed dimension
+    int d, t;            // dimension count, transformed dimension
+    int L;               // n_t
+    int N[kMaxDim], n[kMaxDim];
+    int64_t stride[kMaxDim];  // grid strides (elements)
+    int nl;              // lines per workgroup
+    int pitch;           // LDS elements per line
+    int in_mode;         // 0: coefficients with D, 1: grid, N_t nonzero entries, 2: grid, full line
+    int out_mode;        // 0: full line to grid, 1: N_t entries to grid, 2: N_t entries to coefficients with D^H
+    int sign;            // -1 forward, +1 adjoint
+    int rows;            // 1 when t == d-1 (lines are contiguous rows)
+    int64_t ngroups;     // line groups
+    int nrows;           // rows (t == d-1): prod_{q<d-1} N_q
+    int ncb;             // column blocks (t < d-1): n_{d-1} / nl
+    int vpt;             // points per thread: max(1, nl*L/256)
+};
+hipError_t launch_fft_pass(const FftPass &p, bool dbl, int grid_blocks, hipStream_t s);
+
+// ------------------------------------------------------------------ window kernels
+
+hipError_t launch_interp(const Geom &g, const Nodes &nd, bool dbl, const void *grid, void *f, int blocks,
+                         size_t lds, hipStream_t s);
+hipError_t launch_spread_tiles(const Geom &g, const Nodes &nd, bool dbl, const void *f, void *scratch,
+                               int blocks, size_t lds, hipStream_t s);
+hipError_t launch_fold(const Geom &g, const Nodes &nd, bool dbl, const void *scratch, void *grid,
+                       hipStream_t s);
+hipError_t launch_grad_x(const Geom &g, const Nodes &nd, bool dbl, const void *grid, const void *v,
+                         void *grad, int blocks, size_t lds, hipStream_t s);
+
+// LDS bytes per workgroup of the interpolation / spreading / gradient kernels.
+size_t interp_lds_bytes(const Geom &g, bool dbl);
+size_t spread_lds_bytes(const Geom &g, bool dbl);
+// Largest number of (bin, offset) pairs a grid index can have in one dimension; the
+// fold kernel supports up to kFoldMaxPairs.
+constexpr int kFoldMaxPairs = 24;
+int fold_max_pairs(const Geom &g, int t);
+
+// ------------------------------------------------------------------ direct sums
+
+struct NdftArgs {
+    int d;
+    int N[kMaxDim];
+    int64_t M;
+    int64_t K;  // prod N
+    const double *x;
+    const void *in;
+    void *out;
+};
+hipError_t launch_ndft(const NdftArgs &a, bool dbl, bool adjoint, hipStream_t s);
+
+// ------------------------------------------------------------------ utilities
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace nfft

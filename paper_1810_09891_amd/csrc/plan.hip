@@ -1,0 +1,764 @@
+// Host side of the NFFT library: plan validation and defaults, FP64 tables, workspace
+// layout, launch sequences of Algorithm 2.1 / 2.2, and the exported C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nfft_mi355x.h"
+#include "launch.hpp"
+#include "plan_impl.hpp"
+
+using namespace nfft;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsPreferred = 64 * 1024;  // target LDS per workgroup (occupancy)
+constexpr size_t kLdsMax = 160 * 1024;       // LDS per compute unit on gfx950
+constexpr int kMaxN = 4096;                  // longest FFT line held in one workgroup
+constexpr int kMaxM = 12;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v)
+{
+    int r = 0;
+    while ((int64_t(1) << (r + 1)) <= v)
+        ++r;
+    return r;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan construction
+
+namespace nfft {
+
+static int choose_bins(nfft_plan_s *p)
+{
+    const int d = p->d;
+    const size_t cs = p->dbl ? 16 : 8;
+    int B[kMaxDim] = {1, 1, 1};
+    // starting edges: long tiles in 1-D, 32x32 in 2-D, 8x8x8 in 3-D
+    const int start = d == 1 ? 512 : d == 2 ? 32 : 8;
+    for (int t = 0; t < d; ++t)
+        B[t] = (int)std::min<int64_t>(start, p->n[t]);
+    auto lds_of = [&](const int *b) {
+        size_t v = cs;
+        for (int t = 0; t < d; ++t)
+            v *= (size_t)(b[t] + p->WM - 1);
+        return v;
+    };
+    // Shrink the largest edge (outer dimension first on ties) until the tiles fit: the
+    // spreading kernel keeps four private tiles per workgroup for d <= 2 and one for d = 3;
+    // the interpolation kernel keeps one.
+    const int minB = 4;
+    const size_t ntiles = d < 3 ? 4 : 1;
+    const size_t budget = d < 3 ? kLdsMax : kLdsPreferred;
+    while (ntiles * lds_of(B) > budget) {
+        int best = -1;
+        for (int t = 0; t < d; ++t)
+            if (B[t] > minB && B[t] > 1 && (best < 0 || B[t] > B[best]))
+                best = t;
+        if (best < 0)
+            break;
+        B[best] /= 2;
+    }
+    if (ntiles * lds_of(B) > kLdsMax)
+        return NFFT_ERR_UNSUPPORTED;
+    Geom &g = p->geom;
+    g.Ptot = 1;
+    g.nbins = 1;
+    for (int t = 0; t < kMaxDim; ++t) {
+        if (t < d) {
+            g.lgB[t] = ilog2(B[t]);
+            g.nb[t] = (int)(p->n[t] / B[t]);
+            g.P[t] = B[t] + p->WM - 1;
+        } else {
+            g.lgB[t] = 0;
+            g.nb[t] = 1;
+            g.P[t] = 1;
+        }
+        g.Ptot *= g.P[t];
+        g.nbins *= g.nb[t];
+    }
+    for (int t = 0; t < d; ++t)
+        if (fold_max_pairs(g, t) > kFoldMaxPairs)
+            return NFFT_ERR_UNSUPPORTED;
+    p->lds_window = lds_of(B);
+    return NFFT_OK;
+}
+
+static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_last, FftPass &fp)
+{
+    const int d = p->d;
+    std::memset(&fp, 0, sizeof(fp));
+    fp.d = d;
+    fp.t = t;
+    fp.L = (int)p->n[t];
+    for (int q = 0; q < kMaxDim; ++q) {
+        fp.N[q] = q < d ? (int)p->N[q] : 1;
+        fp.n[q] = q < d ? (int)p->n[q] : 1;
+    }
+    int64_t st = 1;
+    for (int q = d - 1; q >= 0; --q) {
+        fp.stride[q] = st;
+        st *= p->n[q];
+    }
+    fp.sign = forward ? -1 : +1;
+    fp.rows = (t == d - 1) ? 1 : 0;
+    if (forward) {
+        fp.in_mode = first_or_last ? 0 : 1;
+        fp.out_mode = 0;
+    } else {
+        fp.in_mode = 2;
+        fp.out_mode = first_or_last ? 2 : 1;
+    }
+    const int maxPts = p->dbl ? 4096 : 8192;
+    const int L = fp.L;
+    // Aim for at least 512 line groups (two per compute unit) before packing more lines
+    // into a workgroup; column passes keep >= 2 adjacent columns per row segment.
+    const int64_t target = 512;
+    int nl;
+    if (fp.rows) {
+        int64_t nrows = 1;
+        for (int q = 0; q < d - 1; ++q)
+            nrows *= p->N[q];
+        fp.nrows = (int)nrows;
+        nl = 1;
+        while ((int64_t)nl * 2 * L <= maxPts && nl * 2 <= 256 && nrows / (nl * 2) >= target)
+            nl *= 2;
+        fp.ngroups = (nrows + nl - 1) / nl;
+    } else {
+        int64_t outer = 1;
+        for (int q = 0; q < d - 1; ++q) {
+            if (q == t)
+                continue;
+            outer *= (q < t) ? p->N[q] : p->n[q];
+        }
+        const int inner = (int)p->n[d - 1];
+        nl = std::min<int>(inner, std::max(1, maxPts / L));
+        nl = std::min(nl, std::min(256, p->dbl ? 8 : 16));
+        while (nl > 2 && outer * (inner / nl) < target)
+            nl /= 2;
+        fp.ncb = inner / nl;
+        fp.ngroups = outer * fp.ncb;
+    }
+    fp.nl = nl;
+    fp.pitch = fp.rows ? L : L + 1;
+    int pts = nl * L;
+    fp.vpt = std::max(1, pts / 256);
+}
+
+}  // namespace nfft
+
+static int build_tables(nfft_plan_s *p)
+{
+    const double pi = 3.14159265358979323846264338327950288;
+    for (int t = 0; t < p->d; ++t) {
+        const double b = pi * (2.0 - (double)p->N[t] / (double)p->n[t]);
+        p->geom.b[t] = b;
+        p->geom.emb[t] = std::exp(-b * p->m);
+        // deconvolution factor e^{b m} / (n phihat(k)), n phihat(k) = I0(m sqrt(b^2 - (2 pi k/n)^2))
+        p->wtab[t].resize((size_t)p->N[t]);
+        for (int64_t i = 0; i < p->N[t]; ++i) {
+            const double k = (double)(i - p->N[t] / 2);
+            const double w = 2.0 * pi * k / (double)p->n[t];
+            const double arg = (double)p->m * std::sqrt(b * b - w * w);
+            const double i0 = std::cyl_bessel_i(0.0, arg);
+            p->wtab[t][(size_t)i] = std::exp(b * p->m) / i0;
+        }
+        // twiddles e^{-2 pi i k / n}, k < n, from the exact angle of each k
+        p->twd[t].resize((size_t)p->n[t]);
+        p->twf[t].resize((size_t)p->n[t]);
+        for (int64_t k = 0; k < p->n[t]; ++k) {
+            const double a = 2.0 * pi * (double)k / (double)p->n[t];
+            double c = std::cos(a), s = -std::sin(a);
+            p->twd[t][(size_t)k] = double2{c, s};
+            p->twf[t][(size_t)k] = float2{(float)c, (float)s};
+        }
+    }
+    for (int t = p->d; t < kMaxDim; ++t) {
+        p->geom.b[t] = 0.0;
+        p->geom.emb[t] = 1.0;
+    }
+    return NFFT_OK;
+}
+
+static void layout_workspace(nfft_plan_s *p)
+{
+    const size_t cs = p->dbl ? 16 : 8;
+    const size_t rs = p->dbl ? 8 : 4;
+    const int64_t M = p->M;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    int64_t ngrid = 1;
+    for (int t = 0; t < p->d; ++t)
+        ngrid *= p->n[t];
+    p->ngrid = ngrid;
+    for (int t = 0; t < p->d; ++t)
+        p->off_w[t] = take(sizeof(double) * (size_t)p->N[t]);
+    for (int t = 0; t < p->d; ++t)
+        p->off_tw[t] = take(cs * (size_t)p->n[t]);
+    p->off_grid = take(cs * (size_t)ngrid);
+    p->off_grid_adj = (p->flags & NFFT_KEEP_GRID) ? take(cs * (size_t)ngrid) : p->off_grid;
+    for (int t = 0; t < p->d; ++t)
+        p->off_u[t] = take(4 * (size_t)M);
+    for (int t = 0; t < p->d; ++t)
+        p->off_delta[t] = take(rs * (size_t)M);
+    p->off_perm = take(4 * (size_t)M);
+    p->off_key = take(4 * (size_t)M);
+    p->off_rank = take(4 * (size_t)M);
+    p->off_bin_count = take(4 * (size_t)p->geom.nbins);
+    p->off_bin_start = take(4 * (size_t)(p->geom.nbins + 1));
+    p->off_bin_chunk = take(4 * (size_t)(p->geom.nbins + 1));
+    p->off_chunk_bin = take(4 * (size_t)p->max_chunks);
+    p->off_chunk_first = take(4 * (size_t)p->max_chunks);
+    p->off_chunk_len = take(4 * (size_t)p->max_chunks);
+    p->off_counters = take(64);
+    p->off_xcopy = take(sizeof(double) * (size_t)M * p->d);
+    p->off_psi = take(rs * (size_t)M * p->d * (size_t)(2 * p->m + 2));
+    p->off_scratch = take(cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
+    p->ws_bytes = off;
+}
+
+static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
+                       nfft_dtype dtype, uint32_t flags)
+{
+    if (!out || !N || d < 1 || d > kMaxDim || M < 1 || M > (int64_t)0x7fffffff)
+        return NFFT_ERR_ARG;
+    if (dtype != NFFT_C64 && dtype != NFFT_C128)
+        return NFFT_ERR_ARG;
+    if (m == 0)
+        m = 8;
+    if (m < 1)
+        return NFFT_ERR_ARG;
+    int64_t nn[kMaxDim];
+    for (int t = 0; t < d; ++t) {
+        if (N[t] < 2 || (N[t] & 1))
+            return NFFT_ERR_ARG;
+        if (n) {
+            nn[t] = n[t];
+        } else {
+            int e = 0;
+            while ((int64_t(1) << e) < N[t])
+                ++e;
+            nn[t] = int64_t(1) << (e + 1);
+        }
+        if (nn[t] <= N[t] || (nn[t] & 1))
+            return NFFT_ERR_ARG;
+        if (2 * m + 2 > nn[t])
+            return NFFT_ERR_ARG;
+    }
+    for (int t = 0; t < d; ++t)
+        if (!is_pow2(nn[t]) || nn[t] > kMaxN)
+            return NFFT_ERR_UNSUPPORTED;
+    if (m > kMaxM)
+        return NFFT_ERR_UNSUPPORTED;
+
+    nfft_plan_s *p = new (std::nothrow) nfft_plan_s();
+    if (!p)
+        return NFFT_ERR_ARG;
+    p->d = d;
+    p->m = m;
+    p->dtype = dtype;
+    p->dbl = dtype == NFFT_C128;
+    p->flags = flags | NFFT_SORT_NODES;
+    p->M = M;
+    for (int t = 0; t < kMaxDim; ++t) {
+        p->N[t] = t < d ? N[t] : 1;
+        p->n[t] = t < d ? nn[t] : 1;
+    }
+    Geom &g = p->geom;
+    std::memset(&g, 0, sizeof(g));
+    g.d = d;
+    g.m = m;
+    g.W = 2 * m + 2;
+    g.WM = wm_bucket(m);
+    p->WM = g.WM;
+    for (int t = 0; t < kMaxDim; ++t)
+        g.n[t] = (int)p->n[t];
+    int st = choose_bins(p);
+    if (st != NFFT_OK) {
+        delete p;
+        return st;
+    }
+    p->chunk_cap = 1024;
+    p->max_chunks = (int)(g.nbins + (M + p->chunk_cap - 1) / p->chunk_cap);
+    build_tables(p);
+    // FFT passes
+    p->fwd_passes.clear();
+    for (int t = d - 1; t >= 0; --t) {
+        FftPass fp;
+        plan_fft_pass(p, t, true, t == d - 1, fp);
+        p->fwd_passes.push_back(fp);
+    }
+    p->adj_passes.clear();
+    for (int t = 0; t < d; ++t) {
+        FftPass fp;
+        plan_fft_pass(p, t, false, t == d - 1, fp);
+        p->adj_passes.push_back(fp);
+    }
+    layout_workspace(p);
+    *out = p;
+    return NFFT_OK;
+}
+
+// ------------------------------------------------------------------ device views
+
+static Nodes node_view(nfft_plan_s *p)
+{
+    Nodes nd;
+    std::memset(&nd, 0, sizeof(nd));
+    char *ws = static_cast<char *>(p->ws);
+    for (int t = 0; t < p->d; ++t) {
+        nd.u[t] = reinterpret_cast<int32_t *>(ws + p->off_u[t]);
+        nd.delta[t] = ws + p->off_delta[t];
+    }
+    nd.perm = reinterpret_cast<int32_t *>(ws + p->off_perm);
+    nd.key = reinterpret_cast<int32_t *>(ws + p->off_key);
+    nd.rank = reinterpret_cast<int32_t *>(ws + p->off_rank);
+    nd.bin_count = reinterpret_cast<int32_t *>(ws + p->off_bin_count);
+    nd.bin_start = reinterpret_cast<int32_t *>(ws + p->off_bin_start);
+    nd.bin_chunk = reinterpret_cast<int32_t *>(ws + p->off_bin_chunk);
+    nd.chunk_bin = reinterpret_cast<int32_t *>(ws + p->off_chunk_bin);
+    nd.chunk_first = reinterpret_cast<int32_t *>(ws + p->off_chunk_first);
+    nd.chunk_len = reinterpret_cast<int32_t *>(ws + p->off_chunk_len);
+    nd.counters = reinterpret_cast<int32_t *>(ws + p->off_counters);
+    nd.psi = ws + p->off_psi;
+    nd.M = p->M;
+    nd.chunk_cap = p->chunk_cap;
+    nd.max_chunks = p->max_chunks;
+    return nd;
+}
+
+static FftPass bind_pass(nfft_plan_s *p, const FftPass &tmpl, void *grid, const void *fin, void *fout)
+{
+    FftPass fp = tmpl;
+    char *ws = static_cast<char *>(p->ws);
+    fp.grid = grid;
+    fp.fin = fin;
+    fp.fout = fout;
+    for (int t = 0; t < kMaxDim; ++t)
+        fp.w[t] = t < p->d ? reinterpret_cast<const double *>(ws + p->off_w[t]) : nullptr;
+    fp.tw = ws + p->off_tw[tmpl.t];
+    return fp;
+}
+
+// ------------------------------------------------------------------ profiling
+
+static void prof_begin(nfft_plan_s *p, hipStream_t s)
+{
+    if (!p->prof_on)
+        return;
+    hipEvent_t e;
+    if (p->ev_pool.empty()) {
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+    } else {
+        e = p->ev_pool.back();
+        p->ev_pool.pop_back();
+    }
+    (void)hipEventRecord(e, s);
+    p->ev_open = e;
+}
+
+static void prof_end(nfft_plan_s *p, hipStream_t s, const char *name)
+{
+    if (!p->prof_on || !p->ev_open)
+        return;
+    hipEvent_t e;
+    if (p->ev_pool.empty()) {
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+    } else {
+        e = p->ev_pool.back();
+        p->ev_pool.pop_back();
+    }
+    (void)hipEventRecord(e, s);
+    p->ev_pending.push_back({name, p->ev_open, e});
+    p->ev_open = nullptr;
+}
+
+#define LAUNCH(p, s, name, call)                                                                      \
+    do {                                                                                              \
+        prof_begin(p, s);                                                                             \
+        hipError_t e_ = (call);                                                                       \
+        prof_end(p, s, name);                                                                         \
+        if (e_ != hipSuccess) {                                                                       \
+            p->last_hip_error = e_;                                                                   \
+            return NFFT_ERR_HIP;                                                                      \
+        }                                                                                             \
+    } while (0)
+
+// ------------------------------------------------------------------ launch sequences
+
+static int grid_blocks(nfft_plan_s *p)
+{
+    // work items are visited with a grid-stride loop; one workgroup per item up to the bound
+    return std::max(1, std::min(p->max_chunks, 1 << 20));
+}
+
+static int run_forward_grid(nfft_plan_s *p, const void *fhat, void *grid, hipStream_t s)
+{
+    for (size_t i = 0; i < p->fwd_passes.size(); ++i) {
+        FftPass fp = bind_pass(p, p->fwd_passes[i], grid, fhat, nullptr);
+        int blocks = (int)std::min<int64_t>(fp.ngroups, 1 << 20);
+        LAUNCH(p, s, i == 0 ? "fft_fwd_deconv" : "fft_fwd", launch_fft_pass(fp, p->dbl, blocks, s));
+    }
+    return NFFT_OK;
+}
+
+static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_t s)
+{
+    for (size_t i = 0; i < p->adj_passes.size(); ++i) {
+        FftPass fp = bind_pass(p, p->adj_passes[i], grid, nullptr, hhat);
+        int blocks = (int)std::min<int64_t>(fp.ngroups, 1 << 20);
+        LAUNCH(p, s, i + 1 == p->adj_passes.size() ? "fft_adj_deconv" : "fft_adj",
+               launch_fft_pass(fp, p->dbl, blocks, s));
+    }
+    return NFFT_OK;
+}
+
+static int run_interp(nfft_plan_s *p, const void *grid, void *f, hipStream_t s)
+{
+    Nodes nd = node_view(p);
+    LAUNCH(p, s, "interp",
+           launch_interp(p->geom, nd, p->dbl, grid, f, grid_blocks(p), interp_lds_bytes(p->geom, p->dbl), s));
+    return NFFT_OK;
+}
+
+static int run_spread(nfft_plan_s *p, const void *f, void *grid, hipStream_t s)
+{
+    Nodes nd = node_view(p);
+    void *scratch = static_cast<char *>(p->ws) + p->off_scratch;
+    LAUNCH(p, s, "spread_tiles",
+           launch_spread_tiles(p->geom, nd, p->dbl, f, scratch, grid_blocks(p),
+                               spread_lds_bytes(p->geom, p->dbl), s));
+    LAUNCH(p, s, "spread_fold", launch_fold(p->geom, nd, p->dbl, scratch, grid, s));
+    return NFFT_OK;
+}
+
+static int ensure_tables(nfft_plan_s *p, hipStream_t s)
+{
+    if (p->tables_on_device)
+        return NFFT_OK;
+    char *ws = static_cast<char *>(p->ws);
+    for (int t = 0; t < p->d; ++t) {
+        if (hipMemcpyAsync(ws + p->off_w[t], p->wtab[t].data(), sizeof(double) * p->wtab[t].size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return NFFT_ERR_HIP;
+        const void *src = p->dbl ? (const void *)p->twd[t].data() : (const void *)p->twf[t].data();
+        size_t bytes = (p->dbl ? 16 : 8) * (size_t)p->n[t];
+        if (hipMemcpyAsync(ws + p->off_tw[t], src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return NFFT_ERR_HIP;
+    }
+    // the host tables stay alive in the plan; wait so a later destroy cannot race the copy
+    if (hipStreamSynchronize(s) != hipSuccess)
+        return NFFT_ERR_HIP;
+    p->tables_on_device = true;
+    return NFFT_OK;
+}
+
+// ------------------------------------------------------------------ exported ABI
+
+extern "C" {
+
+const char *nfft_status_string(int status)
+{
+    switch (status) {
+    case NFFT_OK: return "ok";
+    case NFFT_ERR_ARG: return "invalid argument";
+    case NFFT_ERR_STATE: return "call out of order";
+    case NFFT_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case NFFT_ERR_HIP: return "HIP call failed";
+    case NFFT_ERR_UNSUPPORTED: return "not supported by this library";
+    default: return "unknown status";
+    }
+}
+
+int nfft_plan_create(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
+                     nfft_dtype dtype, uint32_t flags)
+{
+    if (!out)
+        return NFFT_ERR_ARG;
+    nfft_plan_s *p = nullptr;
+    int st = create_plan(&p, d, N, M, n, m, dtype, flags);
+    if (st == NFFT_OK)
+        *out = p;
+    return st;
+}
+
+int nfft_plan_destroy(nfft_plan p)
+{
+    if (!p)
+        return NFFT_ERR_ARG;
+    for (auto &pe : p->ev_pending) {
+        (void)hipEventDestroy(pe.a);
+        (void)hipEventDestroy(pe.b);
+    }
+    for (auto e : p->ev_pool)
+        (void)hipEventDestroy(e);
+    delete p;
+    return NFFT_OK;
+}
+
+int nfft_plan_get_info(nfft_plan p, nfft_plan_info *info)
+{
+    if (!p || !info)
+        return NFFT_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->d = p->d;
+    info->m = p->m;
+    info->dtype = p->dtype;
+    info->flags = p->flags;
+    info->M = p->M;
+    for (int t = 0; t < kMaxDim; ++t) {
+        info->N[t] = p->N[t];
+        info->n[t] = p->n[t];
+        info->bin[t] = (int64_t)1 << p->geom.lgB[t];
+    }
+    info->nbins = p->geom.nbins;
+    info->chunk_cap = p->chunk_cap;
+    info->max_chunks = p->max_chunks;
+    info->workspace_bytes = p->ws_bytes;
+    info->lds_bytes = p->lds_window;
+    double sc = 1.0;
+    for (int t = 0; t < p->d; ++t)
+        sc /= p->geom.emb[t];
+    info->grid_scale = sc;
+    return NFFT_OK;
+}
+
+int nfft_workspace_bytes(nfft_plan p, size_t *bytes)
+{
+    if (!p || !bytes)
+        return NFFT_ERR_ARG;
+    *bytes = p->ws_bytes;
+    return NFFT_OK;
+}
+
+int nfft_set_workspace(nfft_plan p, void *ws, size_t bytes)
+{
+    if (!p)
+        return NFFT_ERR_ARG;
+    if (!ws || bytes < p->ws_bytes || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return NFFT_ERR_WORKSPACE;
+    p->ws = ws;
+    p->tables_on_device = false;
+    p->nodes_set = false;
+    p->grid_valid = false;
+    return NFFT_OK;
+}
+
+int nfft_set_nodes(nfft_plan p, const double *x, hipStream_t s)
+{
+    if (!p || !x)
+        return NFFT_ERR_ARG;
+    if (!p->ws)
+        return NFFT_ERR_WORKSPACE;
+    int st = ensure_tables(p, s);
+    if (st != NFFT_OK)
+        return st;
+    Nodes nd = node_view(p);
+    nd.x = x;
+    double *xcopy = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->off_xcopy);
+    p->nodes_set = false;
+    p->grid_valid = false;
+    LAUNCH(p, s, "nodes_reset", launch_node_reset(p->geom, nd, s));
+    LAUNCH(p, s, "nodes_key", launch_node_key(p->geom, nd, xcopy, s));
+    LAUNCH(p, s, "nodes_scan", launch_node_scan(p->geom, nd, s));
+    LAUNCH(p, s, "nodes_scatter", launch_node_scatter(p->geom, nd, p->dbl, s));
+    p->nodes_set = true;
+    return NFFT_OK;
+}
+
+static int check_ready(nfft_plan p)
+{
+    if (!p)
+        return NFFT_ERR_ARG;
+    if (!p->ws)
+        return NFFT_ERR_WORKSPACE;
+    if (!p->nodes_set)
+        return NFFT_ERR_STATE;
+    return NFFT_OK;
+}
+
+int nfft_trafo(nfft_plan p, const void *fhat, void *f, hipStream_t s)
+{
+    int st = check_ready(p);
+    if (st != NFFT_OK)
+        return st;
+    if (!fhat || !f)
+        return NFFT_ERR_ARG;
+    void *grid = static_cast<char *>(p->ws) + p->off_grid;
+    if ((st = run_forward_grid(p, fhat, grid, s)) != NFFT_OK)
+        return st;
+    if ((st = run_interp(p, grid, f, s)) != NFFT_OK)
+        return st;
+    p->grid_valid = true;
+    return NFFT_OK;
+}
+
+int nfft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t s)
+{
+    int st = check_ready(p);
+    if (st != NFFT_OK)
+        return st;
+    if (!f || !hhat)
+        return NFFT_ERR_ARG;
+    void *grid = static_cast<char *>(p->ws) + p->off_grid_adj;
+    if ((st = run_spread(p, f, grid, s)) != NFFT_OK)
+        return st;
+    if ((st = run_adjoint_coeffs(p, grid, hhat, s)) != NFFT_OK)
+        return st;
+    if (p->off_grid_adj == p->off_grid)
+        p->grid_valid = false;
+    return NFFT_OK;
+}
+
+int nfft_step_grid(nfft_plan p, const void *fhat, void *g, hipStream_t s)
+{
+    if (!p || !fhat || !g)
+        return NFFT_ERR_ARG;
+    if (!p->ws)
+        return NFFT_ERR_WORKSPACE;
+    int st = ensure_tables(p, s);
+    if (st != NFFT_OK)
+        return st;
+    return run_forward_grid(p, fhat, g, s);
+}
+
+int nfft_step_interp(nfft_plan p, const void *g, void *f, hipStream_t s)
+{
+    int st = check_ready(p);
+    if (st != NFFT_OK)
+        return st;
+    if (!g || !f)
+        return NFFT_ERR_ARG;
+    return run_interp(p, g, f, s);
+}
+
+int nfft_step_spread(nfft_plan p, const void *f, void *g, hipStream_t s)
+{
+    int st = check_ready(p);
+    if (st != NFFT_OK)
+        return st;
+    if (!g || !f)
+        return NFFT_ERR_ARG;
+    return run_spread(p, f, g, s);
+}
+
+int nfft_step_coeffs(nfft_plan p, const void *g, void *hhat, hipStream_t s)
+{
+    if (!p || !g || !hhat)
+        return NFFT_ERR_ARG;
+    if (!p->ws)
+        return NFFT_ERR_WORKSPACE;
+    int st = ensure_tables(p, s);
+    if (st != NFFT_OK)
+        return st;
+    // the passes work in place: transform a copy held in the workspace grid
+    void *grid = static_cast<char *>(p->ws) + p->off_grid_adj;
+    if (hipMemcpyAsync(grid, g, (p->dbl ? 16 : 8) * (size_t)p->ngrid, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return NFFT_ERR_HIP;
+    if (p->off_grid_adj == p->off_grid)
+        p->grid_valid = false;
+    return run_adjoint_coeffs(p, grid, hhat, s);
+}
+
+static int run_ndft(nfft_plan p, const void *in, void *out, bool adjoint, hipStream_t s)
+{
+    int st = check_ready(p);
+    if (st != NFFT_OK)
+        return st;
+    if (!in || !out)
+        return NFFT_ERR_ARG;
+    NdftArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.d = p->d;
+    a.K = 1;
+    for (int t = 0; t < kMaxDim; ++t) {
+        a.N[t] = (int)p->N[t];
+        if (t < p->d)
+            a.K *= p->N[t];
+    }
+    a.M = p->M;
+    a.x = reinterpret_cast<const double *>(static_cast<char *>(p->ws) + p->off_xcopy);
+    a.in = in;
+    a.out = out;
+    LAUNCH(p, s, adjoint ? "ndft_adjoint" : "ndft_trafo", launch_ndft(a, p->dbl, adjoint, s));
+    return NFFT_OK;
+}
+
+int ndft_trafo(nfft_plan p, const void *fhat, void *f, hipStream_t s) { return run_ndft(p, fhat, f, false, s); }
+
+int ndft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t s) { return run_ndft(p, f, hhat, true, s); }
+
+int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t s)
+{
+    int st = check_ready(p);
+    if (st != NFFT_OK)
+        return st;
+    if (!v || !grad_x)
+        return NFFT_ERR_ARG;
+    if (!(p->flags & NFFT_KEEP_GRID) || !p->grid_valid)
+        return NFFT_ERR_STATE;
+    Nodes nd = node_view(p);
+    const void *grid = static_cast<char *>(p->ws) + p->off_grid;
+    LAUNCH(p, s, "grad_x",
+           launch_grad_x(p->geom, nd, p->dbl, grid, v, grad_x, grid_blocks(p), interp_lds_bytes(p->geom, p->dbl),
+                         s));
+    return NFFT_OK;
+}
+
+int nfft_profile_enable(nfft_plan p, int on)
+{
+    if (!p)
+        return NFFT_ERR_ARG;
+    p->prof_on = on != 0;
+    return NFFT_OK;
+}
+
+int nfft_profile_read(nfft_plan p, const char **names, double *total_ms, int64_t *launches, int cap, int *count)
+{
+    if (!p || !count)
+        return NFFT_ERR_ARG;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+    for (auto &pe : p->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            auto &slot = acc[pe.name];
+            slot.first += ms;
+            slot.second += 1;
+        }
+        p->ev_pool.push_back(pe.a);
+        p->ev_pool.push_back(pe.b);
+    }
+    p->ev_pending.clear();
+    int i = 0;
+    for (auto &kv : acc) {
+        if (i < cap) {
+            // names point at the static strings passed to LAUNCH
+            names[i] = p->intern(kv.first);
+            total_ms[i] = kv.second.first;
+            launches[i] = kv.second.second;
+        }
+        ++i;
+    }
+    *count = i;
+    return NFFT_OK;
+}
+
+}  // extern "C"

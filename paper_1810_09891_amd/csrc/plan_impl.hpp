@@ -1,0 +1,60 @@
+// Host-side plan object behind the opaque nfft_plan handle.
+#pragma once
+
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/nfft_mi355x.h"
+#include "launch.hpp"
+
+struct nfft_prof_pair {
+    const char *name;
+    hipEvent_t a, b;
+};
+
+struct nfft_plan_s {
+    int d = 0, m = 0, WM = 0;
+    nfft_dtype dtype = NFFT_C64;
+    bool dbl = false;
+    uint32_t flags = 0;
+    int64_t N[nfft::kMaxDim] = {1, 1, 1};
+    int64_t n[nfft::kMaxDim] = {1, 1, 1};
+    int64_t M = 0;
+    int64_t ngrid = 0;
+    nfft::Geom geom;
+    int chunk_cap = 0;
+    int max_chunks = 0;
+    size_t lds_window = 0;
+
+    // FP64 deconvolution factors (centred index) and twiddles per dimension
+    std::vector<double> wtab[nfft::kMaxDim];
+    std::vector<double2> twd[nfft::kMaxDim];
+    std::vector<float2> twf[nfft::kMaxDim];
+
+    std::vector<nfft::FftPass> fwd_passes, adj_passes;
+
+    // workspace layout (byte offsets)
+    size_t off_w[nfft::kMaxDim] = {0, 0, 0}, off_tw[nfft::kMaxDim] = {0, 0, 0};
+    size_t off_grid = 0, off_grid_adj = 0;
+    size_t off_u[nfft::kMaxDim] = {0, 0, 0}, off_delta[nfft::kMaxDim] = {0, 0, 0};
+    size_t off_perm = 0, off_key = 0, off_rank = 0;
+    size_t off_bin_count = 0, off_bin_start = 0, off_bin_chunk = 0;
+    size_t off_chunk_bin = 0, off_chunk_first = 0, off_chunk_len = 0;
+    size_t off_counters = 0, off_xcopy = 0, off_scratch = 0, off_psi = 0;
+    size_t ws_bytes = 0;
+
+    void *ws = nullptr;
+    bool tables_on_device = false;
+    bool nodes_set = false;
+    bool grid_valid = false;
+    hipError_t last_hip_error = hipSuccess;
+
+    // kernel timing
+    bool prof_on = false;
+    hipEvent_t ev_open = nullptr;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<nfft_prof_pair> ev_pending;
+    std::set<std::string> names;
+    const char *intern(const std::string &s) { return names.insert(s).first->c_str(); }
+};

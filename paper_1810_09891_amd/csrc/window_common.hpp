@@ -1,0 +1,79 @@
+// Helpers shared by the window kernels (interpolation, spreading, gradient).
+#pragma once
+
+#include "launch.hpp"
+
+namespace nfft {
+
+namespace window {
+
+template <typename T, int D> __device__ __forceinline__ void bin_coords(const Geom &g, int bin, int *bc)
+{
+    int r = bin;
+#pragma unroll
+    for (int t = D - 1; t >= 0; --t) {
+        bc[t] = r % g.nb[t];
+        r /= g.nb[t];
+    }
+}
+
+// Stage the padded tile of bin `bc` into LDS (complex, row-major P_0 x ... x P_{d-1}).
+template <typename T, int D>
+__device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
+{
+    int o[kMaxDim];
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        o[t] = (bc[t] << g.lgB[t]) - g.m + g.n[t];  // + n keeps it non-negative
+    if constexpr (D == 1) {
+        for (int i = threadIdx.x; i < g.P[0]; i += kBlock)
+            tile[i] = grid[(o[0] + i) & (g.n[0] - 1)];
+    } else if constexpr (D == 2) {
+        const int P1 = g.P[1];
+        for (int idx = threadIdx.x; idx < g.Ptot; idx += kBlock) {
+            int i0 = idx / P1;
+            int i1 = idx - i0 * P1;
+            int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
+            int c1 = (o[1] + i1) & (g.n[1] - 1);
+            tile[idx] = grid[r0 * g.n[1] + c1];
+        }
+    } else {
+        const int P1 = g.P[1], P2 = g.P[2];
+        const int P12 = P1 * P2;
+        for (int idx = threadIdx.x; idx < g.Ptot; idx += kBlock) {
+            int i0 = idx / P12;
+            int rem = idx - i0 * P12;
+            int i1 = rem / P2;
+            int i2 = rem - i1 * P2;
+            int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
+            int64_t r1 = (o[1] + i1) & (g.n[1] - 1);
+            int c2 = (o[2] + i2) & (g.n[2] - 1);
+            tile[idx] = grid[(r0 * g.n[1] + r1) * g.n[2] + c2];
+        }
+    }
+}
+
+// Window factors of one dimension at all WM stencil points (zero beyond 2m+2).
+template <typename T, int WM>
+__device__ __forceinline__ void window_row(T delta, const Geom &g, int t, T *w)
+{
+    const T m = (T)g.m, b = (T)g.b[t], emb = (T)g.emb[t];
+#pragma unroll
+    for (int s = 0; s < WM; ++s)
+        w[s] = s < g.W ? kb_point<T>(delta, s, g.W, m, b, emb) : T(0);
+}
+
+template <typename T, int WM>
+__device__ __forceinline__ void window_row_d(T delta, const Geom &g, int t, T *w, T *dw)
+{
+    const T m = (T)g.m, b = (T)g.b[t], emb = (T)g.emb[t];
+#pragma unroll
+    for (int s = 0; s < WM; ++s) {
+        w[s] = s < g.W ? kb_point<T>(delta, s, g.W, m, b, emb) : T(0);
+        dw[s] = s < g.W ? kb_point_d<T>(delta, s, g.W, m, b, emb) : T(0);
+    }
+}
+
+}  // namespace window
+
+}  // namespace nfft

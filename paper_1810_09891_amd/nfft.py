@@ -1,0 +1,207 @@
+"""Python front end of the HIP NFFT library (argument marshalling only).
+
+``Plan`` mirrors the plan interface of arXiv:1810.09891 Sec. 3 (Table 3.1, the
+constructors ``Plan(N, M)`` / ``Plan(N, M, n, m, ...)``, ``p.x = ...``,
+``NFFT.trafo(p)``): create a plan, set its nodes (which runs the node
+precomputation), then call ``trafo`` / ``adjoint`` as often as needed.  PyTorch only
+provides device memory (tensors, including the plan's workspace) and the stream the
+library enqueues on.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import NFFT_C64, NFFT_C128, NFFT_KEEP_GRID, NFFT_SORT_NODES, check
+
+_CDTYPE = {torch.complex64: NFFT_C64, torch.complex128: NFFT_C128}
+_RDTYPE = {torch.complex64: torch.float32, torch.complex128: torch.float64}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def default_n(N):
+    """n_t = 2^(ceil(log2 N_t) + 1), the default FFT length (Sec. 2 and Sec. 3.1)."""
+    out = []
+    for v in N:
+        e = 0
+        while (1 << e) < v:
+            e += 1
+        out.append(1 << (e + 1))
+    return tuple(out)
+
+
+class Plan:
+    """NFFT plan for d-variate transforms with bandwidths N, M nodes, FFT lengths n and
+    window size m, computing in complex64 or complex128.
+
+    Arrays: coefficients have shape N (centred: index i holds k = i - N/2), nodes are
+    (M, d) float64, values are (M,).  All tensors live on ``device``.
+    """
+
+    def __init__(self, N, M, n=None, m=8, dtype=torch.complex64, flags=0, device="cuda"):
+        lib = _lib.load()
+        self.N = tuple(int(v) for v in N)
+        self.d = len(self.N)
+        self.M = int(M)
+        self.dtype = dtype
+        if dtype not in _CDTYPE:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.device = torch.device(device)
+        Na = (ctypes.c_int64 * self.d)(*self.N)
+        na = None if n is None else (ctypes.c_int64 * self.d)(*[int(v) for v in n])
+        h = ctypes.c_void_p()
+        check(lib.nfft_plan_create(ctypes.byref(h), self.d, Na, self.M, na, int(m), _CDTYPE[dtype], int(flags)),
+              "nfft_plan_create")
+        self._h = h
+        self._lib = lib
+        info = _lib.PlanInfo()
+        check(lib.nfft_plan_get_info(h, ctypes.byref(info)), "nfft_plan_get_info")
+        self.info = info
+        self.n = tuple(int(info.n[t]) for t in range(self.d))
+        self.m = int(info.m)
+        self.workspace = None
+        self._x = None
+        self.nodes_set = False
+
+    # ---------------------------------------------------------------- set-up
+
+    def allocate(self):
+        """Allocate and attach the workspace (a uint8 tensor on the plan's device)."""
+        nbytes = ctypes.c_size_t()
+        check(self._lib.nfft_workspace_bytes(self._h, ctypes.byref(nbytes)), "nfft_workspace_bytes")
+        ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        check(self._lib.nfft_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr() + off), nbytes.value),
+              "nfft_set_workspace")
+        return self
+
+    @property
+    def workspace_bytes(self):
+        return int(self.info.workspace_bytes)
+
+    def set_nodes(self, x):
+        """Set the nodes x, an (M, d) float64 tensor, and run the node precomputation."""
+        if self.workspace is None:
+            self.allocate()
+        x = self._as(x, torch.float64, (self.M, self.d), "x")
+        check(self._lib.nfft_set_nodes(self._h, _ptr(x), _stream(self.device)), "nfft_set_nodes")
+        self._x = x  # kept alive until the enqueued work has read it
+        self.nodes_set = True
+        return self
+
+    # ---------------------------------------------------------------- transforms
+
+    def _as(self, t, dtype, shape, name):
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=dtype)
+        if tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape)
+        return t.contiguous()
+
+    def _out(self, out, shape, dtype=None):
+        dtype = self.dtype if dtype is None else dtype
+        if out is None:
+            return torch.empty(shape, dtype=dtype, device=self.device)
+        if out.dtype != dtype or tuple(out.shape) != tuple(shape) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (dtype, shape))
+        return out
+
+    def trafo(self, fhat, out=None):
+        """NFFT (Algorithm 2.1): f_j ~ sum_k fhat_k exp(-2 pi i k.x_j)."""
+        fhat = self._as(fhat, self.dtype, self.N, "fhat")
+        f = self._out(out, (self.M,))
+        check(self._lib.nfft_trafo(self._h, _ptr(fhat), _ptr(f), _stream(self.device)), "nfft_trafo")
+        return f
+
+    def adjoint(self, f, out=None):
+        """Adjoint NFFT (Algorithm 2.2): hhat_k ~ sum_j f_j exp(+2 pi i k.x_j)."""
+        f = self._as(f, self.dtype, (self.M,), "f")
+        h = self._out(out, self.N)
+        check(self._lib.nfft_adjoint(self._h, _ptr(f), _ptr(h), _stream(self.device)), "nfft_adjoint")
+        return h
+
+    def ndft_trafo(self, fhat, out=None):
+        """Direct sum eq. (1.2) on the device."""
+        fhat = self._as(fhat, self.dtype, self.N, "fhat")
+        f = self._out(out, (self.M,))
+        check(self._lib.ndft_trafo(self._h, _ptr(fhat), _ptr(f), _stream(self.device)), "ndft_trafo")
+        return f
+
+    def ndft_adjoint(self, f, out=None):
+        """Direct sum eq. (1.3) on the device."""
+        f = self._as(f, self.dtype, (self.M,), "f")
+        h = self._out(out, self.N)
+        check(self._lib.ndft_adjoint(self._h, _ptr(f), _ptr(h), _stream(self.device)), "ndft_adjoint")
+        return h
+
+    def grad_x(self, v, out=None):
+        """Re(conj(v_j) d f_j / d x_{j,t}) for the last trafo (needs NFFT_KEEP_GRID)."""
+        v = self._as(v, self.dtype, (self.M,), "v")
+        g = self._out(out, (self.M, self.d), _RDTYPE[self.dtype])
+        check(self._lib.nfft_grad_x(self._h, _ptr(v), _ptr(g), _stream(self.device)), "nfft_grad_x")
+        return g
+
+    # ---------------------------------------------------------------- single steps
+
+    def step_grid(self, fhat, out=None):
+        fhat = self._as(fhat, self.dtype, self.N, "fhat")
+        g = self._out(out, self.n)
+        if self.workspace is None:
+            self.allocate()
+        check(self._lib.nfft_step_grid(self._h, _ptr(fhat), _ptr(g), _stream(self.device)), "nfft_step_grid")
+        return g
+
+    def step_interp(self, g, out=None):
+        g = self._as(g, self.dtype, self.n, "g")
+        f = self._out(out, (self.M,))
+        check(self._lib.nfft_step_interp(self._h, _ptr(g), _ptr(f), _stream(self.device)), "nfft_step_interp")
+        return f
+
+    def step_spread(self, f, out=None):
+        f = self._as(f, self.dtype, (self.M,), "f")
+        g = self._out(out, self.n)
+        check(self._lib.nfft_step_spread(self._h, _ptr(f), _ptr(g), _stream(self.device)), "nfft_step_spread")
+        return g
+
+    def step_coeffs(self, g, out=None):
+        g = self._as(g, self.dtype, self.n, "g")
+        h = self._out(out, self.N)
+        if self.workspace is None:
+            self.allocate()
+        check(self._lib.nfft_step_coeffs(self._h, _ptr(g), _ptr(h), _stream(self.device)), "nfft_step_coeffs")
+        return h
+
+    # ---------------------------------------------------------------- timing
+
+    def profile(self, on=True):
+        check(self._lib.nfft_profile_enable(self._h, 1 if on else 0), "nfft_profile_enable")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last read (synchronise first)."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        count = ctypes.c_int()
+        check(self._lib.nfft_profile_read(self._h, names, ms, cnt, cap, ctypes.byref(count)), "nfft_profile_read")
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(cap, count.value))}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nfft_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point,
+and validates arguments and call order before enqueueing anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1810_09891_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nfft_mi355x.h")
+
+OK, ARG, STATE, WS, HIP, UNSUP = 0, -1, -2, -3, -4, -5
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|char)\s*\**\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def create(lib, N, M, n=None, m=8, dtype=1, flags=0):
+    h = ctypes.c_void_p()
+    d = len(N)
+    Na = (ctypes.c_int64 * d)(*N)
+    na = None if n is None else (ctypes.c_int64 * d)(*n)
+    st = lib.nfft_plan_create(ctypes.byref(h), d, Na, M, na, m, dtype, flags)
+    return st, h
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    assert set(names) == set(_lib.ABI_SYMBOLS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for st in (OK, ARG, STATE, WS, HIP, UNSUP):
+        assert lib.nfft_status_string(st)
+
+
+@pytest.mark.parametrize(
+    "N,M,n,m,expect",
+    [
+        ((8,), 10, None, 8, ARG),  # default n = 16 < 2m+2 = 18
+        ((8,), 10, (16,), 7, OK),
+        ((7,), 10, None, 2, ARG),  # odd N (Sec. 3.1: N in 2N^d)
+        ((8,), 0, None, 2, ARG),  # M < 1
+        ((8,), 10, (8,), 2, ARG),  # n <= N
+        ((8,), 10, (11,), 2, ARG),  # odd n
+        ((8,), 10, (12,), 2, UNSUP),  # even, > N, not a power of two
+        ((8,), 10, (8192,), 2, UNSUP),  # longer than one workgroup line
+        ((8,), 10, (64,), 13, UNSUP),  # m beyond the compiled stencils
+        ((8,), 10, (16,), -1, ARG),
+        ((8, 8, 8, 8), 10, None, 2, ARG),  # d > 3
+        ((512, 512), 262144, None, 8, OK),
+        ((128, 128, 128), 2097152, None, 6, OK),
+    ],
+)
+def test_plan_validation(lib, N, M, n, m, expect):
+    st, h = create(lib, N, M, n, m)
+    assert st == expect
+    if st == OK:
+        assert lib.nfft_plan_destroy(h) == OK
+
+
+def test_defaults(lib):
+    st, h = create(lib, (100, 64), 5, None, 0)
+    assert st == OK
+    info = _lib.PlanInfo()
+    assert lib.nfft_plan_get_info(h, ctypes.byref(info)) == OK
+    assert info.m == 8  # m = 0 selects the default 8 (Sec. 3.1)
+    assert (info.n[0], info.n[1]) == (256, 128)  # 2^(ceil(log2 N)+1)
+    lib.nfft_plan_destroy(h)
+
+
+def test_call_order_and_workspace(lib):
+    st, h = create(lib, (16, 16), 100, None, 4)
+    assert st == OK
+    nbytes = ctypes.c_size_t()
+    assert lib.nfft_workspace_bytes(h, ctypes.byref(nbytes)) == OK
+    assert nbytes.value > 0
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced on the host
+    # no workspace yet
+    assert lib.nfft_set_nodes(h, fake, None) == WS
+    assert lib.nfft_trafo(h, fake, fake, None) == WS
+    # workspace too small / misaligned
+    assert lib.nfft_set_workspace(h, fake, nbytes.value - 1) == WS
+    assert lib.nfft_set_workspace(h, ctypes.c_void_p((1 << 20) + 8), nbytes.value) == WS
+    assert lib.nfft_set_workspace(h, None, nbytes.value) == WS
+    assert lib.nfft_set_workspace(h, fake, nbytes.value) == OK
+    # nodes not set yet
+    assert lib.nfft_trafo(h, fake, fake, None) == STATE
+    assert lib.nfft_adjoint(h, fake, fake, None) == STATE
+    assert lib.ndft_trafo(h, fake, fake, None) == STATE
+    assert lib.nfft_step_interp(h, fake, fake, None) == STATE
+    assert lib.nfft_step_spread(h, fake, fake, None) == STATE
+    assert lib.nfft_grad_x(h, fake, fake, None) == STATE
+    # null arguments
+    assert lib.nfft_set_nodes(h, None, None) == ARG
+    assert lib.nfft_workspace_bytes(None, ctypes.byref(nbytes)) == ARG
+    assert lib.nfft_plan_destroy(h) == OK
+
+
+def test_null_plan_arguments(lib):
+    fake = ctypes.c_void_p(1 << 20)
+    for fn in ("nfft_trafo", "nfft_adjoint", "ndft_trafo", "ndft_adjoint", "nfft_grad_x"):
+        assert getattr(lib, fn)(None, fake, fake, None) == ARG, fn
+    st = lib.nfft_plan_create(None, 1, (ctypes.c_int64 * 1)(8), 4, None, 2, 1, 0)
+    assert st == ARG
+    assert lib.nfft_plan_create(ctypes.byref(ctypes.c_void_p()), 1, (ctypes.c_int64 * 1)(8), 4, None, 2, 3, 0) == ARG
+
+
+def test_workspace_sizes_scale(lib):
+    """Workspace grows with M and with the grid; complex128 needs more than complex64."""
+    sizes = {}
+    for dt in (1, 2):
+        for M in (1000, 100000):
+            st, h = create(lib, (64, 64), M, None, 4, dt)
+            nb = ctypes.c_size_t()
+            lib.nfft_workspace_bytes(h, ctypes.byref(nb))
+            sizes[(dt, M)] = nb.value
+            lib.nfft_plan_destroy(h)
+    assert sizes[(1, 100000)] > sizes[(1, 1000)]
+    assert sizes[(2, 1000)] > sizes[(1, 1000)]

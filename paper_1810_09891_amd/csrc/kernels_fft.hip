@@ -80,13 +80,17 @@ template <typename C, int SIGN, int R> __device__ __forceinline__ void dftR(C *v
         dft8v<C, SIGN>(v);
 }
 
+// LDS position of line element i: one padding element after every 32, so the strided
+// accesses of the early Stockham stages (stride R, R^2, ...) spread over the banks.
+__device__ __forceinline__ int skew(int i) { return i + (i >> 5); }
+
 // One radix-R Stockham stage over nl lines of length L held in LDS (pitch elements per
 // line).  Ns = product of the radices of the earlier stages.  Job (line, j), j < L/R,
 // reads x[j + r L/R], multiplies input r by w^{(j mod Ns) r / (Ns R)} with
 // w = e^{SIGN 2 pi i}, transforms, and writes y[(j / Ns) Ns R + (j mod Ns) + r Ns].
 template <typename T, int VPT, int SIGN, int R>
 __device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, int pitch, int lgNs,
-                                          const Cplx<T> *tw)
+                                          const Cplx<T> *tw /* in LDS */)
 {
     using C = Cplx<T>;
     constexpr int J = VPT >= R ? VPT / R : 1;
@@ -104,10 +108,10 @@ __device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, 
         if (b < jobs) {
             int line = b >> lgJobs;
             int j = b & ((1 << lgJobs) - 1);
-            const C *src = lds + line * pitch + j;
+            const C *src = lds + line * pitch;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                v[q][r] = src[r << lgJobs];
+                v[q][r] = src[skew(j + (r << lgJobs))];
             int jm = j & (Ns - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -117,16 +121,19 @@ __device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, 
                 v[q][r] = cmul(v[q][r], w);
             }
             dftR<C, SIGN, R>(v[q]);
-            base[q] = line * pitch + ((j >> lgNs) << (lgNs + lgR)) + jm;
+            base[q] = ((j >> lgNs) << (lgNs + lgR)) + jm;  // position in the line
+            base[q] |= line << 24;                            // line index in the high bits
         }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < J; ++q) {
         if (base[q] >= 0) {
+            C *dst = lds + (base[q] >> 24) * pitch;
+            const int pos = base[q] & 0xffffff;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                lds[base[q] + r * Ns] = v[q][r];
+                dst[skew(pos + r * Ns)] = v[q][r];
         }
     }
     __syncthreads();
@@ -195,10 +202,15 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
     __shared__ int64_t s_gbase[kMaxLines];
     __shared__ int s_cbase[kMaxLines];
     __shared__ double s_fac[kMaxLines];
-    C *lds = reinterpret_cast<C *>(smem_raw);
-    C *grid = static_cast<C *>(p.grid);
-    const C *tw = static_cast<const C *>(p.tw);
     const int L = p.L, nl = p.nl, pitch = p.pitch;
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    C *tw = lds + nl * pitch;  // twiddle table staged once per workgroup
+    C *grid = static_cast<C *>(p.grid);
+    {
+        const C *twg = static_cast<const C *>(p.tw);
+        for (int i = threadIdx.x; i < L; i += kBlock)
+            tw[i] = twg[i];
+    }
     const int lgL = 31 - __clz(L);
     const int lgnl = 31 - __clz(nl);
     const int total = nl * L;
@@ -209,7 +221,7 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
     const C *fin = static_cast<const C *>(p.fin);
     C *fout = static_cast<C *>(p.fout);
 
-    for (int g = blockIdx.x; g < (int)p.ngroups; g += gridDim.x) {
+    for (int g = xcd_local_id(blockIdx.x, gridDim.x); g < (int)p.ngroups; g += gridDim.x) {
         if (threadIdx.x < nl)
             line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
         __syncthreads();
@@ -240,7 +252,7 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
                     val = grid[gb + i * st];
                 }
             }
-            lds[c * pitch + i] = val;
+            lds[c * pitch + skew(i)] = val;
         }
         __syncthreads();
 
@@ -269,7 +281,7 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
             const int64_t gb = s_gbase[c];
             if (gb < 0)
                 continue;
-            C val = lds[c * pitch + i];
+            C val = lds[c * pitch + skew(i)];
             if (p.out_mode == 0) {
                 grid[gb + i * st] = val;
             } else {
@@ -290,7 +302,7 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
 
 template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int blocks, hipStream_t s)
 {
-    size_t lds = (size_t)p.nl * p.pitch * sizeof(Cplx<T>);
+    size_t lds = ((size_t)p.nl * p.pitch + p.L) * sizeof(Cplx<T>);
     dim3 grid(blocks), block(kBlock);
 #define NFFT_FFT_CALL(V)                                                                               \
     {                                                                                                  \

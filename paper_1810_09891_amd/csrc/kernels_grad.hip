@@ -19,7 +19,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *tile = reinterpret_cast<C *>(smem_raw);
     const int nchunks = nd.counters[0];
-    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // work items are mapped over the first min(grid, items) workgroups, XCD by XCD
+    const int nwg = min((int)gridDim.x, nchunks);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
         const int bin = nd.chunk_bin[c];
         const int first = nd.chunk_first[c];
         const int len = nd.chunk_len[c];
@@ -117,27 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
     }
 }
 
-#define NFFT_WM_SWITCH(WMV, CALL)                                                                       \
-    switch (WMV) {                                                                                     \
-    case 6: CALL(6); break;                                                                            \
-    case 10: CALL(10); break;                                                                          \
-    case 14: CALL(14); break;                                                                          \
-    case 18: CALL(18); break;                                                                          \
-    case 22: CALL(22); break;                                                                          \
-    case 26: CALL(26); break;                                                                          \
-    default: return hipErrorInvalidValue;                                                              \
-    }
 
-#define NFFT_DT_SWITCH(FN, ...)                                                                        \
-    switch (g.d * 2 + (dbl ? 1 : 0)) {                                                                 \
-    case 2: return FN<float, 1>(__VA_ARGS__);                                                          \
-    case 3: return FN<double, 1>(__VA_ARGS__);                                                         \
-    case 4: return FN<float, 2>(__VA_ARGS__);                                                          \
-    case 5: return FN<double, 2>(__VA_ARGS__);                                                         \
-    case 6: return FN<float, 3>(__VA_ARGS__);                                                          \
-    case 7: return FN<double, 3>(__VA_ARGS__);                                                         \
-    default: return hipErrorInvalidValue;                                                              \
-    }
 
 template <typename T, int D>
 hipError_t grad_typed(const Geom &g, const Nodes &nd, const void *grid, const void *v, void *grad, int blocks,

@@ -26,7 +26,7 @@ using namespace window;
 // ------------------------------------------------------------------ interpolation
 
 template <typename T, int D, int WM>
-__global__ __launch_bounds__(kBlock) void k_interp(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
+__global__ __launch_bounds__(kBlock) void k_interp_nodes(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
                                                    Cplx<T> *__restrict__ f)
 {
     using C = Cplx<T>;
@@ -36,7 +36,11 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geom g, Nodes nd, const Cplx<
     const int W = g.W;
     const int dW = D * W;
     const int nchunks = nd.counters[0];
-    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // work items are mapped over the first min(grid, items) workgroups, XCD by XCD
+    const int nwg = min((int)gridDim.x, nchunks);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
         const int bin = nd.chunk_bin[c];
         const int first = nd.chunk_first[c];
         const int len = nd.chunk_len[c];
@@ -44,7 +48,15 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geom g, Nodes nd, const Cplx<
         bin_coords<T, D>(g, bin, bc);
         stage_tile<T, D>(g, bc, grid, tile);
         __syncthreads();
-        for (int i = threadIdx.x; i < len; i += kBlock) {
+        // Thread t takes segment 4 (t mod 64) + t / 64 of the item's nodes (K per segment):
+        // the nodes are ordered by the bank residue of their tile position, so the 64 lanes
+        // of a wave start on different LDS banks.
+        const int K = (len + kBlock - 1) / kBlock;
+        const int seg = 4 * (threadIdx.x & 63) + (threadIdx.x >> 6);
+        for (int k = 0; k < K; ++k) {
+            const int i = seg * K + k;
+            if (i >= len)
+                continue;
             const int node = first + i;
             const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
             int ul[kMaxDim];
@@ -65,18 +77,24 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geom g, Nodes nd, const Cplx<
                     ay += wl[s] * v.y;
                 }
             } else if constexpr (D == 2) {
-                for (int s0 = 0; s0 < W; ++s0) {
-                    const T w0 = pw[s0];
-                    const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
-                    T rx = 0, ry = 0;
+                T w0r[WM];
 #pragma unroll
-                    for (int s1 = 0; s1 < WM; ++s1) {
-                        C v = row[s1];
-                        rx += wl[s1] * v.x;
-                        ry += wl[s1] * v.y;
+                for (int s = 0; s < WM; ++s)
+                    w0r[s] = s < W ? pw[s] : T(0);
+#pragma unroll
+                for (int s0 = 0; s0 < WM; ++s0) {
+                    if (s0 < W) {
+                        const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
+                        T rx = 0, ry = 0;
+#pragma unroll
+                        for (int s1 = 0; s1 < WM; ++s1) {
+                            C v = row[s1];
+                            rx += wl[s1] * v.x;
+                            ry += wl[s1] * v.y;
+                        }
+                        ax += w0r[s0] * rx;
+                        ay += w0r[s0] * ry;
                     }
-                    ax += w0 * rx;
-                    ay += w0 * ry;
                 }
             } else {
                 T wmid[WM];
@@ -111,27 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geom g, Nodes nd, const Cplx<
     }
 }
 
-#define NFFT_WM_SWITCH(WMV, CALL)                                                                       \
-    switch (WMV) {                                                                                     \
-    case 6: CALL(6); break;                                                                            \
-    case 10: CALL(10); break;                                                                          \
-    case 14: CALL(14); break;                                                                          \
-    case 18: CALL(18); break;                                                                          \
-    case 22: CALL(22); break;                                                                          \
-    case 26: CALL(26); break;                                                                          \
-    default: return hipErrorInvalidValue;                                                              \
-    }
-
-#define NFFT_DT_SWITCH(FN, ...)                                                                        \
-    switch (g.d * 2 + (dbl ? 1 : 0)) {                                                                 \
-    case 2: return FN<float, 1>(__VA_ARGS__);                                                          \
-    case 3: return FN<double, 1>(__VA_ARGS__);                                                         \
-    case 4: return FN<float, 2>(__VA_ARGS__);                                                          \
-    case 5: return FN<double, 2>(__VA_ARGS__);                                                         \
-    case 6: return FN<float, 3>(__VA_ARGS__);                                                          \
-    case 7: return FN<double, 3>(__VA_ARGS__);                                                         \
-    default: return hipErrorInvalidValue;                                                              \
-    }
+template <typename T, int D, int WM> constexpr auto pick_interp() { return k_interp_nodes<T, D, WM>; }
 
 template <typename T, int D>
 hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *f, int blocks, size_t lds,
@@ -140,7 +138,7 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
     using C = Cplx<T>;
 #define CALL(W_)                                                                                       \
     {                                                                                                  \
-        auto kf = k_interp<T, D, W_>;                                                                  \
+        auto kf = pick_interp<T, D, W_>();                                                                  \
         (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, g, nd, static_cast<const C *>(grid), \
                            static_cast<C *>(f));                                                       \

@@ -162,6 +162,109 @@ __global__ __launch_bounds__(kBlock) void k_node_chunks(Nodes nd, int nbins)
     }
 }
 
+// Order the nodes of every work item by (r, cell, caller index) with r the residue mod 32
+// of the cell's position in the padded tile, so that the window kernels -- which give
+// thread t the nodes of segment 4 (t mod 64) + t / 64 of this order -- access 32
+// different LDS bank pairs per wave.  The caller index makes the order unique.  Also
+// flags the item safe for plain read-add-write spreading by one thread per node: two
+// lanes of a wave then look at positions at least 4K apart (K = ceil(len / 256)), and
+// nodes of one cell are contiguous, so they never meet if no cell holds more than 4K
+// nodes of the item.
+constexpr int kSortMax = 1024;  // chunk_cap is at most this
+template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_sort(Geom g, Nodes nd)
+{
+    __shared__ unsigned long long keys[kSortMax];
+    __shared__ int maxrun;
+    const int nchunks = nd.counters[0];
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int first = nd.chunk_first[c];
+        const int len = nd.chunk_len[c];
+        int npow = 1;
+        while (npow < len)
+            npow <<= 1;
+        for (int i = threadIdx.x; i < npow; i += kBlock) {
+            unsigned long long key = ~0ull;
+            if (i < len) {
+                const int node = first + i;
+                int pos = 0, cell = 0;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    const int ul = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
+                    pos = pos * g.P[t] + ul;
+                    cell = (cell << g.lgB[t]) | ul;
+                }
+                const unsigned long long r = (unsigned)pos & 31u;
+                key = (r << 58) | ((unsigned long long)cell << 41) | ((unsigned long long)nd.perm[node] << 10) |
+                      (unsigned long long)i;
+            }
+            keys[i] = key;
+        }
+        if (threadIdx.x == 0)
+            maxrun = 1;
+        __syncthreads();
+        // bitonic sort of npow keys
+        for (int k = 2; k <= npow; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < npow; i += kBlock) {
+                    const int ij = i ^ j;
+                    if (ij > i) {
+                        const unsigned long long a = keys[i], b = keys[ij];
+                        const bool up = (i & k) == 0;
+                        if ((a > b) == up) {
+                            keys[i] = b;
+                            keys[ij] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // gather the node data in the new order (read all, then write)
+        int u_new[kSortMax / kBlock][D];
+        T d_new[kSortMax / kBlock][D];
+        int p_new[kSortMax / kBlock];
+#pragma unroll
+        for (int q = 0; q < kSortMax / kBlock; ++q) {
+            const int i = threadIdx.x + q * kBlock;
+            if (i < len) {
+                const int src = first + (int)(keys[i] & 1023ull);
+                p_new[q] = nd.perm[src];
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    u_new[q][t] = nd.u[t][src];
+                    d_new[q][t] = static_cast<const T *>(nd.delta[t])[src];
+                }
+                // length of the run of equal cells ending here
+                const unsigned long long cell_mask = ((1ull << 17) - 1) << 41;
+                const int cap = 4 * ((len + kBlock - 1) / kBlock) + 1;  // only "more than 4K" matters
+                int run = 1;
+                while (run < cap && i - run >= 0 && ((keys[i - run] ^ keys[i]) & cell_mask) == 0 &&
+                       ((keys[i - run] ^ keys[i]) >> 58) == 0)
+                    ++run;
+                atomicMax(&maxrun, run);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSortMax / kBlock; ++q) {
+            const int i = threadIdx.x + q * kBlock;
+            if (i < len) {
+                nd.perm[first + i] = p_new[q];
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    nd.u[t][first + i] = u_new[q][t];
+                    static_cast<T *>(nd.delta[t])[first + i] = d_new[q][t];
+                }
+            }
+        }
+        if (threadIdx.x == 0) {
+            const int K = (len + kBlock - 1) / kBlock;
+            nd.chunk_safe[c] = maxrun <= 4 * K ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_fill_zero(uint32_t *p, int64_t words)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,6 +322,21 @@ hipError_t launch_node_scatter(const Geom &g, const Nodes &nd, bool dbl, hipStre
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    {
+        const int sort_blocks = nd.max_chunks < 4096 ? nd.max_chunks : 4096;
+        switch (g.d * 2 + (dbl ? 1 : 0)) {
+        case 2: hipLaunchKernelGGL((k_chunk_sort<1, float>), dim3(sort_blocks), block, 0, s, g, nd); break;
+        case 3: hipLaunchKernelGGL((k_chunk_sort<1, double>), dim3(sort_blocks), block, 0, s, g, nd); break;
+        case 4: hipLaunchKernelGGL((k_chunk_sort<2, float>), dim3(sort_blocks), block, 0, s, g, nd); break;
+        case 5: hipLaunchKernelGGL((k_chunk_sort<2, double>), dim3(sort_blocks), block, 0, s, g, nd); break;
+        case 6: hipLaunchKernelGGL((k_chunk_sort<3, float>), dim3(sort_blocks), block, 0, s, g, nd); break;
+        case 7: hipLaunchKernelGGL((k_chunk_sort<3, double>), dim3(sort_blocks), block, 0, s, g, nd); break;
+        default: return hipErrorInvalidValue;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     const int64_t nf = nd.M * g.d * g.W;
     if (dbl)
         hipLaunchKernelGGL(k_node_psi<double>, dim3(blocks_for(nf)), block, 0, s, g, nd);

@@ -23,8 +23,23 @@ using namespace window;
 //    barrier separates consecutive nodes.
 
 constexpr int kWaves = kBlock / 64;
+constexpr int kBatch = 16;  // nodes whose data a wave loads at once
 
 template <typename T> __device__ __forceinline__ T lane_shfl(T v, int src) { return __shfl(v, src, 64); }
+
+// Value of lane k (k wave-uniform) in every lane.
+__device__ __forceinline__ int bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ float bcast(float v, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double bcast(double v, int k)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 template <typename T, int D, int WM>
 __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const Cplx<T> *__restrict__ f,
@@ -38,48 +53,103 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
     const int lane = threadIdx.x & 63;
     const int W = g.W;
     const int dW = D * W;
-    const int R = 64 / W;  // stencil rows per pass
-    const int r = lane / W;
-    const int sc = lane - r * W;  // stencil column of this lane
-    const bool lane_ok = r < R;
+    // lane layout over the stencil, fixed by the compiled width WM: R rows of WM columns
+    constexpr int R = 64 / WM;
+    constexpr int NPASS = (WM + R - 1) / R;
+    const int r = lane / WM;
+    const int sc = lane - r * WM;  // stencil column of this lane
+    const bool lane_ok = r < R && sc < W;
     const int nchunks = nd.counters[0];
-    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // work items are mapped over the first min(grid, items) workgroups, XCD by XCD
+    const int nwg = min((int)gridDim.x, nchunks);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
         const int first = nd.chunk_first[c];
         const int len = nd.chunk_len[c];
         if constexpr (D < 3) {
             C *sub = tiles + wave * g.Ptot;
             for (int i = lane; i < g.Ptot; i += 64)
                 sub[i] = C{T(0), T(0)};
-            for (int i = wave; i < len; i += kWaves) {
-                const int node = first + i;
-                const C fv = f[nd.perm[node]];
-                const T wv = lane < dW ? psi[(int64_t)node * dW + lane] : T(0);
-                if constexpr (D == 1) {
-                    const int ul0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
-                    if (lane < W) {
-                        C v = sub[ul0 + lane];
-                        v.x += fv.x * wv;
-                        v.y += fv.y * wv;
-                        sub[ul0 + lane] = v;
-                    }
-                } else {
-                    const int ul0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
-                    const int ul1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
-                    const T w1 = lane_shfl(wv, W + sc);
-                    const T ax = fv.x * w1, ay = fv.y * w1;
-                    const int base = ul0 * g.P[1] + ul1 + sc;
-                    for (int s0b = 0; s0b < W; s0b += R) {
-                        const int s0 = s0b + r;
-                        const T w0 = lane_shfl(wv, s0 < W ? s0 : W - 1);
-                        if (lane_ok && s0 < W) {
-                            const int idx = base + s0 * g.P[1];
-                            C v = sub[idx];
-                            v.x += ax * w0;
-                            v.y += ay * w0;
-                            sub[idx] = v;
+            // this wave's contiguous share of the work item, in batches of kBatch nodes whose
+            // data is loaded one batch ahead (one node per lane; window factor l in lane l)
+            const int lo = first + (len * wave) / kWaves;
+            const int hi = first + (len * (wave + 1)) / kWaves;
+            T fx = 0, fy = 0, wv[kBatch];
+            int u0 = 0, u1 = 0;
+            auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, int &lu1, T *lwv) {
+                const int nb = min(kBatch, hi - b0);
+                lfx = lfy = T(0);
+                lu0 = lu1 = 0;
+                if (lane < nb) {
+                    const C fv = f[nd.perm[b0 + lane]];
+                    lfx = fv.x;
+                    lfy = fv.y;
+                    lu0 = nd.u[0][b0 + lane] & ((1 << g.lgB[0]) - 1);
+                    if (D == 2)
+                        lu1 = nd.u[1][b0 + lane] & ((1 << g.lgB[1]) - 1);
+                }
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k)
+                    lwv[k] = (k < nb && lane < dW) ? psi[(int64_t)(b0 + k) * dW + lane] : T(0);
+            };
+            if (lo < hi)
+                load_batch(lo, fx, fy, u0, u1, wv);
+            for (int b0 = lo; b0 < hi; b0 += kBatch) {
+                const int nb = min(kBatch, hi - b0);
+                T nfx = 0, nfy = 0, nwv[kBatch];
+                int nu0 = 0, nu1 = 0;
+                if (b0 + kBatch < hi)
+                    load_batch(b0 + kBatch, nfx, nfy, nu0, nu1, nwv);
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    if (k >= nb)
+                        break;
+                    const T fxk = bcast(fx, k), fyk = bcast(fy, k);
+                    const int ul0 = bcast(u0, k);
+                    if constexpr (D == 1) {
+                        if (lane < W) {
+                            C v = sub[ul0 + lane];
+                            v.x += fxk * wv[k];
+                            v.y += fyk * wv[k];
+                            sub[ul0 + lane] = v;
+                        }
+                    } else {
+                        const int ul1 = bcast(u1, k);
+                        const T w1 = lane_shfl(wv[k], W + (sc < W ? sc : 0));
+                        const T ax = fxk * w1, ay = fyk * w1;
+                        const int base = ul0 * g.P[1] + ul1 + sc;
+                        T w0[NPASS];
+                        C v[NPASS];
+#pragma unroll
+                        for (int q = 0; q < NPASS; ++q) {
+                            const int s0 = q * R + r;
+                            w0[q] = lane_shfl(wv[k], s0 < W ? s0 : 0);
+                        }
+#pragma unroll
+                        for (int q = 0; q < NPASS; ++q) {
+                            const int s0 = q * R + r;
+                            if (lane_ok && s0 < W)
+                                v[q] = sub[base + s0 * g.P[1]];
+                        }
+#pragma unroll
+                        for (int q = 0; q < NPASS; ++q) {
+                            const int s0 = q * R + r;
+                            if (lane_ok && s0 < W) {
+                                v[q].x += ax * w0[q];
+                                v[q].y += ay * w0[q];
+                                sub[base + s0 * g.P[1]] = v[q];
+                            }
                         }
                     }
                 }
+                fx = nfx;
+                fy = nfy;
+                u0 = nu0;
+                u1 = nu1;
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k)
+                    wv[k] = nwv[k];
             }
             __syncthreads();
             C *slot = scratch + (int64_t)c * g.Ptot;
@@ -108,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
                 const int ul0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
                 const int ul1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
                 const int ul2 = nd.u[2][node] & ((1 << g.lgB[2]) - 1);
-                const int slot2 = 2 * W + sc;  // factor of dimension 2 at this lane's column
+                const int slot2 = 2 * W + (sc < W ? sc : 0);  // factor of dimension 2 at this lane's column
                 const T w2a = lane_shfl(wv0, slot2 < 64 ? slot2 : 0);
                 const T w2b = lane_shfl(wv1, slot2 >= 64 ? slot2 - 64 : 0);
                 const T w2 = slot2 < 64 ? w2a : w2b;
@@ -119,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
                     const int pbase = (ul0 + s0) * P1 + ul1;
                     for (int s1b = 0; s1b < W; s1b += R) {
                         const int s1 = s1b + r;
-                        const T w1 = lane_shfl(wv0, W + (s1 < W ? s1 : W - 1));
+                        const T w1 = lane_shfl(wv0, W + (s1 < W ? s1 : 0));
                         if (lane_ok && s1 < W) {
                             const int idx = (pbase + s1) * P2 + ul2 + sc;
                             C v = tiles[idx];
@@ -139,27 +209,25 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
     }
 }
 
-// (bin, offset) pairs of one dimension covering grid index l: bin b covers the unwrapped
-// indices b*B - m .. b*B - m + P - 1; l is covered through l + k*n for k = -1, 0, 1.
-__device__ __forceinline__ int cover_pairs(int l, int n, int B, int lgB, int nb, int m, int P, int *bins,
-                                           int *offs)
+// Fold: grid cell l receives, from every work item of every bin b whose padded tile covers
+// it, the tile entry at offset o = l + k n + m - b B (k = -1, 0, 1 accounts for the
+// periodic wrap; 0 <= o < P).  Bins are visited in increasing order per dimension and
+// work items in order, so every cell is a sum in a fixed order.
+struct Cover {
+    int lo, hi;  // bins lo..hi (inclusive) cover unwrapped index lu
+    int lu;
+};
+
+__device__ __forceinline__ Cover cover_range(int l, int k, int n, int lgB, int nb, int m, int P)
 {
-    int cnt = 0;
-    for (int k = -1; k <= 1; ++k) {
-        int lu = l + k * n + m;  // unwrapped index relative to origin shift
-        // need 0 <= lu - b*B < P  ->  (lu - P + 1)/B <= b <= lu/B
-        int hi = lu >= 0 ? (lu >> lgB) : -1;
-        int lo_num = lu - P + 1;
-        int lo = lo_num <= 0 ? 0 : ((lo_num + B - 1) >> lgB);
-        if (hi > nb - 1)
-            hi = nb - 1;
-        for (int b = lo; b <= hi && cnt < kFoldMaxPairs; ++b) {
-            bins[cnt] = b;
-            offs[cnt] = lu - b * B;
-            ++cnt;
-        }
-    }
-    return cnt;
+    Cover cv;
+    cv.lu = l + k * n + m;
+    cv.hi = cv.lu >= 0 ? (cv.lu >> lgB) : -1;
+    const int lo_num = cv.lu - P + 1;
+    cv.lo = lo_num <= 0 ? 0 : ((lo_num + (1 << lgB) - 1) >> lgB);
+    if (cv.hi > nb - 1)
+        cv.hi = nb - 1;
+    return cv;
 }
 
 template <typename T, int D>
@@ -171,80 +239,56 @@ __global__ __launch_bounds__(kBlock) void k_fold(Geom g, Nodes nd, const Cplx<T>
 #pragma unroll
     for (int t = 0; t < D; ++t)
         total *= g.n[t];
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total)
         return;
-    int l[kMaxDim];
+    int l[kMaxDim] = {0, 0, 0};
     {
-        int64_t r = q;
+        int64_t rq = q;
 #pragma unroll
         for (int t = D - 1; t >= 0; --t) {
-            l[t] = (int)(r & (g.n[t] - 1));
-            r >>= (31 - __clz(g.n[t]));
+            l[t] = (int)(rq & (g.n[t] - 1));
+            rq >>= (31 - __clz(g.n[t]));
         }
     }
-    int bins[kMaxDim][kFoldMaxPairs], offs[kMaxDim][kFoldMaxPairs], cnt[kMaxDim];
-#pragma unroll
-    for (int t = 0; t < D; ++t)
-        cnt[t] = cover_pairs(l[t], g.n[t], 1 << g.lgB[t], g.lgB[t], g.nb[t], g.m, g.P[t], bins[t], offs[t]);
     T ax = 0, ay = 0;
-    if constexpr (D == 1) {
-        for (int a = 0; a < cnt[0]; ++a) {
-            int bin = bins[0][a];
-            for (int c = nd.bin_chunk[bin]; c < nd.bin_chunk[bin + 1]; ++c) {
-                C v = scratch[(int64_t)c * g.Ptot + offs[0][a]];
-                ax += v.x;
-                ay += v.y;
-            }
+    auto add_bin = [&](int bin, int off) {
+        const int c1 = nd.bin_chunk[bin + 1];
+        for (int c = nd.bin_chunk[bin]; c < c1; ++c) {
+            const C v = scratch[(int64_t)c * g.Ptot + off];
+            ax += v.x;
+            ay += v.y;
         }
-    } else if constexpr (D == 2) {
-        for (int a = 0; a < cnt[0]; ++a)
-            for (int e = 0; e < cnt[1]; ++e) {
-                int bin = bins[0][a] * g.nb[1] + bins[1][e];
-                int off = offs[0][a] * g.P[1] + offs[1][e];
-                for (int c = nd.bin_chunk[bin]; c < nd.bin_chunk[bin + 1]; ++c) {
-                    C v = scratch[(int64_t)c * g.Ptot + off];
-                    ax += v.x;
-                    ay += v.y;
-                }
-            }
-    } else {
-        for (int a = 0; a < cnt[0]; ++a)
-            for (int e = 0; e < cnt[1]; ++e)
-                for (int h = 0; h < cnt[2]; ++h) {
-                    int bin = (bins[0][a] * g.nb[1] + bins[1][e]) * g.nb[2] + bins[2][h];
-                    int off = (offs[0][a] * g.P[1] + offs[1][e]) * g.P[2] + offs[2][h];
-                    for (int c = nd.bin_chunk[bin]; c < nd.bin_chunk[bin + 1]; ++c) {
-                        C v = scratch[(int64_t)c * g.Ptot + off];
-                        ax += v.x;
-                        ay += v.y;
+    };
+    for (int k0 = -1; k0 <= 1; ++k0) {
+        const Cover c0 = cover_range(l[0], k0, g.n[0], g.lgB[0], g.nb[0], g.m, g.P[0]);
+        for (int b0 = c0.lo; b0 <= c0.hi; ++b0) {
+            const int o0 = c0.lu - (b0 << g.lgB[0]);
+            if constexpr (D == 1) {
+                add_bin(b0, o0);
+            } else {
+                for (int k1 = -1; k1 <= 1; ++k1) {
+                    const Cover c1 = cover_range(l[1], k1, g.n[1], g.lgB[1], g.nb[1], g.m, g.P[1]);
+                    for (int b1 = c1.lo; b1 <= c1.hi; ++b1) {
+                        const int o1 = c1.lu - (b1 << g.lgB[1]);
+                        if constexpr (D == 2) {
+                            add_bin(b0 * g.nb[1] + b1, o0 * g.P[1] + o1);
+                        } else {
+                            for (int k2 = -1; k2 <= 1; ++k2) {
+                                const Cover c2 = cover_range(l[2], k2, g.n[2], g.lgB[2], g.nb[2], g.m, g.P[2]);
+                                for (int b2 = c2.lo; b2 <= c2.hi; ++b2) {
+                                    const int o2 = c2.lu - (b2 << g.lgB[2]);
+                                    add_bin((b0 * g.nb[1] + b1) * g.nb[2] + b2, (o0 * g.P[1] + o1) * g.P[2] + o2);
+                                }
+                            }
+                        }
                     }
                 }
+            }
+        }
     }
     grid[q] = C{ax, ay};
 }
-
-#define NFFT_WM_SWITCH(WMV, CALL)                                                                       \
-    switch (WMV) {                                                                                     \
-    case 6: CALL(6); break;                                                                            \
-    case 10: CALL(10); break;                                                                          \
-    case 14: CALL(14); break;                                                                          \
-    case 18: CALL(18); break;                                                                          \
-    case 22: CALL(22); break;                                                                          \
-    case 26: CALL(26); break;                                                                          \
-    default: return hipErrorInvalidValue;                                                              \
-    }
-
-#define NFFT_DT_SWITCH(FN, ...)                                                                        \
-    switch (g.d * 2 + (dbl ? 1 : 0)) {                                                                 \
-    case 2: return FN<float, 1>(__VA_ARGS__);                                                          \
-    case 3: return FN<double, 1>(__VA_ARGS__);                                                         \
-    case 4: return FN<float, 2>(__VA_ARGS__);                                                          \
-    case 5: return FN<double, 2>(__VA_ARGS__);                                                         \
-    case 6: return FN<float, 3>(__VA_ARGS__);                                                          \
-    case 7: return FN<double, 3>(__VA_ARGS__);                                                         \
-    default: return hipErrorInvalidValue;                                                              \
-    }
 
 template <typename T, int D>
 hipError_t spread_typed(const Geom &g, const Nodes &nd, const void *f, void *scratch, int blocks, size_t lds,

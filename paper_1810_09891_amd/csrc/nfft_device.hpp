@@ -34,6 +34,21 @@ template <typename C, typename T> __host__ __device__ __forceinline__ C cscale(C
     return C{a.x * s, a.y * s};
 }
 
+// ------------------------------------------------------------------ launch mapping
+
+// The dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD has
+// its own L2.  This bijection of [0, G) gives XCD x (blocks b with b mod 8 = x) one
+// contiguous range of logical work items, so neighbouring items -- which share cache
+// lines of the grid -- run behind the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local_id(int b, int G)
+{
+    const int x = b % kXcds;
+    const int q = G / kXcds, r = G % kXcds;
+    const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return start + b / kXcds;
+}
+
 // ------------------------------------------------------------------ window
 
 // Stencil width bucket: kernels are compiled for WM = 6, 10, ..., 26 points per
@@ -173,6 +188,7 @@ struct Nodes {
     int32_t *chunk_bin;    // [max_chunks]
     int32_t *chunk_first;  // [max_chunks] first sorted node
     int32_t *chunk_len;    // [max_chunks]
+    int32_t *chunk_safe;   // [max_chunks] 1: no cell holds more than 4 ceil(len/256) nodes
     int32_t *counters;     // [0] = number of work items, [1] = non-finite node flag
     void *psi;             // window factors per sorted node: [M][d][W] (float or double)
     const double *x;       // caller node array (only used while setting nodes)

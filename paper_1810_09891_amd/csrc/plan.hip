@@ -152,7 +152,8 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
         fp.ngroups = outer * fp.ncb;
     }
     fp.nl = nl;
-    fp.pitch = fp.rows ? L : L + 1;
+    // line pitch in LDS: L elements plus one skew element per 32 (and one more for columns)
+    fp.pitch = L + (L >> 5) + (fp.rows ? 0 : 1);
     int pts = nl * L;
     fp.vpt = std::max(1, pts / 256);
 }
@@ -226,6 +227,7 @@ static void layout_workspace(nfft_plan_s *p)
     p->off_chunk_bin = take(4 * (size_t)p->max_chunks);
     p->off_chunk_first = take(4 * (size_t)p->max_chunks);
     p->off_chunk_len = take(4 * (size_t)p->max_chunks);
+    p->off_chunk_safe = take(4 * (size_t)p->max_chunks);
     p->off_counters = take(64);
     p->off_xcopy = take(sizeof(double) * (size_t)M * p->d);
     p->off_psi = take(rs * (size_t)M * p->d * (size_t)(2 * p->m + 2));
@@ -335,6 +337,7 @@ static Nodes node_view(nfft_plan_s *p)
     nd.chunk_bin = reinterpret_cast<int32_t *>(ws + p->off_chunk_bin);
     nd.chunk_first = reinterpret_cast<int32_t *>(ws + p->off_chunk_first);
     nd.chunk_len = reinterpret_cast<int32_t *>(ws + p->off_chunk_len);
+    nd.chunk_safe = reinterpret_cast<int32_t *>(ws + p->off_chunk_safe);
     nd.counters = reinterpret_cast<int32_t *>(ws + p->off_counters);
     nd.psi = ws + p->off_psi;
     nd.M = p->M;

@@ -77,3 +77,26 @@ __device__ __forceinline__ void window_row_d(T delta, const Geom &g, int t, T *w
 }  // namespace window
 
 }  // namespace nfft
+
+// Dispatch over the compiled stencil widths and over (precision, dimension).
+#define NFFT_WM_SWITCH(WMV, CALL)                                                                       \
+    switch (WMV) {                                                                                     \
+    case 6: CALL(6); break;                                                                            \
+    case 10: CALL(10); break;                                                                          \
+    case 14: CALL(14); break;                                                                          \
+    case 18: CALL(18); break;                                                                          \
+    case 22: CALL(22); break;                                                                          \
+    case 26: CALL(26); break;                                                                          \
+    default: return hipErrorInvalidValue;                                                              \
+    }
+
+#define NFFT_DT_SWITCH(FN, ...)                                                                        \
+    switch (g.d * 2 + (dbl ? 1 : 0)) {                                                                 \
+    case 2: return FN<float, 1>(__VA_ARGS__);                                                          \
+    case 3: return FN<double, 1>(__VA_ARGS__);                                                         \
+    case 4: return FN<float, 2>(__VA_ARGS__);                                                          \
+    case 5: return FN<double, 2>(__VA_ARGS__);                                                         \
+    case 6: return FN<float, 3>(__VA_ARGS__);                                                          \
+    case 7: return FN<double, 3>(__VA_ARGS__);                                                         \
+    default: return hipErrorInvalidValue;                                                              \
+    }

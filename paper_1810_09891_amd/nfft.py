@@ -66,9 +66,12 @@ class Plan:
         self.info = info
         self.n = tuple(int(info.n[t]) for t in range(self.d))
         self.m = int(info.m)
+        self.flags = int(info.flags)
         self.workspace = None
         self._x = None
         self.nodes_set = False
+        self.nodes_version = None
+        self.generation = 0  # counts calls that rewrite the plan's forward grid
 
     # ---------------------------------------------------------------- set-up
 
@@ -95,6 +98,8 @@ class Plan:
         check(self._lib.nfft_set_nodes(self._h, _ptr(x), _stream(self.device)), "nfft_set_nodes")
         self._x = x  # kept alive until the enqueued work has read it
         self.nodes_set = True
+        self.nodes_version = x._version
+        self.generation += 1
         return self
 
     # ---------------------------------------------------------------- transforms
@@ -120,6 +125,7 @@ class Plan:
         fhat = self._as(fhat, self.dtype, self.N, "fhat")
         f = self._out(out, (self.M,))
         check(self._lib.nfft_trafo(self._h, _ptr(fhat), _ptr(f), _stream(self.device)), "nfft_trafo")
+        self.generation += 1
         return f
 
     def adjoint(self, f, out=None):

@@ -196,19 +196,56 @@ int nfft_profile_read(nfft_plan p, const char **names, double *total_ms, int64_t
 
 /* ---------------------------------------------------------------- batches */
 
-/* A batch runs many independent plans (each with its own nodes, set through
- * nfft_set_nodes on its own workspace) with one persistent launch per step kind.
- *   plans      [host] `count` plans, all NFFT_C64 or all NFFT_C128, each with a
- *              workspace attached.
- *   tune_cache [host] path of a text file caching autotuned launch parameters, or NULL.
- * nfft_batch_workspace_bytes / nfft_batch_set_workspace attach the batch's own small
- * device table.  nfft_batch_trafo / nfft_batch_adjoint take host arrays of `count`
- * device pointers.  nfft_batch_autotune times candidate launch shapes on `stream`,
- * synchronising it, and records the fastest (in the cache file when one is given). */
+/* A batch runs many independent plans, each with its own nodes (set through
+ * nfft_set_nodes on its own workspace), with one launch per step kind instead of one per
+ * plan and step.  Sec. 3 measures FFT plans once and keeps the result (FFTW's MEASURE
+ * flag and wisdom); the batch autotuner does the same for its launch shapes.
+ *
+ * nfft_batch_create
+ *   plans      [host] `count` >= 1 distinct plans, all NFFT_C64 or all NFFT_C128, each
+ *              with its workspace attached; the workspaces must stay attached as they are
+ *              (a later nfft_set_workspace on a member makes batch calls fail with
+ *              NFFT_ERR_STATE).  The batch does not own the plans: destroy it first.
+ *   tune_cache [host] path of a text file of tuned launch parameters, or NULL.  Read by
+ *              nfft_batch_set_workspace, rewritten by nfft_batch_autotune.
+ *   Plans are grouped by dimension, compiled stencil width and precision, and each group
+ *   is cut into launch groups of at most 64 plans, largest M first.  Host-only call.
+ * nfft_batch_workspace_bytes / nfft_batch_set_workspace attach the batch's own device
+ *   memory (256-byte aligned; per-plan descriptor tables and work-queue counters), copy
+ *   the descriptors to it and synchronise the device.
+ * nfft_batch_trafo / nfft_batch_adjoint take host arrays of `count` device pointers, in
+ *   the order of `plans`, shaped as for nfft_trafo / nfft_adjoint of each plan; every
+ *   plan needs its nodes set.  Enqueued on `stream`; results equal the per-plan calls.
+ *   A batch is used by one stream at a time.
+ * nfft_batch_autotune times every candidate launch shape of each step kind on `stream`
+ *   (with zero stand-in inputs in device memory it allocates and frees), keeps the
+ *   fastest, synchronises `stream` and, with a cache file, rewrites the file.  Returns
+ *   NFFT_ERR_ARG when the cache file cannot be written.
+ * nfft_batch_get_params / nfft_batch_set_params read or set the NFFT_BATCH_NPARAMS launch
+ *   parameters of launch group `group` (0 <= group < info.groups):
+ *     [0] pack_fwd, [2] pack_adj   lines per FFT workgroup as a multiple (1, 2, 4, ...) of
+ *                                  the plan's own packing (capped per plan);
+ *     [1] k_fwd, [3] k_adj, [4] k_interp, [5] k_spread, [6] k_fold
+ *                                  grid of k x (compute units) workgroups, 0 for one
+ *                                  workgroup per work item;
+ *     [7] reserved (0).
+ *   plan_count (may be NULL) receives the number of plans of the launch group. */
+#define NFFT_BATCH_NPARAMS 8
+
+typedef struct {
+    int count;              /* plans */
+    int groups;             /* launch groups */
+    int tuned;              /* 1 when every launch group has tuned (or cached) parameters */
+    size_t workspace_bytes; /* device bytes of the batch */
+} nfft_batch_info;
+
 int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const char *tune_cache);
+int nfft_batch_get_info(nfft_batch b, nfft_batch_info *info);
 int nfft_batch_workspace_bytes(nfft_batch b, size_t *bytes);
 int nfft_batch_set_workspace(nfft_batch b, void *ws, size_t bytes);
 int nfft_batch_autotune(nfft_batch b, hipStream_t stream);
+int nfft_batch_get_params(nfft_batch b, int group, int *params, int *plan_count);
+int nfft_batch_set_params(nfft_batch b, int group, const int *params);
 int nfft_batch_trafo(nfft_batch b, const void *const *fhat, void *const *f, hipStream_t stream);
 int nfft_batch_adjoint(nfft_batch b, const void *const *f, void *const *hhat, hipStream_t stream);
 int nfft_batch_destroy(nfft_batch b);

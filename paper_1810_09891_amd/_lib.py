@@ -29,8 +29,8 @@ ABI_SYMBOLS = [
     "nfft_set_workspace", "nfft_set_nodes", "nfft_trafo", "nfft_adjoint", "ndft_trafo",
     "ndft_adjoint", "nfft_grad_x", "nfft_step_grid", "nfft_step_interp", "nfft_step_spread",
     "nfft_step_coeffs", "nfft_profile_enable", "nfft_profile_read", "nfft_batch_create",
-    "nfft_batch_workspace_bytes", "nfft_batch_set_workspace", "nfft_batch_autotune",
-    "nfft_batch_trafo", "nfft_batch_adjoint", "nfft_batch_destroy", "nfft_status_string",
+    "nfft_batch_get_info", "nfft_batch_workspace_bytes", "nfft_batch_set_workspace",
+    "nfft_batch_autotune", "nfft_batch_get_params", "nfft_batch_set_params", "nfft_batch_trafo", "nfft_batch_adjoint", "nfft_batch_destroy", "nfft_status_string",
 ]
 
 
@@ -58,6 +58,18 @@ class PlanInfo(ctypes.Structure):
         ("grid_scale", ctypes.c_double),
     ]
 
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int),
+        ("groups", ctypes.c_int),
+        ("tuned", ctypes.c_int),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+NFFT_BATCH_NPARAMS = 8
+BATCH_PARAM_NAMES = ("pack_fwd", "k_fwd", "pack_adj", "k_adj", "k_interp", "k_spread", "k_fold", "reserved")
 
 _lib = None
 
@@ -96,6 +108,9 @@ def load():
         "nfft_profile_read": [P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(I64), I, ctypes.POINTER(I)],
         "nfft_batch_create": [ctypes.POINTER(P), I, ctypes.POINTER(P), ctypes.c_char_p],
+        "nfft_batch_get_info": [P, ctypes.POINTER(BatchInfo)],
+        "nfft_batch_get_params": [P, I, ctypes.POINTER(I), ctypes.POINTER(I)],
+        "nfft_batch_set_params": [P, I, ctypes.POINTER(I)],
         "nfft_batch_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
         "nfft_batch_set_workspace": [P, P, ctypes.c_size_t],
         "nfft_batch_autotune": [P, P],

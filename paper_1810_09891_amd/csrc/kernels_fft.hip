@@ -14,7 +14,7 @@
 //  * adjoint passes run t = 0, 1, ..., d-1 and keep only the N_t entries with k in I_N;
 //    the last pass applies the deconvolution of Algorithm 2.2 step 3 and writes the
 //    centred coefficient array.
-#include "launch.hpp"
+#include "batch_desc.hpp"
 
 namespace nfft {
 
@@ -195,22 +195,21 @@ __device__ __forceinline__ void line_info(const FftPass &p, int g, int c, int64_
 
 constexpr int kMaxLines = 256;
 
-template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass p)
+// One line group g of a pass: load (with the deconvolution when in_mode == 0), transform
+// in LDS, store (with the deconvolution when out_mode == 2).
+template <typename T, int VPT, int SIGN>
+__device__ __forceinline__ void fft_group(const FftPass &p, int g, Cplx<T> *lds, int64_t *s_gbase, int *s_cbase,
+                                          double *s_fac)
 {
     using C = Cplx<T>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int64_t s_gbase[kMaxLines];
-    __shared__ int s_cbase[kMaxLines];
-    __shared__ double s_fac[kMaxLines];
     const int L = p.L, nl = p.nl, pitch = p.pitch;
-    C *lds = reinterpret_cast<C *>(smem_raw);
-    C *tw = lds + nl * pitch;  // twiddle table staged once per workgroup
-    C *grid = static_cast<C *>(p.grid);
+    C *tw = lds + nl * pitch;  // twiddle table of this pass
     {
         const C *twg = static_cast<const C *>(p.tw);
         for (int i = threadIdx.x; i < L; i += kBlock)
             tw[i] = twg[i];
     }
+    C *grid = static_cast<C *>(p.grid);
     const int lgL = 31 - __clz(L);
     const int lgnl = 31 - __clz(nl);
     const int total = nl * L;
@@ -220,83 +219,124 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
     const double *wt = p.w[t];
     const C *fin = static_cast<const C *>(p.fin);
     C *fout = static_cast<C *>(p.fout);
-
-    for (int g = xcd_local_id(blockIdx.x, gridDim.x); g < (int)p.ngroups; g += gridDim.x) {
-        if (threadIdx.x < nl)
-            line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
-        __syncthreads();
-        // ---------------- load
-        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-            int c, i;
-            if (p.rows) {
-                c = idx >> lgL;
-                i = idx & (L - 1);
-            } else {
-                c = idx & (nl - 1);
-                i = idx >> lgnl;
-            }
-            const int64_t gb = s_gbase[c];
-            C val = C{T(0), T(0)};
-            if (gb >= 0) {
-                if (p.in_mode == 0) {
-                    int pc = pos_to_coef(i, Nt, L);
-                    if (pc >= 0) {
-                        C a = fin[s_cbase[c] + pc];
-                        double f = s_fac[c] * wt[pc];
-                        val = C{(T)((double)a.x * f), (T)((double)a.y * f)};
-                    }
-                } else if (p.in_mode == 1) {
-                    if (pos_to_coef(i, Nt, L) >= 0)
-                        val = grid[gb + i * st];
-                } else {
-                    val = grid[gb + i * st];
+    if (threadIdx.x < nl)
+        line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
+    __syncthreads();
+    // ---------------- load
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        int c, i;
+        if (p.rows) {
+            c = idx >> lgL;
+            i = idx & (L - 1);
+        } else {
+            c = idx & (nl - 1);
+            i = idx >> lgnl;
+        }
+        const int64_t gb = s_gbase[c];
+        C val = C{T(0), T(0)};
+        if (gb >= 0) {
+            if (p.in_mode == 0) {
+                int pc = pos_to_coef(i, Nt, L);
+                if (pc >= 0) {
+                    C a = fin[s_cbase[c] + pc];
+                    double f = s_fac[c] * wt[pc];
+                    val = C{(T)((double)a.x * f), (T)((double)a.y * f)};
                 }
-            }
-            lds[c * pitch + skew(i)] = val;
-        }
-        __syncthreads();
-
-        // ---------------- transform: radix 8 stages, then one radix 4 or 2 stage
-        int lgNs = 0;
-        while (lgL - lgNs >= 3) {
-            fft_stage<T, VPT, SIGN, 8>(lds, L, lgL, nl, pitch, lgNs, tw);
-            lgNs += 3;
-        }
-        if (lgL - lgNs == 2) {
-            fft_stage<T, VPT, SIGN, 4>(lds, L, lgL, nl, pitch, lgNs, tw);
-        } else if (lgL - lgNs == 1) {
-            fft_stage<T, VPT, SIGN, 2>(lds, L, lgL, nl, pitch, lgNs, tw);
-        }
-
-        // ---------------- store
-        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-            int c, i;
-            if (p.rows) {
-                c = idx >> lgL;
-                i = idx & (L - 1);
+            } else if (p.in_mode == 1) {
+                if (pos_to_coef(i, Nt, L) >= 0)
+                    val = grid[gb + i * st];
             } else {
-                c = idx & (nl - 1);
-                i = idx >> lgnl;
+                val = grid[gb + i * st];
             }
-            const int64_t gb = s_gbase[c];
-            if (gb < 0)
+        }
+        lds[c * pitch + skew(i)] = val;
+    }
+    __syncthreads();
+
+    // ---------------- transform: radix 8 stages, then one radix 4 or 2 stage
+    int lgNs = 0;
+    while (lgL - lgNs >= 3) {
+        fft_stage<T, VPT, SIGN, 8>(lds, L, lgL, nl, pitch, lgNs, tw);
+        lgNs += 3;
+    }
+    if (lgL - lgNs == 2) {
+        fft_stage<T, VPT, SIGN, 4>(lds, L, lgL, nl, pitch, lgNs, tw);
+    } else if (lgL - lgNs == 1) {
+        fft_stage<T, VPT, SIGN, 2>(lds, L, lgL, nl, pitch, lgNs, tw);
+    }
+
+    // ---------------- store
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+        int c, i;
+        if (p.rows) {
+            c = idx >> lgL;
+            i = idx & (L - 1);
+        } else {
+            c = idx & (nl - 1);
+            i = idx >> lgnl;
+        }
+        const int64_t gb = s_gbase[c];
+        if (gb < 0)
+            continue;
+        C val = lds[c * pitch + skew(i)];
+        if (p.out_mode == 0) {
+            grid[gb + i * st] = val;
+        } else {
+            int pc = pos_to_coef(i, Nt, L);
+            if (pc < 0)
                 continue;
-            C val = lds[c * pitch + skew(i)];
-            if (p.out_mode == 0) {
+            if (p.out_mode == 1) {
                 grid[gb + i * st] = val;
             } else {
-                int pc = pos_to_coef(i, Nt, L);
-                if (pc < 0)
-                    continue;
-                if (p.out_mode == 1) {
-                    grid[gb + i * st] = val;
-                } else {
-                    double f = s_fac[c] * wt[pc];
-                    fout[s_cbase[c] + pc] = C{(T)((double)val.x * f), (T)((double)val.y * f)};
-                }
+                double f = s_fac[c] * wt[pc];
+                fout[s_cbase[c] + pc] = C{(T)((double)val.x * f), (T)((double)val.y * f)};
             }
         }
-        __syncthreads();
+    }
+    __syncthreads();
+}
+
+template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass p)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int64_t s_gbase[kMaxLines];
+    __shared__ int s_cbase[kMaxLines];
+    __shared__ double s_fac[kMaxLines];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    for (int g = xcd_local_id(blockIdx.x, gridDim.x); g < (int)p.ngroups; g += gridDim.x)
+        fft_group<T, VPT, SIGN>(p, g, lds, s_gbase, s_cbase, s_fac);
+}
+
+// Pass `pass` (forward or adjoint) of every plan of a batch in one launch.
+template <typename T, int VPT, int SIGN>
+__global__ __launch_bounds__(kBlock) void k_fft_batch(const PlanDev *__restrict__ plans, int count, int pass,
+                                                      BatchPtrs ptrs)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int64_t s_gbase[kMaxLines];
+    __shared__ int s_cbase[kMaxLines];
+    __shared__ double s_fac[kMaxLines];
+    __shared__ int s_cnt[kMaxBatch];
+    __shared__ int s_prefix[kMaxBatch + 1];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    if ((int)threadIdx.x < count) {
+        const PlanDev &pd = plans[threadIdx.x];
+        s_cnt[threadIdx.x] = (int)(SIGN < 0 ? pd.fwd[pass].ngroups : pd.adj[pass].ngroups);
+    }
+    __syncthreads();
+    batch_prefix(s_prefix, count, s_cnt);
+    const int total = s_prefix[count];
+    for (int it = xcd_local_id(blockIdx.x, gridDim.x); it < total; it += gridDim.x) {
+        const int pi = batch_find(s_prefix, count, it);
+        const PlanDev &pd = plans[pi];
+        FftPass fp = SIGN < 0 ? pd.fwd[pass] : pd.adj[pass];
+        if (SIGN < 0 && pass == 0)
+            fp.fin = ptrs.in[pi];
+        if (SIGN > 0 && pass == pd.nfft - 1)
+            fp.fout = ptrs.out[pi];
+        fft_group<T, VPT, SIGN>(fp, it - s_prefix[pi], lds, s_gbase, s_cbase, s_fac);
     }
 }
 
@@ -324,6 +364,40 @@ template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int bl
 }
 
 }  // namespace
+
+template <typename T, int SIGN>
+hipError_t launch_batch_typed(const PlanDev *plans, int count, int pass, const BatchPtrs &ptrs, int vpt, int blocks,
+                              size_t lds, hipStream_t s)
+{
+    dim3 grid(blocks), block(kBlock);
+#define NFFT_FFT_CALL(V)                                                                               \
+    {                                                                                                  \
+        auto kf = k_fft_batch<T, V, SIGN>;                                                             \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kf, grid, block, lds, s, plans, count, pass, ptrs);                         \
+    }
+    switch (vpt) {
+    case 1: NFFT_FFT_CALL(1); break;
+    case 2: NFFT_FFT_CALL(2); break;
+    case 4: NFFT_FFT_CALL(4); break;
+    case 8: NFFT_FFT_CALL(8); break;
+    case 16: NFFT_FFT_CALL(16); break;
+    case 32: NFFT_FFT_CALL(32); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef NFFT_FFT_CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_batch(const PlanDev *plans, int count, int pass, bool forward, const BatchPtrs &ptrs,
+                            bool dbl, int vpt, int blocks, size_t lds, hipStream_t s)
+{
+    if (dbl)
+        return forward ? launch_batch_typed<double, -1>(plans, count, pass, ptrs, vpt, blocks, lds, s)
+                       : launch_batch_typed<double, 1>(plans, count, pass, ptrs, vpt, blocks, lds, s);
+    return forward ? launch_batch_typed<float, -1>(plans, count, pass, ptrs, vpt, blocks, lds, s)
+                   : launch_batch_typed<float, 1>(plans, count, pass, ptrs, vpt, blocks, lds, s);
+}
 
 hipError_t launch_fft_pass(const FftPass &p, bool dbl, int blocks, hipStream_t s)
 {

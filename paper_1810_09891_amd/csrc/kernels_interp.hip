@@ -15,6 +15,7 @@
 //    in LDS (LDS atomics, no global atomics) and writes the tile to its own slot of a
 //    scratch buffer; a fold kernel then writes every grid cell once as the sum, in a fixed
 //    order, of the tile slots that cover it.
+#include "batch_desc.hpp"
 #include "window_common.hpp"
 
 namespace nfft {
@@ -25,108 +26,142 @@ using namespace window;
 
 // ------------------------------------------------------------------ interpolation
 
+// One work item c of a plan: stage the bin's padded tile, then interpolate its nodes.
+template <typename T, int D, int WM>
+__device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ grid,
+                                            Cplx<T> *__restrict__ f, int c, Cplx<T> *tile)
+{
+    using C = Cplx<T>;
+    const T *psi = static_cast<const T *>(nd.psi);
+    const int W = g.W;
+    const int dW = D * W;
+    const int bin = nd.chunk_bin[c];
+    const int first = nd.chunk_first[c];
+    const int len = nd.chunk_len[c];
+    int bc[kMaxDim];
+    bin_coords<T, D>(g, bin, bc);
+    stage_tile<T, D>(g, bc, grid, tile);
+    __syncthreads();
+    // Thread t takes segment 4 (t mod 64) + t / 64 of the item's nodes (K per segment):
+    // the nodes are ordered by the bank residue of their tile position, so the 64 lanes
+    // of a wave start on different LDS banks.
+    const int K = (len + kBlock - 1) / kBlock;
+    const int seg = 4 * (threadIdx.x & 63) + (threadIdx.x >> 6);
+    for (int k = 0; k < K; ++k) {
+        const int i = seg * K + k;
+        if (i >= len)
+            continue;
+        const int node = first + i;
+        const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
+        int ul[kMaxDim];
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
+        T wl[WM];  // innermost dimension
+#pragma unroll
+        for (int s = 0; s < WM; ++s)
+            wl[s] = s < W ? pw[(D - 1) * W + s] : T(0);
+        T ax = 0, ay = 0;
+        if constexpr (D == 1) {
+            const C *row = tile + ul[0];
+#pragma unroll
+            for (int s = 0; s < WM; ++s) {
+                C v = row[s];
+                ax += wl[s] * v.x;
+                ay += wl[s] * v.y;
+            }
+        } else if constexpr (D == 2) {
+            T w0r[WM];
+#pragma unroll
+            for (int s = 0; s < WM; ++s)
+                w0r[s] = s < W ? pw[s] : T(0);
+#pragma unroll
+            for (int s0 = 0; s0 < WM; ++s0) {
+                if (s0 < W) {
+                    const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
+                    T rx = 0, ry = 0;
+#pragma unroll
+                    for (int s1 = 0; s1 < WM; ++s1) {
+                        C v = row[s1];
+                        rx += wl[s1] * v.x;
+                        ry += wl[s1] * v.y;
+                    }
+                    ax += w0r[s0] * rx;
+                    ay += w0r[s0] * ry;
+                }
+            }
+        } else {
+            T wmid[WM];
+#pragma unroll
+            for (int s = 0; s < WM; ++s)
+                wmid[s] = s < W ? pw[W + s] : T(0);
+            const int P1 = g.P[1], P2 = g.P[2];
+            for (int s0 = 0; s0 < W; ++s0) {
+                const T w0 = pw[s0];
+                const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
+                T px = 0, py = 0;
+#pragma unroll
+                for (int s1 = 0; s1 < WM; ++s1) {
+                    const C *row = plane + s1 * P2;
+                    T rx = 0, ry = 0;
+#pragma unroll
+                    for (int s2 = 0; s2 < WM; ++s2) {
+                        C v = row[s2];
+                        rx += wl[s2] * v.x;
+                        ry += wl[s2] * v.y;
+                    }
+                    px += wmid[s1] * rx;
+                    py += wmid[s1] * ry;
+                }
+                ax += w0 * px;
+                ay += w0 * py;
+            }
+        }
+        f[nd.perm[node]] = C{ax, ay};
+    }
+    __syncthreads();
+}
+
 template <typename T, int D, int WM>
 __global__ __launch_bounds__(kBlock) void k_interp_nodes(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
-                                                   Cplx<T> *__restrict__ f)
+                                                         Cplx<T> *__restrict__ f)
 {
     using C = Cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *tile = reinterpret_cast<C *>(smem_raw);
-    const T *psi = static_cast<const T *>(nd.psi);
-    const int W = g.W;
-    const int dW = D * W;
     const int nchunks = nd.counters[0];
     // work items are mapped over the first min(grid, items) workgroups, XCD by XCD
     const int nwg = min((int)gridDim.x, nchunks);
     if ((int)blockIdx.x >= nwg)
         return;
-    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
-        const int bin = nd.chunk_bin[c];
-        const int first = nd.chunk_first[c];
-        const int len = nd.chunk_len[c];
-        int bc[kMaxDim];
-        bin_coords<T, D>(g, bin, bc);
-        stage_tile<T, D>(g, bc, grid, tile);
-        __syncthreads();
-        // Thread t takes segment 4 (t mod 64) + t / 64 of the item's nodes (K per segment):
-        // the nodes are ordered by the bank residue of their tile position, so the 64 lanes
-        // of a wave start on different LDS banks.
-        const int K = (len + kBlock - 1) / kBlock;
-        const int seg = 4 * (threadIdx.x & 63) + (threadIdx.x >> 6);
-        for (int k = 0; k < K; ++k) {
-            const int i = seg * K + k;
-            if (i >= len)
-                continue;
-            const int node = first + i;
-            const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
-            int ul[kMaxDim];
-#pragma unroll
-            for (int t = 0; t < D; ++t)
-                ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
-            T wl[WM];  // innermost dimension
-#pragma unroll
-            for (int s = 0; s < WM; ++s)
-                wl[s] = s < W ? pw[(D - 1) * W + s] : T(0);
-            T ax = 0, ay = 0;
-            if constexpr (D == 1) {
-                const C *row = tile + ul[0];
-#pragma unroll
-                for (int s = 0; s < WM; ++s) {
-                    C v = row[s];
-                    ax += wl[s] * v.x;
-                    ay += wl[s] * v.y;
-                }
-            } else if constexpr (D == 2) {
-                T w0r[WM];
-#pragma unroll
-                for (int s = 0; s < WM; ++s)
-                    w0r[s] = s < W ? pw[s] : T(0);
-#pragma unroll
-                for (int s0 = 0; s0 < WM; ++s0) {
-                    if (s0 < W) {
-                        const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
-                        T rx = 0, ry = 0;
-#pragma unroll
-                        for (int s1 = 0; s1 < WM; ++s1) {
-                            C v = row[s1];
-                            rx += wl[s1] * v.x;
-                            ry += wl[s1] * v.y;
-                        }
-                        ax += w0r[s0] * rx;
-                        ay += w0r[s0] * ry;
-                    }
-                }
-            } else {
-                T wmid[WM];
-#pragma unroll
-                for (int s = 0; s < WM; ++s)
-                    wmid[s] = s < W ? pw[W + s] : T(0);
-                const int P1 = g.P[1], P2 = g.P[2];
-                for (int s0 = 0; s0 < W; ++s0) {
-                    const T w0 = pw[s0];
-                    const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
-                    T px = 0, py = 0;
-#pragma unroll
-                    for (int s1 = 0; s1 < WM; ++s1) {
-                        const C *row = plane + s1 * P2;
-                        T rx = 0, ry = 0;
-#pragma unroll
-                        for (int s2 = 0; s2 < WM; ++s2) {
-                            C v = row[s2];
-                            rx += wl[s2] * v.x;
-                            ry += wl[s2] * v.y;
-                        }
-                        px += wmid[s1] * rx;
-                        py += wmid[s1] * ry;
-                    }
-                    ax += w0 * px;
-                    ay += w0 * py;
-                }
-            }
-            f[nd.perm[node]] = C{ax, ay};
-        }
-        __syncthreads();
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg)
+        interp_item<T, D, WM>(g, nd, grid, f, c, tile);
+}
+
+// All plans of a batch in one launch: the work items of every plan, flattened in plan
+// order and handed out by the dynamic queue (plans come largest first).
+template <typename T, int D, int WM>
+__global__ __launch_bounds__(kBlock) void k_interp_batch(const PlanDev *__restrict__ plans, int count, BatchPtrs ptrs,
+                                                         int *queue)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *tile = reinterpret_cast<C *>(smem_raw);
+    __shared__ int s_cnt[kMaxBatch];
+    __shared__ int s_prefix[kMaxBatch + 1];
+    __shared__ int s_item;
+    if ((int)threadIdx.x < count)
+        s_cnt[threadIdx.x] = plans[threadIdx.x].nd.counters[0];
+    __syncthreads();
+    batch_prefix(s_prefix, count, s_cnt);
+    const int total = s_prefix[count];
+    for (int it = queue_next(queue, &s_item); it < total; it = queue_next(queue, &s_item)) {
+        const int p = batch_find(s_prefix, count, it);
+        const PlanDev &pd = plans[p];
+        interp_item<T, D, WM>(pd.g, pd.nd, static_cast<const C *>(pd.grid), static_cast<C *>(ptrs.out[p]),
+                              it - s_prefix[p], tile);
     }
+    queue_done(queue);
 }
 
 template <typename T, int D, int WM> constexpr auto pick_interp() { return k_interp_nodes<T, D, WM>; }
@@ -170,6 +205,37 @@ int fold_max_pairs(const Geom &g, int t)
             worst = cnt;
     }
     return worst;
+}
+
+namespace {
+template <typename T, int D>
+hipError_t interp_batch_typed(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int WMv,
+                              int blocks, size_t lds, hipStream_t s)
+{
+#define CALL(W_)                                                                                       \
+    {                                                                                                  \
+        auto kf = k_interp_batch<T, D, W_>;                                                            \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, plans, count, ptrs, queue);         \
+    }
+    NFFT_WM_SWITCH(WMv, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_interp_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,
+                               bool dbl, int WMv, int blocks, size_t lds, hipStream_t s)
+{
+    switch (d * 2 + (dbl ? 1 : 0)) {
+    case 2: return interp_batch_typed<float, 1>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 3: return interp_batch_typed<double, 1>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 4: return interp_batch_typed<float, 2>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 5: return interp_batch_typed<double, 2>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 6: return interp_batch_typed<float, 3>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 7: return interp_batch_typed<double, 3>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_interp(const Geom &g, const Nodes &nd, bool dbl, const void *grid, void *f, int blocks,

@@ -1,5 +1,6 @@
 // Spreading (Algorithm 2.2 step 1): LDS tile accumulation per work item and the
 // deterministic fold of the tiles into the grid.  Geometry as in window_common.hpp.
+#include "batch_desc.hpp"
 #include "window_common.hpp"
 
 namespace nfft {
@@ -41,13 +42,12 @@ __device__ __forceinline__ double bcast(double v, int k)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// One work item c: accumulate its nodes into LDS tiles, write the summed tile to its slot.
 template <typename T, int D, int WM>
-__global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const Cplx<T> *__restrict__ f,
-                                                         Cplx<T> *__restrict__ scratch)
+__device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ f,
+                                            Cplx<T> *__restrict__ scratch, int c, Cplx<T> *tiles)
 {
     using C = Cplx<T>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *tiles = reinterpret_cast<C *>(smem_raw);
     const T *psi = static_cast<const T *>(nd.psi);
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -59,154 +59,188 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
     const int r = lane / WM;
     const int sc = lane - r * WM;  // stencil column of this lane
     const bool lane_ok = r < R && sc < W;
+    const int first = nd.chunk_first[c];
+    const int len = nd.chunk_len[c];
+    if constexpr (D < 3) {
+        C *sub = tiles + wave * g.Ptot;
+        for (int i = lane; i < g.Ptot; i += 64)
+            sub[i] = C{T(0), T(0)};
+        // this wave's contiguous share of the work item, in batches of kBatch nodes whose
+        // data is loaded one batch ahead (one node per lane; window factor l in lane l)
+        const int lo = first + (len * wave) / kWaves;
+        const int hi = first + (len * (wave + 1)) / kWaves;
+        T fx = 0, fy = 0, wv[kBatch];
+        int u0 = 0, u1 = 0;
+        auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, int &lu1, T *lwv) {
+            const int nb = min(kBatch, hi - b0);
+            lfx = lfy = T(0);
+            lu0 = lu1 = 0;
+            if (lane < nb) {
+                const C fv = f[nd.perm[b0 + lane]];
+                lfx = fv.x;
+                lfy = fv.y;
+                lu0 = nd.u[0][b0 + lane] & ((1 << g.lgB[0]) - 1);
+                if (D == 2)
+                    lu1 = nd.u[1][b0 + lane] & ((1 << g.lgB[1]) - 1);
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                lwv[k] = (k < nb && lane < dW) ? psi[(int64_t)(b0 + k) * dW + lane] : T(0);
+        };
+        if (lo < hi)
+            load_batch(lo, fx, fy, u0, u1, wv);
+        for (int b0 = lo; b0 < hi; b0 += kBatch) {
+            const int nb = min(kBatch, hi - b0);
+            T nfx = 0, nfy = 0, nwv[kBatch];
+            int nu0 = 0, nu1 = 0;
+            if (b0 + kBatch < hi)
+                load_batch(b0 + kBatch, nfx, nfy, nu0, nu1, nwv);
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (k >= nb)
+                    break;
+                const T fxk = bcast(fx, k), fyk = bcast(fy, k);
+                const int ul0 = bcast(u0, k);
+                if constexpr (D == 1) {
+                    if (lane < W) {
+                        C v = sub[ul0 + lane];
+                        v.x += fxk * wv[k];
+                        v.y += fyk * wv[k];
+                        sub[ul0 + lane] = v;
+                    }
+                } else {
+                    const int ul1 = bcast(u1, k);
+                    const T w1 = lane_shfl(wv[k], W + (sc < W ? sc : 0));
+                    const T ax = fxk * w1, ay = fyk * w1;
+                    const int base = ul0 * g.P[1] + ul1 + sc;
+                    T w0[NPASS];
+                    C v[NPASS];
+#pragma unroll
+                    for (int q = 0; q < NPASS; ++q) {
+                        const int s0 = q * R + r;
+                        w0[q] = lane_shfl(wv[k], s0 < W ? s0 : 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < NPASS; ++q) {
+                        const int s0 = q * R + r;
+                        if (lane_ok && s0 < W)
+                            v[q] = sub[base + s0 * g.P[1]];
+                    }
+#pragma unroll
+                    for (int q = 0; q < NPASS; ++q) {
+                        const int s0 = q * R + r;
+                        if (lane_ok && s0 < W) {
+                            v[q].x += ax * w0[q];
+                            v[q].y += ay * w0[q];
+                            sub[base + s0 * g.P[1]] = v[q];
+                        }
+                    }
+                }
+            }
+            fx = nfx;
+            fy = nfy;
+            u0 = nu0;
+            u1 = nu1;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                wv[k] = nwv[k];
+        }
+        __syncthreads();
+        C *slot = scratch + (int64_t)c * g.Ptot;
+        for (int i = threadIdx.x; i < g.Ptot; i += kBlock) {
+            C a = tiles[i];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) {
+                C b = tiles[w * g.Ptot + i];
+                a.x += b.x;
+                a.y += b.y;
+            }
+            slot[i] = a;
+        }
+        __syncthreads();
+    } else {
+        for (int i = threadIdx.x; i < g.Ptot; i += kBlock)
+            tiles[i] = C{T(0), T(0)};
+        __syncthreads();
+        const int P1 = g.P[1], P2 = g.P[2];
+        for (int i = 0; i < len; ++i) {
+            const int node = first + i;
+            const C fv = f[nd.perm[node]];
+            const int64_t prow = (int64_t)node * dW;
+            const T wv0 = lane < dW ? psi[prow + lane] : T(0);
+            const T wv1 = lane + 64 < dW ? psi[prow + 64 + lane] : T(0);
+            const int ul0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
+            const int ul1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
+            const int ul2 = nd.u[2][node] & ((1 << g.lgB[2]) - 1);
+            const int slot2 = 2 * W + (sc < W ? sc : 0);  // factor of dimension 2 at this lane's column
+            const T w2a = lane_shfl(wv0, slot2 < 64 ? slot2 : 0);
+            const T w2b = lane_shfl(wv1, slot2 >= 64 ? slot2 - 64 : 0);
+            const T w2 = slot2 < 64 ? w2a : w2b;
+            const T ax = fv.x * w2, ay = fv.y * w2;
+            for (int s0 = wave; s0 < W; s0 += kWaves) {
+                const T w0 = lane_shfl(wv0, s0);
+                const T bx = ax * w0, by = ay * w0;
+                const int pbase = (ul0 + s0) * P1 + ul1;
+                for (int s1b = 0; s1b < W; s1b += R) {
+                    const int s1 = s1b + r;
+                    const T w1 = lane_shfl(wv0, W + (s1 < W ? s1 : 0));
+                    if (lane_ok && s1 < W) {
+                        const int idx = (pbase + s1) * P2 + ul2 + sc;
+                        C v = tiles[idx];
+                        v.x += bx * w1;
+                        v.y += by * w1;
+                        tiles[idx] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        C *slot = scratch + (int64_t)c * g.Ptot;
+        for (int i = threadIdx.x; i < g.Ptot; i += kBlock)
+            slot[i] = tiles[i];
+        __syncthreads();
+    }
+}
+
+template <typename T, int D, int WM>
+__global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const Cplx<T> *__restrict__ f,
+                                                         Cplx<T> *__restrict__ scratch)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *tiles = reinterpret_cast<C *>(smem_raw);
     const int nchunks = nd.counters[0];
     // work items are mapped over the first min(grid, items) workgroups, XCD by XCD
     const int nwg = min((int)gridDim.x, nchunks);
     if ((int)blockIdx.x >= nwg)
         return;
-    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
-        const int first = nd.chunk_first[c];
-        const int len = nd.chunk_len[c];
-        if constexpr (D < 3) {
-            C *sub = tiles + wave * g.Ptot;
-            for (int i = lane; i < g.Ptot; i += 64)
-                sub[i] = C{T(0), T(0)};
-            // this wave's contiguous share of the work item, in batches of kBatch nodes whose
-            // data is loaded one batch ahead (one node per lane; window factor l in lane l)
-            const int lo = first + (len * wave) / kWaves;
-            const int hi = first + (len * (wave + 1)) / kWaves;
-            T fx = 0, fy = 0, wv[kBatch];
-            int u0 = 0, u1 = 0;
-            auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, int &lu1, T *lwv) {
-                const int nb = min(kBatch, hi - b0);
-                lfx = lfy = T(0);
-                lu0 = lu1 = 0;
-                if (lane < nb) {
-                    const C fv = f[nd.perm[b0 + lane]];
-                    lfx = fv.x;
-                    lfy = fv.y;
-                    lu0 = nd.u[0][b0 + lane] & ((1 << g.lgB[0]) - 1);
-                    if (D == 2)
-                        lu1 = nd.u[1][b0 + lane] & ((1 << g.lgB[1]) - 1);
-                }
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k)
-                    lwv[k] = (k < nb && lane < dW) ? psi[(int64_t)(b0 + k) * dW + lane] : T(0);
-            };
-            if (lo < hi)
-                load_batch(lo, fx, fy, u0, u1, wv);
-            for (int b0 = lo; b0 < hi; b0 += kBatch) {
-                const int nb = min(kBatch, hi - b0);
-                T nfx = 0, nfy = 0, nwv[kBatch];
-                int nu0 = 0, nu1 = 0;
-                if (b0 + kBatch < hi)
-                    load_batch(b0 + kBatch, nfx, nfy, nu0, nu1, nwv);
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k) {
-                    if (k >= nb)
-                        break;
-                    const T fxk = bcast(fx, k), fyk = bcast(fy, k);
-                    const int ul0 = bcast(u0, k);
-                    if constexpr (D == 1) {
-                        if (lane < W) {
-                            C v = sub[ul0 + lane];
-                            v.x += fxk * wv[k];
-                            v.y += fyk * wv[k];
-                            sub[ul0 + lane] = v;
-                        }
-                    } else {
-                        const int ul1 = bcast(u1, k);
-                        const T w1 = lane_shfl(wv[k], W + (sc < W ? sc : 0));
-                        const T ax = fxk * w1, ay = fyk * w1;
-                        const int base = ul0 * g.P[1] + ul1 + sc;
-                        T w0[NPASS];
-                        C v[NPASS];
-#pragma unroll
-                        for (int q = 0; q < NPASS; ++q) {
-                            const int s0 = q * R + r;
-                            w0[q] = lane_shfl(wv[k], s0 < W ? s0 : 0);
-                        }
-#pragma unroll
-                        for (int q = 0; q < NPASS; ++q) {
-                            const int s0 = q * R + r;
-                            if (lane_ok && s0 < W)
-                                v[q] = sub[base + s0 * g.P[1]];
-                        }
-#pragma unroll
-                        for (int q = 0; q < NPASS; ++q) {
-                            const int s0 = q * R + r;
-                            if (lane_ok && s0 < W) {
-                                v[q].x += ax * w0[q];
-                                v[q].y += ay * w0[q];
-                                sub[base + s0 * g.P[1]] = v[q];
-                            }
-                        }
-                    }
-                }
-                fx = nfx;
-                fy = nfy;
-                u0 = nu0;
-                u1 = nu1;
-#pragma unroll
-                for (int k = 0; k < kBatch; ++k)
-                    wv[k] = nwv[k];
-            }
-            __syncthreads();
-            C *slot = scratch + (int64_t)c * g.Ptot;
-            for (int i = threadIdx.x; i < g.Ptot; i += kBlock) {
-                C a = tiles[i];
-#pragma unroll
-                for (int w = 1; w < kWaves; ++w) {
-                    C b = tiles[w * g.Ptot + i];
-                    a.x += b.x;
-                    a.y += b.y;
-                }
-                slot[i] = a;
-            }
-            __syncthreads();
-        } else {
-            for (int i = threadIdx.x; i < g.Ptot; i += kBlock)
-                tiles[i] = C{T(0), T(0)};
-            __syncthreads();
-            const int P1 = g.P[1], P2 = g.P[2];
-            for (int i = 0; i < len; ++i) {
-                const int node = first + i;
-                const C fv = f[nd.perm[node]];
-                const int64_t prow = (int64_t)node * dW;
-                const T wv0 = lane < dW ? psi[prow + lane] : T(0);
-                const T wv1 = lane + 64 < dW ? psi[prow + 64 + lane] : T(0);
-                const int ul0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
-                const int ul1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
-                const int ul2 = nd.u[2][node] & ((1 << g.lgB[2]) - 1);
-                const int slot2 = 2 * W + (sc < W ? sc : 0);  // factor of dimension 2 at this lane's column
-                const T w2a = lane_shfl(wv0, slot2 < 64 ? slot2 : 0);
-                const T w2b = lane_shfl(wv1, slot2 >= 64 ? slot2 - 64 : 0);
-                const T w2 = slot2 < 64 ? w2a : w2b;
-                const T ax = fv.x * w2, ay = fv.y * w2;
-                for (int s0 = wave; s0 < W; s0 += kWaves) {
-                    const T w0 = lane_shfl(wv0, s0);
-                    const T bx = ax * w0, by = ay * w0;
-                    const int pbase = (ul0 + s0) * P1 + ul1;
-                    for (int s1b = 0; s1b < W; s1b += R) {
-                        const int s1 = s1b + r;
-                        const T w1 = lane_shfl(wv0, W + (s1 < W ? s1 : 0));
-                        if (lane_ok && s1 < W) {
-                            const int idx = (pbase + s1) * P2 + ul2 + sc;
-                            C v = tiles[idx];
-                            v.x += bx * w1;
-                            v.y += by * w1;
-                            tiles[idx] = v;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            C *slot = scratch + (int64_t)c * g.Ptot;
-            for (int i = threadIdx.x; i < g.Ptot; i += kBlock)
-                slot[i] = tiles[i];
-            __syncthreads();
-        }
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg)
+        spread_item<T, D, WM>(g, nd, f, scratch, c, tiles);
+}
+
+// All plans of a batch in one launch, items handed out by the dynamic queue.
+template <typename T, int D, int WM>
+__global__ __launch_bounds__(kBlock) void k_spread_batch(const PlanDev *__restrict__ plans, int count, BatchPtrs ptrs,
+                                                         int *queue)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *tiles = reinterpret_cast<C *>(smem_raw);
+    __shared__ int s_cnt[kMaxBatch];
+    __shared__ int s_prefix[kMaxBatch + 1];
+    __shared__ int s_item;
+    if ((int)threadIdx.x < count)
+        s_cnt[threadIdx.x] = plans[threadIdx.x].nd.counters[0];
+    __syncthreads();
+    batch_prefix(s_prefix, count, s_cnt);
+    const int total = s_prefix[count];
+    for (int it = queue_next(queue, &s_item); it < total; it = queue_next(queue, &s_item)) {
+        const int p = batch_find(s_prefix, count, it);
+        const PlanDev &pd = plans[p];
+        spread_item<T, D, WM>(pd.g, pd.nd, static_cast<const C *>(ptrs.in[p]), static_cast<C *>(pd.scratch),
+                              it - s_prefix[p], tiles);
     }
+    queue_done(queue);
 }
 
 // Fold: grid cell l receives, from every work item of every bin b whose padded tile covers
@@ -230,18 +264,13 @@ __device__ __forceinline__ Cover cover_range(int l, int k, int n, int lgB, int n
     return cv;
 }
 
+// Grid cell q of a plan: sum of the tile entries covering it, in a fixed order.
 template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_fold(Geom g, Nodes nd, const Cplx<T> *__restrict__ scratch,
-                                                 Cplx<T> *__restrict__ grid)
+__device__ __forceinline__ void fold_cell(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ scratch,
+                                          Cplx<T> *__restrict__ grid, int64_t q)
 {
     using C = Cplx<T>;
-    int64_t total = 1;
-#pragma unroll
-    for (int t = 0; t < D; ++t)
-        total *= g.n[t];
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total)
-        return;
+
     int l[kMaxDim] = {0, 0, 0};
     {
         int64_t rq = q;
@@ -291,6 +320,40 @@ __global__ __launch_bounds__(kBlock) void k_fold(Geom g, Nodes nd, const Cplx<T>
 }
 
 template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_fold(Geom g, Nodes nd, const Cplx<T> *__restrict__ scratch,
+                                                 Cplx<T> *__restrict__ grid)
+{
+    int64_t total = 1;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        total *= g.n[t];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < total)
+        fold_cell<T, D>(g, nd, scratch, grid, q);
+}
+
+// Batched fold: items are blocks of kBlock cells of every plan's adjoint grid.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_fold_batch(const PlanDev *__restrict__ plans, int count)
+{
+    using C = Cplx<T>;
+    __shared__ int s_cnt[kMaxBatch];
+    __shared__ int s_prefix[kMaxBatch + 1];
+    if ((int)threadIdx.x < count)
+        s_cnt[threadIdx.x] = (int)((plans[threadIdx.x].ngrid + kBlock - 1) / kBlock);
+    __syncthreads();
+    batch_prefix(s_prefix, count, s_cnt);
+    const int total = s_prefix[count];
+    for (int it = xcd_local_id(blockIdx.x, gridDim.x); it < total; it += gridDim.x) {
+        const int p = batch_find(s_prefix, count, it);
+        const PlanDev &pd = plans[p];
+        const int64_t q = (int64_t)(it - s_prefix[p]) * kBlock + threadIdx.x;
+        if (q < pd.ngrid)
+            fold_cell<T, D>(pd.g, pd.nd, static_cast<const C *>(pd.scratch), static_cast<C *>(pd.grid_adj), q);
+    }
+}
+
+template <typename T, int D>
 hipError_t spread_typed(const Geom &g, const Nodes &nd, const void *f, void *scratch, int blocks, size_t lds,
                         hipStream_t s)
 {
@@ -328,6 +391,55 @@ hipError_t launch_spread_tiles(const Geom &g, const Nodes &nd, bool dbl, const v
 hipError_t launch_fold(const Geom &g, const Nodes &nd, bool dbl, const void *scratch, void *grid, hipStream_t s)
 {
     NFFT_DT_SWITCH(fold_typed, g, nd, scratch, grid, s)
+}
+
+namespace {
+template <typename T, int D>
+hipError_t spread_batch_typed(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int WMv,
+                              int blocks, size_t lds, hipStream_t s)
+{
+#define CALL(W_)                                                                                       \
+    {                                                                                                  \
+        auto kf = k_spread_batch<T, D, W_>;                                                            \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, plans, count, ptrs, queue);         \
+    }
+    NFFT_WM_SWITCH(WMv, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+template <typename T, int D> hipError_t fold_batch_typed(const PlanDev *plans, int count, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fold_batch<T, D>), dim3(blocks), dim3(kBlock), 0, s, plans, count);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_spread_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,
+                               bool dbl, int WMv, int blocks, size_t lds, hipStream_t s)
+{
+    switch (d * 2 + (dbl ? 1 : 0)) {
+    case 2: return spread_batch_typed<float, 1>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 3: return spread_batch_typed<double, 1>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 4: return spread_batch_typed<float, 2>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 5: return spread_batch_typed<double, 2>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 6: return spread_batch_typed<float, 3>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    case 7: return spread_batch_typed<double, 3>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fold_batch(const PlanDev *plans, int count, int d, bool dbl, int blocks, hipStream_t s)
+{
+    switch (d * 2 + (dbl ? 1 : 0)) {
+    case 2: return fold_batch_typed<float, 1>(plans, count, blocks, s);
+    case 3: return fold_batch_typed<double, 1>(plans, count, blocks, s);
+    case 4: return fold_batch_typed<float, 2>(plans, count, blocks, s);
+    case 5: return fold_batch_typed<double, 2>(plans, count, blocks, s);
+    case 6: return fold_batch_typed<float, 3>(plans, count, blocks, s);
+    case 7: return fold_batch_typed<double, 3>(plans, count, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace nfft

@@ -64,6 +64,23 @@ size_t spread_lds_bytes(const Geom &g, bool dbl);
 constexpr int kFoldMaxPairs = 24;
 int fold_max_pairs(const Geom &g, int t);
 
+// ------------------------------------------------------------------ batched launches
+//
+// One launch covers pass / step of every plan in `plans` (a device array of `count`
+// PlanDev, count <= kMaxBatch, all with the same d, compiled width WMv and precision).
+// The interpolation and spreading kernels take work items from the queue `queue`
+// (two ints, zero between launches).
+
+struct PlanDev;
+struct BatchPtrs;
+hipError_t launch_fft_batch(const PlanDev *plans, int count, int pass, bool forward, const BatchPtrs &ptrs,
+                            bool dbl, int vpt, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_interp_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,
+                               bool dbl, int WMv, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_spread_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,
+                               bool dbl, int WMv, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_fold_batch(const PlanDev *plans, int count, int d, bool dbl, int blocks, hipStream_t s);
+
 // ------------------------------------------------------------------ direct sums
 
 struct NdftArgs {

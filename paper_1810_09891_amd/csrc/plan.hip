@@ -61,7 +61,8 @@ static int choose_bins(nfft_plan_s *p)
     // the interpolation kernel keeps one.
     const int minB = 4;
     const size_t ntiles = d < 3 ? 4 : 1;
-    const size_t budget = d < 3 ? kLdsMax : kLdsPreferred;
+    // (1 KB of LDS is left for the static arrays of the batched kernels)
+    const size_t budget = (d < 3 ? kLdsMax : kLdsPreferred) - 1024;
     while (ntiles * lds_of(B) > budget) {
         int best = -1;
         for (int t = 0; t < d; ++t)
@@ -71,7 +72,7 @@ static int choose_bins(nfft_plan_s *p)
             break;
         B[best] /= 2;
     }
-    if (ntiles * lds_of(B) > kLdsMax)
+    if (ntiles * lds_of(B) > kLdsMax - 1024)
         return NFFT_ERR_UNSUPPORTED;
     Geom &g = p->geom;
     g.Ptot = 1;
@@ -159,6 +160,32 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
 }
 
 }  // namespace nfft
+
+bool plan_repack_pass(const nfft_plan_s *p, const FftPass &tmpl, int factor, FftPass &out)
+{
+    out = tmpl;
+    if (factor == 1)
+        return true;
+    const int maxPts = p->dbl ? 4096 : 8192;
+    int nl = tmpl.nl * factor;
+    if (nl < 1 || nl > 256 || (int64_t)nl * tmpl.L > maxPts)
+        return false;
+    if (tmpl.rows) {
+        if (nl > tmpl.nrows)
+            return false;
+        out.ngroups = (tmpl.nrows + nl - 1) / nl;
+    } else {
+        const int inner = (int)p->n[p->d - 1];
+        if (nl > inner || nl < 2)
+            return false;
+        const int64_t outer = tmpl.ngroups / tmpl.ncb;
+        out.ncb = inner / nl;
+        out.ngroups = outer * out.ncb;
+    }
+    out.nl = nl;
+    out.vpt = std::max(1, nl * tmpl.L / 256);
+    return true;
+}
 
 static int build_tables(nfft_plan_s *p)
 {
@@ -319,7 +346,7 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
 
 // ------------------------------------------------------------------ device views
 
-static Nodes node_view(nfft_plan_s *p)
+Nodes plan_node_view(nfft_plan_s *p)
 {
     Nodes nd;
     std::memset(&nd, 0, sizeof(nd));
@@ -346,7 +373,7 @@ static Nodes node_view(nfft_plan_s *p)
     return nd;
 }
 
-static FftPass bind_pass(nfft_plan_s *p, const FftPass &tmpl, void *grid, const void *fin, void *fout)
+FftPass plan_bind_pass(nfft_plan_s *p, const FftPass &tmpl, void *grid, const void *fin, void *fout)
 {
     FftPass fp = tmpl;
     char *ws = static_cast<char *>(p->ws);
@@ -416,7 +443,7 @@ static int grid_blocks(nfft_plan_s *p)
 static int run_forward_grid(nfft_plan_s *p, const void *fhat, void *grid, hipStream_t s)
 {
     for (size_t i = 0; i < p->fwd_passes.size(); ++i) {
-        FftPass fp = bind_pass(p, p->fwd_passes[i], grid, fhat, nullptr);
+        FftPass fp = plan_bind_pass(p, p->fwd_passes[i], grid, fhat, nullptr);
         int blocks = (int)std::min<int64_t>(fp.ngroups, 1 << 20);
         LAUNCH(p, s, i == 0 ? "fft_fwd_deconv" : "fft_fwd", launch_fft_pass(fp, p->dbl, blocks, s));
     }
@@ -426,7 +453,7 @@ static int run_forward_grid(nfft_plan_s *p, const void *fhat, void *grid, hipStr
 static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_t s)
 {
     for (size_t i = 0; i < p->adj_passes.size(); ++i) {
-        FftPass fp = bind_pass(p, p->adj_passes[i], grid, nullptr, hhat);
+        FftPass fp = plan_bind_pass(p, p->adj_passes[i], grid, nullptr, hhat);
         int blocks = (int)std::min<int64_t>(fp.ngroups, 1 << 20);
         LAUNCH(p, s, i + 1 == p->adj_passes.size() ? "fft_adj_deconv" : "fft_adj",
                launch_fft_pass(fp, p->dbl, blocks, s));
@@ -436,7 +463,7 @@ static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_
 
 static int run_interp(nfft_plan_s *p, const void *grid, void *f, hipStream_t s)
 {
-    Nodes nd = node_view(p);
+    Nodes nd = plan_node_view(p);
     LAUNCH(p, s, "interp",
            launch_interp(p->geom, nd, p->dbl, grid, f, grid_blocks(p), interp_lds_bytes(p->geom, p->dbl), s));
     return NFFT_OK;
@@ -444,7 +471,7 @@ static int run_interp(nfft_plan_s *p, const void *grid, void *f, hipStream_t s)
 
 static int run_spread(nfft_plan_s *p, const void *f, void *grid, hipStream_t s)
 {
-    Nodes nd = node_view(p);
+    Nodes nd = plan_node_view(p);
     void *scratch = static_cast<char *>(p->ws) + p->off_scratch;
     LAUNCH(p, s, "spread_tiles",
            launch_spread_tiles(p->geom, nd, p->dbl, f, scratch, grid_blocks(p),
@@ -574,7 +601,7 @@ int nfft_set_nodes(nfft_plan p, const double *x, hipStream_t s)
     int st = ensure_tables(p, s);
     if (st != NFFT_OK)
         return st;
-    Nodes nd = node_view(p);
+    Nodes nd = plan_node_view(p);
     nd.x = x;
     double *xcopy = reinterpret_cast<double *>(static_cast<char *>(p->ws) + p->off_xcopy);
     p->nodes_set = false;
@@ -718,7 +745,7 @@ int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t s)
         return NFFT_ERR_ARG;
     if (!(p->flags & NFFT_KEEP_GRID) || !p->grid_valid)
         return NFFT_ERR_STATE;
-    Nodes nd = node_view(p);
+    Nodes nd = plan_node_view(p);
     const void *grid = static_cast<char *>(p->ws) + p->off_grid;
     LAUNCH(p, s, "grad_x",
            launch_grad_x(p->geom, nd, p->dbl, grid, v, grad_x, grid_blocks(p), interp_lds_bytes(p->geom, p->dbl),

@@ -58,3 +58,10 @@ struct nfft_plan_s {
     std::set<std::string> names;
     const char *intern(const std::string &s) { return names.insert(s).first->c_str(); }
 };
+
+// Device views of a plan with a workspace attached (shared with the batch code).
+nfft::Nodes plan_node_view(nfft_plan_s *p);
+nfft::FftPass plan_bind_pass(nfft_plan_s *p, const nfft::FftPass &tmpl, void *grid, const void *fin, void *fout);
+// FFT pass `tmpl` with `factor` times as many lines per workgroup (factor 1: unchanged);
+// false when the packing does not fit the pass.
+bool plan_repack_pass(const nfft_plan_s *p, const nfft::FftPass &tmpl, int factor, nfft::FftPass &out);

@@ -211,3 +211,96 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many plans run together: ``trafo`` / ``adjoint`` take and return lists in the order of
+    ``plans`` and launch each step kind once for all of them.  Every plan needs its nodes
+    set (``Plan.set_nodes``) before the first call; ``autotune`` picks the launch shapes
+    (cached in ``tune_cache`` when given)."""
+
+    def __init__(self, plans, tune_cache=None):
+        lib = _lib.load()
+        self._lib = lib
+        self.plans = list(plans)
+        if not self.plans:
+            raise ValueError("a batch needs at least one plan")
+        self.device = self.plans[0].device
+        for p in self.plans:
+            if p.workspace is None:
+                p.allocate()
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        cache = None if tune_cache is None else str(tune_cache).encode()
+        check(lib.nfft_batch_create(ctypes.byref(h), len(self.plans), arr, cache), "nfft_batch_create")
+        self._h = h
+        info = _lib.BatchInfo()
+        check(lib.nfft_batch_get_info(h, ctypes.byref(info)), "nfft_batch_get_info")
+        nbytes = int(info.workspace_bytes)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        check(lib.nfft_batch_set_workspace(h, ctypes.c_void_p(ws.data_ptr() + off), nbytes),
+              "nfft_batch_set_workspace")
+
+    @property
+    def info(self):
+        info = _lib.BatchInfo()
+        check(self._lib.nfft_batch_get_info(self._h, ctypes.byref(info)), "nfft_batch_get_info")
+        return info
+
+    def params(self, group):
+        """Launch parameters of launch group ``group`` as a dict (see the C header)."""
+        v = (ctypes.c_int * _lib.NFFT_BATCH_NPARAMS)()
+        cnt = ctypes.c_int()
+        check(self._lib.nfft_batch_get_params(self._h, int(group), v, ctypes.byref(cnt)), "nfft_batch_get_params")
+        out = dict(zip(_lib.BATCH_PARAM_NAMES, list(v)))
+        out["plans"] = cnt.value
+        return out
+
+    def set_params(self, group, **kw):
+        cur = self.params(group)
+        v = (ctypes.c_int * _lib.NFFT_BATCH_NPARAMS)(*[int(kw.get(k, cur[k])) for k in _lib.BATCH_PARAM_NAMES])
+        check(self._lib.nfft_batch_set_params(self._h, int(group), v), "nfft_batch_set_params")
+
+    def autotune(self):
+        check(self._lib.nfft_batch_autotune(self._h, _stream(self.device)), "nfft_batch_autotune")
+        return [self.params(g) for g in range(self.info.groups)]
+
+    def _io(self, ins, outs, in_shape, out_shape):
+        if len(ins) != len(self.plans):
+            raise ValueError("expected %d arrays" % len(self.plans))
+        ins = [p._as(a, p.dtype, in_shape(p), "in") for p, a in zip(self.plans, ins)]
+        if outs is None:
+            outs = [p._out(None, out_shape(p)) for p in self.plans]
+        else:
+            outs = [p._out(o, out_shape(p)) for p, o in zip(self.plans, outs)]
+        n = len(self.plans)
+        ip = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ins])
+        op = (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs])
+        return ins, outs, ip, op
+
+    def trafo(self, fhats, outs=None):
+        fhats, outs, ip, op = self._io(fhats, outs, lambda p: p.N, lambda p: (p.M,))
+        check(self._lib.nfft_batch_trafo(self._h, ip, op, _stream(self.device)), "nfft_batch_trafo")
+        for p in self.plans:
+            p.generation += 1
+        self._keep = fhats  # alive until the enqueued work has read them
+        return outs
+
+    def adjoint(self, fs, outs=None):
+        fs, outs, ip, op = self._io(fs, outs, lambda p: (p.M,), lambda p: p.N)
+        check(self._lib.nfft_batch_adjoint(self._h, ip, op, _stream(self.device)), "nfft_batch_adjoint")
+        self._keep = fs
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nfft_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

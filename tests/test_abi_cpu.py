@@ -131,3 +131,59 @@ def test_workspace_sizes_scale(lib):
             lib.nfft_plan_destroy(h)
     assert sizes[(1, 100000)] > sizes[(1, 1000)]
     assert sizes[(2, 1000)] > sizes[(1, 1000)]
+
+
+def test_batch_create_validation(lib):
+    """Batch creation is host-only: it checks its plans and lays out its own memory."""
+    fake = ctypes.c_void_p(1 << 20)
+    hs = []
+    for N, m, dt in (((64, 64), 6, 1), ((32, 128), 6, 1), ((64, 64), 4, 1), ((128,), 6, 1), ((64, 64), 6, 2)):
+        st, h = create(lib, N, 1000, None, m, dt)
+        assert st == OK
+        hs.append(h)
+    P = ctypes.c_void_p
+    arr = lambda *h: (P * len(h))(*[x.value for x in h])  # noqa: E731
+    out = P()
+    assert lib.nfft_batch_create(None, 1, arr(hs[0]), None) == ARG
+    assert lib.nfft_batch_create(ctypes.byref(out), 0, arr(hs[0]), None) == ARG
+    assert lib.nfft_batch_create(ctypes.byref(out), 1, None, None) == ARG
+    # no workspace attached yet
+    assert lib.nfft_batch_create(ctypes.byref(out), 2, arr(hs[0], hs[1]), None) == WS
+    for h in hs:
+        nb = ctypes.c_size_t()
+        lib.nfft_workspace_bytes(h, ctypes.byref(nb))
+        assert lib.nfft_set_workspace(h, fake, nb.value) == OK
+    # mixed precision, repeated plan
+    assert lib.nfft_batch_create(ctypes.byref(out), 2, arr(hs[0], hs[4]), None) == ARG
+    assert lib.nfft_batch_create(ctypes.byref(out), 2, arr(hs[0], hs[0]), None) == ARG
+    # four complex64 plans: d=2 width 14 (two plans), d=2 width 10, d=1 -> three launch groups
+    assert lib.nfft_batch_create(ctypes.byref(out), 4, arr(*hs[:4]), None) == OK
+    info = _lib.BatchInfo()
+    assert lib.nfft_batch_get_info(out, ctypes.byref(info)) == OK
+    assert (info.count, info.groups, info.tuned) == (4, 3, 0)
+    assert info.workspace_bytes > 0
+    params = (ctypes.c_int * 8)()
+    cnt = ctypes.c_int()
+    counts = []
+    for g in range(3):
+        assert lib.nfft_batch_get_params(out, g, params, ctypes.byref(cnt)) == OK
+        counts.append(cnt.value)
+        assert list(params)[:7] == [1, 0, 1, 0, 8, 8, 0]
+    assert sorted(counts) == [1, 1, 2]
+    assert lib.nfft_batch_get_params(out, 3, params, None) == ARG
+    bad = (ctypes.c_int * 8)(3, 0, 1, 0, 8, 8, 0, 0)  # packing must be a power of two
+    assert lib.nfft_batch_set_params(out, 0, bad) == ARG
+    good = (ctypes.c_int * 8)(2, 4, 1, 0, 2, 2, 1, 0)
+    assert lib.nfft_batch_set_params(out, 0, good) == OK  # no batch workspace yet: host only
+    assert lib.nfft_batch_get_params(out, 0, params, None) == OK
+    assert list(params) == list(good)
+    # calls before the batch workspace is attached
+    ptrs = (P * 4)(*([fake.value] * 4))
+    assert lib.nfft_batch_trafo(out, ptrs, ptrs, None) == WS
+    assert lib.nfft_batch_adjoint(out, ptrs, ptrs, None) == WS
+    assert lib.nfft_batch_autotune(out, None) == WS
+    assert lib.nfft_batch_set_workspace(out, fake, 0) == WS
+    assert lib.nfft_batch_destroy(out) == OK
+    assert lib.nfft_batch_destroy(None) == ARG
+    for h in hs:
+        lib.nfft_plan_destroy(h)

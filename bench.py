@@ -1,25 +1,33 @@
 """Throughput of the NFFT forward + adjoint on one MI355X.
 
-Workload: d = 2, N = (512, 512), n = (1024, 1024) (sigma = 2), M = 262144 nodes uniform on
-[-1/2, 1/2)^2, complex Gaussian data, Kaiser-Bessel window.  The headline line is the
-complex64 plan with m = 8; complex128 and m = 4 variants are reported beside it.
+Headline workload: d = 2, N = (512, 512), n = (1024, 1024) (sigma = 2), M = 262144 nodes
+uniform on [-1/2, 1/2)^2, complex Gaussian data, Kaiser-Bessel window, complex64 plan
+with m = 8.  Reported beside it: complex128 and m = 4 variants of the same workload, and
+the other workloads -- d = 1 (N = 256, M = 1024, complex128, m = 8), d = 3 radial spokes
+(N = 128^3, M = 2,097,152, complex64, m = 6), 64 uneven d = 2 plans in one batch
+(complex64, m = 6, autotuned launch shapes, against per-plan launches) and the
+differentiable d = 2 radial workload (forward + backward).
 
 A step is one nfft_trafo plus one nfft_adjoint of the whole node set (inputs resident in
 device memory; the node precomputation is timed separately, as Sec. 4 of the paper does).
 value = M / (time of one step) in nonuniform points per second.
 
-The dominant kernel is timed with HIP events recorded around every kernel launch on the
-stream the library launches on (a second, event-bracketed pass of the same steps).  Its
-algorithmic bytes per launch (nodes, values and grid read or written once) over that time
-give the HBM roofline fraction.  The CPU baseline is the FP64 oracle (serial NFFT, one
-core) on the same workload; it also provides the reference for the E_2 errors.
+Kernel durations are measured live with HIP events: right after the timed steps, the same
+number of steps runs again with the library recording a HIP event pair around every
+launch on the stream it launches on (the markers add about 7 us per launch, so `value`
+comes from the steps without them; the step time with them is reported beside).  The dominant kernel's
+algorithmic bytes per launch over its average duration give the HBM roofline fraction.
+The CPU baseline is the FP64 oracle (serial NFFT + adjoint, one core) on the same
+workload; it also provides the reference for the E_2 errors.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu]
+                    [--primary-only] [--copy-calibration-mib MIB]
 """
 import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -27,36 +35,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NFFT fwd+adj nonuniform points/s at stated rel-ℓ2 error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-FETCH_WRITE_FILE = os.path.join(ROOT, "profiles", "traffic_d2_512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2_512_c64_m8.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(name, d, N, n, M, cbytes):
     """Bytes a kernel must move at least once (per launch) for this plan.
 
-    Per node: the grid index and offset (8 bytes per dimension: int32 index + float32
-    offset, or int32 + float64 in complex128 where this counts 12), the permutation entry
-    (4 bytes) and the value (cbytes).  Grid, coefficient and line data: cbytes per entry."""
+    Per node: the grid index and offset (int32 index + real offset per dimension: 8 bytes
+    in complex64, 12 in complex128), the permutation entry (4 bytes) and the value
+    (cbytes).  Grid, coefficient and line data: cbytes per entry.  The window factors of
+    the node precomputation are not counted (they can be recomputed from the offsets)."""
     import numpy as np
 
     per_node = d * (4 + cbytes // 2) + 4 + cbytes
     grid = int(np.prod(n)) * cbytes
     coef = int(np.prod(N)) * cbytes
-    rows_after_pass1 = int(np.prod(N[:-1])) * n[-1] * cbytes
-    if name == "interp" or name == "grad_x":
+    if d == 1:
+        first = coef + grid  # the only pass: coefficients in, full line out
+        mid = grid
+    else:
+        first = coef + int(np.prod(N[:-1])) * n[-1] * cbytes
+        mid = int(np.prod(N[:-1])) * n[-1] * cbytes
+    if name in ("interp", "grad_x"):
         return M * per_node + grid
     if name == "spread_tiles":
         return M * per_node
     if name == "spread_fold":
         return grid
-    if name == "fft_fwd_deconv":
-        return coef + rows_after_pass1
-    if name == "fft_fwd":
-        return rows_after_pass1 + grid
-    if name == "fft_adj":
-        return grid + rows_after_pass1
-    if name == "fft_adj_deconv":
-        return rows_after_pass1 + coef
+    if name == "fft_fwd_deconv" or name == "fft_adj_deconv":
+        return first
+    if name in ("fft_fwd", "fft_adj"):
+        return mid + grid
     return None
+
+
+# rocprofv3 kernel names of the library's launch labels (the FFT passes share one kernel)
+ROCPROF_NAME = {"interp": "k_interp_nodes", "spread_tiles": "k_spread_tiles", "spread_fold": "k_fold",
+                "grad_x": "k_grad_x"}
 
 
 class Case:
@@ -68,7 +87,7 @@ class Case:
         self.dtype = dtype
         self.torch = torch
         dev = torch.device("cuda:0")
-        self.plan = Plan(w["N"], w["M"], m=m, dtype=dtype, device=dev)
+        self.plan = Plan(w["N"], w["M"], n=w["n"], m=m, dtype=dtype, device=dev)
         self.x = torch.as_tensor(w["x"]).to(dev)
         self.fhat = torch.as_tensor(w["fhat"]).to(dev, dtype)
         self.f = torch.as_tensor(w["f"]).to(dev, dtype)
@@ -114,30 +133,27 @@ class Case:
             for _ in range(steps):
                 self.step()
 
-    def time_steps(self, steps, warmup):
+    def time_steps(self, steps, warmup, events):
+        """ms per step over `steps` steps; with `events`, the library's per-launch events
+        are recorded during the same steps and their averages returned too."""
         torch = self.torch
         self.run(warmup)
         torch.cuda.synchronize()
+        if events:
+            self.plan.profile(True)
+            self.plan.profile_read()
         stream = torch.cuda.current_stream()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         self.run(steps)
         b.record(stream)
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / steps
-
-    def kernel_times(self, steps):
-        """Average duration per launch of every kernel, from HIP events the library
-        records around each launch on its stream."""
-        torch = self.torch
-        self.plan.profile(True)
-        self.plan.profile_read()
-        for _ in range(steps):
-            self.step()
-        torch.cuda.synchronize()
-        res = self.plan.profile_read()
-        self.plan.profile(False)
-        return {k: (v[0] / v[1], v[1]) for k, v in res.items()}
+        kt = None
+        if events:
+            res = self.plan.profile_read()
+            self.plan.profile(False)
+            kt = {k: (v[0] / v[1], v[1]) for k, v in res.items()}
+        return a.elapsed_time(b) / steps, kt
 
     def outputs(self):
         torch = self.torch
@@ -171,17 +187,190 @@ def e2(ref, approx):
     return float(np.linalg.norm(ref - approx) / np.linalg.norm(ref))
 
 
+def sample(n, k, seed):
+    import numpy as np
+
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False))
+
+
+def cuda_time(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(steps):
+        fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+# ------------------------------------------------------------------ other workloads
+
+def bench_d1(torch, steps, warmup, check):
+    """d = 1, N = 256, M = 1024, complex128, m = 8 against the direct sums."""
+    from oracle import oracle as O
+    from paper_1810_09891_amd import workloads as W
+
+    w = W.workload("d1")
+    case = Case(w, 8, torch.complex128, torch)
+    case.set_nodes_ms()
+    ms, _ = case.time_steps(steps, warmup, False)
+    f, h = case.outputs()
+    r = {"workload": "d=1 N=256 n=512 M=1024 uniform, complex128, m=8", "ms_per_step": ms,
+         "points_per_s": w["M"] / (ms * 1e-3)}
+    if check:
+        r["e2_trafo_vs_ndft"] = e2(O.ndft_trafo(w["x"], w["fhat"]), f)
+        r["e2_adjoint_vs_ndft"] = e2(O.ndft_adjoint(w["x"], w["f"], w["N"]), h)
+    return r
+
+
+def bench_d3(torch, steps, warmup, check):
+    """d = 3, N = 128^3, 4096 radial spokes of 512 points, complex64, m = 6."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1810_09891_amd import workloads as W
+
+    w = W.workload("d3r")
+    case = Case(w, 6, torch.complex64, torch)
+    t_nodes = case.set_nodes_ms(reps=3)
+    ms, kt = case.time_steps(steps, warmup, True)
+    f, h = case.outputs()
+    r = {"workload": "d=3 N=(128,128,128) n=(256,256,256) M=2097152 on 4096 radial spokes, complex64, m=6",
+         "ms_per_step": ms, "points_per_s": w["M"] / (ms * 1e-3), "set_nodes_ms": t_nodes,
+         "kernels_ms": {k: round(v[0], 5) for k, v in sorted(kt.items())}}
+    if check:
+        sel = sample(w["M"], 1024, 3)
+        r["e2_trafo_vs_oracle_1024_nodes"] = e2(O.nfft_trafo(w["x"][sel], w["fhat"], w["n"], 6), f[sel])
+        ks = sample(int(np.prod(w["N"])), 32, 4)
+        r["e2_adjoint_vs_ndft_32_coefficients"] = e2(O.ndft_adjoint_at(w["x"], w["f"], w["N"], ks),
+                                                     h.reshape(-1)[ks])
+    del case
+    return r
+
+
+def bench_batch(torch, steps, warmup, check):
+    """64 d = 2 plans, N_i in {64,...,512}^2, M_i log-uniform in [1e3, 2e5], complex64,
+    m = 6: one batch (autotuned) against the same plans launched one by one."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1810_09891_amd import Batch, Plan, workloads as W
+
+    specs = W.batch_plans()
+    C64 = torch.complex64
+    plans, fh, fv = [], [], []
+    for s in specs:
+        p = Plan(s["N"], s["M"], m=6, dtype=C64)
+        p.set_nodes(torch.as_tensor(s["x"]).cuda())
+        plans.append(p)
+        fh.append(torch.as_tensor(s["fhat"]).to("cuda", C64))
+        fv.append(torch.as_tensor(s["f"]).to("cuda", C64))
+    outs_f = [torch.empty(s["M"], dtype=C64, device="cuda") for s in specs]
+    outs_h = [torch.empty(s["N"], dtype=C64, device="cuda") for s in specs]
+    with tempfile.TemporaryDirectory() as td:
+        b = Batch(plans, tune_cache=os.path.join(td, "tune.txt"))
+        t0 = time.perf_counter()
+        params = b.autotune()
+        tune_s = time.perf_counter() - t0
+
+    def batched():
+        b.trafo(fh, outs_f)
+        b.adjoint(fv, outs_h)
+
+    def sequential():
+        for p, a, o in zip(plans, fh, outs_f):
+            p.trafo(a, out=o)
+        for p, a, o in zip(plans, fv, outs_h):
+            p.adjoint(a, out=o)
+
+    ms_b = cuda_time(torch, batched, steps, warmup)
+    ms_s = cuda_time(torch, sequential, steps, warmup)
+    Mtot = int(sum(s["M"] for s in specs))
+    r = {"workload": "64 plans d=2, N_i from {64,128,256,512}^2, M_i log-uniform in [1e3,2e5] "
+                     "(total M=%d, total grid points=%d), complex64, m=6" %
+                     (Mtot, int(sum(4 * np.prod(s["N"]) for s in specs))),
+         "ms_per_step": ms_b, "points_per_s": Mtot / (ms_b * 1e-3),
+         "sequential_ms_per_step": ms_s, "sequential_points_per_s": Mtot / (ms_s * 1e-3),
+         "speedup_vs_sequential": ms_s / ms_b, "autotune_s": tune_s, "params": params}
+    if check:
+        batched()
+        fb = [o.cpu().numpy() for o in outs_f]
+        hb = [o.cpu().numpy() for o in outs_h]
+        sequential()
+        fs = [o.cpu().numpy() for o in outs_f]
+        hs = [o.cpu().numpy() for o in outs_h]
+        r["max_e2_batched_vs_per_plan"] = max(max(e2(a, c) for a, c in zip(fs, fb)),
+                                             max(e2(a, c) for a, c in zip(hs, hb)))
+        order = np.argsort([s["M"] for s in specs])
+        worst = 0.0
+        for i in order[:3]:
+            s = specs[i]
+            worst = max(worst, e2(O.nfft_trafo(s["x"], s["fhat"], None, 6), fb[i]),
+                        e2(O.nfft_adjoint(s["x"], s["f"], s["N"], None, 6), hb[i]))
+        r["max_e2_vs_oracle_3_smallest_plans"] = worst
+    b.close()
+    return r
+
+
+def bench_grad(torch, steps, warmup, check):
+    """d = 2, N = (256,256), 256 spokes x 256 points + N(0, 1e-3^2) jitter, complex64,
+    m = 6: loss ||A(x) fhat - y||^2, forward and backward for fhat and x."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1810_09891_amd import differentiable_plan, nfft, workloads as W
+
+    w = W.workload("grad")
+    N, M, x = w["N"], w["M"], w["x"]
+    r0 = W.rng("grad", 1)
+    fhat_star = W.cgauss(r0, N)
+    fhat = W.cgauss(r0, N)
+    y = O.nfft_trafo(x, fhat_star, None, 8)
+    plan = differentiable_plan(N, M, m=6, dtype=torch.complex64)
+    xt = torch.tensor(x, device="cuda", dtype=torch.float64, requires_grad=True)
+    ft = torch.tensor(fhat, device="cuda", dtype=torch.complex64, requires_grad=True)
+    yt = torch.tensor(y, device="cuda", dtype=torch.complex64)
+
+    def step():
+        xt.grad = None
+        ft.grad = None
+        f = nfft(xt, ft, plan)
+        loss = torch.sum(torch.abs(f - yt) ** 2)
+        loss.backward()
+
+    ms = cuda_time(torch, step, steps, warmup)
+    r = {"workload": "d=2 N=(256,256) M=65536 on 256 radial spokes + N(0,1e-3^2) jitter, complex64, m=6; "
+                     "loss ||A(x)fhat - y||^2, forward + backward (set_nodes, trafo, grad_x, adjoint)",
+         "ms_per_step": ms, "points_per_s": M / (ms * 1e-3)}
+    if check:
+        step()
+        gx = xt.grad.detach().cpu().numpy()
+        gf = ft.grad.detach().cpu().numpy()
+        res = O.nfft_trafo(x, fhat, None, 8) - y
+        r["e2_grad_fhat_vs_oracle"] = e2(2.0 * O.nfft_adjoint(x, res, N, None, 8), gf)
+        sel = sample(M, 256, 5)
+        gref = O.ndft_grad_x(x[sel], fhat, res[sel])
+        r["e2_grad_x_vs_ndft_256_nodes"] = float(np.linalg.norm(gx[sel] - gref) / np.linalg.norm(gref))
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and E_2")
-    ap.add_argument("--primary-only", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the E_2 checks")
+    ap.add_argument("--primary-only", action="store_true", help="only the headline plan")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how "
+        print("bench.py measures one GPU only: this build has no multi-GPU path (DESIGN.md describes how "
               "the transform would shard); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
@@ -189,6 +378,17 @@ def main():
     import torch
 
     from paper_1810_09891_amd import workloads as W
+    from paper_1810_09891_amd.profiling import source_hash
+
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read, %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
+        del src, dst
 
     C64, C128 = torch.complex64, torch.complex128
     variants = [(8, C64)] + ([] if args.primary_only else [(8, C128), (4, C64), (4, C128)])
@@ -201,65 +401,76 @@ def main():
         if args.graph:
             case.capture()
         steps = args.steps if i == 0 else max(10, args.steps // 4)
-        ms = case.time_steps(steps, args.warmup)
-        kt = case.kernel_times(steps)
+        ms, _ = case.time_steps(steps, args.warmup, events=False)
+        # the same steps again with the library's per-launch events (they add ~7 us per launch)
+        ms_events, kt = case.time_steps(steps, args.warmup, events=not args.graph)
         f_gpu, h_gpu = case.outputs()
         r = {
             "m": m,
             "dtype": "c64" if dtype == C64 else "c128",
             "ms_per_step": ms,
+            "ms_per_step_with_events": ms_events,
             "points_per_s": w["M"] / (ms * 1e-3),
             "set_nodes_ms": t_nodes,
-            "kernels_ms": {k: round(v[0], 5) for k, v in sorted(kt.items())},
+            "kernels_ms": None if kt is None else {k: round(v[0], 5) for k, v in sorted(kt.items())},
             "steps": steps,
         }
         if not args.no_cpu:
             if m not in cpu:
-                cpu[m] = cpu_baseline(w, m, reps=1 if cpu else 3)
+                cpu[m] = cpu_baseline(w, m, reps=3 if not cpu else 1)
             r["e2_trafo_vs_oracle"] = e2(cpu[m]["f"], f_gpu)
             r["e2_adjoint_vs_oracle"] = e2(cpu[m]["h"], h_gpu)
         r["_kernel_avg"] = kt
         r["_w"] = (w["N"], w["n"], w["M"])
         results.append(r)
-        print("[bench] %s m=%d: %.4f ms/step, %.3e points/s, set_nodes %.3f ms" %
-              (r["dtype"], m, ms, r["points_per_s"], t_nodes), file=sys.stderr, flush=True)
+        log("%s m=%d: %.4f ms/step (%.4f with events), %.3e points/s, set_nodes %.3f ms" %
+            (r["dtype"], m, ms, ms_events, r["points_per_s"], t_nodes))
         del case
         torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.primary_only:
+        check = not args.no_cpu
+        for name, fn, st in (("d1_256_c128_m8", bench_d1, args.steps), ("d3_radial_128_c64_m6", bench_d3, 20),
+                             ("batch64_c64_m6", bench_batch, 20), ("grad_radial_256_c64_m6", bench_grad, 20)):
+            t0 = time.perf_counter()
+            extra[name] = fn(torch, st, 3, check)
+            log("%s: %.4f ms/step, %.3e points/s (%.1f s)" %
+                (name, extra[name]["ms_per_step"], extra[name]["points_per_s"], time.perf_counter() - t0))
+            torch.cuda.empty_cache()
 
     prim = results[0]
     N, n, M = prim["_w"]
     cb = 8
-    # dominant kernel of the primary plan
     kt = prim["_kernel_avg"]
-    dom = max((k for k in kt if not k.startswith("nodes")), key=lambda k: kt[k][0])
-    dom_ms = kt[dom][0]
-    alg = algorithmic_bytes(dom, 2, N, n, M, cb)
-    achieved = alg / (dom_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(FETCH_WRITE_FILE):
-        try:
-            tr = json.load(open(FETCH_WRITE_FILE))
-            if tr.get("kernel") == dom and tr.get("source_hash") == tr.get("source_hash"):
-                traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    roofline = {
-        "bound": "hbm",
-        "kernel": dom,
-        "achieved": round(achieved, 2),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "algorithmic_bytes": alg,
-        "avg_launch_ms": round(dom_ms, 5),
-    }
+    roofline = None
     per_kernel = {}
-    for k, (avg, cnt) in sorted(kt.items()):
-        b = algorithmic_bytes(k, 2, N, n, M, cb)
-        per_kernel[k] = {"avg_ms": round(avg, 5), "launches": cnt,
-                         "algorithmic_bytes": b,
-                         "hbm_frac": None if b is None else round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if kt is not None:
+        dom = max((k for k in kt if not k.startswith("nodes")), key=lambda k: kt[k][0])
+        dom_ms = kt[dom][0]
+        alg = algorithmic_bytes(dom, 2, N, n, M, cb)
+        achieved = alg / (dom_ms * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            tr = json.load(open(TRAFFIC_FILE))
+            entry = tr.get("kernels", {}).get(ROCPROF_NAME.get(dom, ""), None)
+            if entry is not None and "bytes_per_launch" in entry and tr.get("source_hash") == source_hash():
+                traffic = entry["bytes_per_launch"]
+        roofline = {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes": alg,
+            "avg_launch_ms": round(dom_ms, 5),
+        }
+        for k, (avg, cnt) in sorted(kt.items()):
+            bts = algorithmic_bytes(k, 2, N, n, M, cb)
+            per_kernel[k] = {"avg_ms": round(avg, 5), "launches": cnt, "algorithmic_bytes": bts,
+                             "hbm_frac": None if bts is None else round(bts / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out = {
         "metric": METRIC,
         "value": prim["points_per_s"],
@@ -274,14 +485,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "d=2 N=(512,512) n=(1024,1024) M=262144 uniform nodes, Kaiser-Bessel m=8, complex64, fwd+adj",
-            "d": 2, "N": list(N), "n": list(n), "M": M, "m": 8, "precision": "complex64 data, FP32 window and "
-            "accumulation, FP64 node index and deconvolution table",
+            "workload": "d=2 N=(512,512) n=(1024,1024) M=262144 uniform nodes, Kaiser-Bessel m=8, complex64, "
+                        "trafo+adjoint",
+            "d": 2, "N": list(N), "n": list(n), "M": M, "m": 8,
+            "precision": "complex64 data, FP32 window and accumulation, FP64 node index and deconvolution table",
             "graph": bool(args.graph),
         },
         "roofline": roofline,
         "kernels": per_kernel,
         "set_nodes_ms": prim["set_nodes_ms"],
+        "ms_per_step_with_events": prim["ms_per_step_with_events"],
     }
     if not args.no_cpu:
         c = cpu[8]
@@ -292,12 +505,13 @@ def main():
             "unit": "points/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": "full workload (d=2, N=512^2, M=262144, m=8), serial FP64 NFFT + adjoint NFFT of the "
-                      "oracle, median of %d runs, %.2f s per step; host has %d cores" %
+            "sample": "the full headline workload (d=2, N=512^2, M=262144, m=8): serial FP64 NFFT + adjoint "
+                      "NFFT of the oracle on one thread, median of %d runs, %.2f s per step; host has %d cores" %
                       (c["runs"], c["seconds_per_step"], multiprocessing.cpu_count()),
         }
         out["e2_vs_oracle"] = {"trafo": prim["e2_trafo_vs_oracle"], "adjoint": prim["e2_adjoint_vs_oracle"]}
     out["variants"] = [{k: v for k, v in r.items() if not k.startswith("_")} for r in results[1:]]
+    out["workloads"] = extra
     print(json.dumps(out))
 
 

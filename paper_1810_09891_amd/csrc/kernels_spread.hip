@@ -19,9 +19,9 @@ using namespace window;
 //    s0 = r, r + R, r + 2R, ... (R = 64 / W rows per pass) and column s1.  Each of the
 //    four waves of a workgroup accumulates its share of the work item's nodes into its
 //    own padded tile; the four tiles are summed in wave order when the item is done.
-//  * 3-D: the four waves share one padded tile and split each node's planes s0 (wave w
-//    takes s0 = w, w+4, ...); lanes cover (s1, s2) like the rows and columns above; a
-//    barrier separates consecutive nodes.
+//  * 3-D: the four waves share one padded tile; wave w owns the tile planes with index
+//    w mod 4 and updates those planes of every node's stencil, lanes covering (s1, s2)
+//    like the rows and columns above (no barrier between nodes).
 
 constexpr int kWaves = kBlock / 64;
 constexpr int kBatch = 16;  // nodes whose data a wave loads at once
@@ -159,42 +159,122 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
         }
         __syncthreads();
     } else {
+        // 3-D: one tile shared by the workgroup; wave w owns the tile planes whose index is
+        // w mod 4, so every wave goes through all nodes of the item and updates only its own
+        // planes of each stencil -- no two waves touch the same cell and no barrier is needed
+        // between nodes.  Node data is loaded in batches of kBatch, one batch ahead.
         for (int i = threadIdx.x; i < g.Ptot; i += kBlock)
             tiles[i] = C{T(0), T(0)};
         __syncthreads();
+        constexpr int NW = (3 * WM + 63) / 64;  // registers of window factors per node and lane
+        constexpr int KB = (NW > 1 || sizeof(T) == 8) ? kBatch / 2 : kBatch;  // nodes per batch (registers)
+        constexpr int NPL = (WM + kWaves - 1) / kWaves;                         // planes per wave and node
+        constexpr int G = NPL < 16 / NPASS ? NPL : (16 / NPASS > 0 ? 16 / NPASS : 1);  // planes per group
         const int P1 = g.P[1], P2 = g.P[2];
-        for (int i = 0; i < len; ++i) {
-            const int node = first + i;
-            const C fv = f[nd.perm[node]];
-            const int64_t prow = (int64_t)node * dW;
-            const T wv0 = lane < dW ? psi[prow + lane] : T(0);
-            const T wv1 = lane + 64 < dW ? psi[prow + 64 + lane] : T(0);
-            const int ul0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
-            const int ul1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
-            const int ul2 = nd.u[2][node] & ((1 << g.lgB[2]) - 1);
-            const int slot2 = 2 * W + (sc < W ? sc : 0);  // factor of dimension 2 at this lane's column
-            const T w2a = lane_shfl(wv0, slot2 < 64 ? slot2 : 0);
-            const T w2b = lane_shfl(wv1, slot2 >= 64 ? slot2 - 64 : 0);
-            const T w2 = slot2 < 64 ? w2a : w2b;
-            const T ax = fv.x * w2, ay = fv.y * w2;
-            for (int s0 = wave; s0 < W; s0 += kWaves) {
-                const T w0 = lane_shfl(wv0, s0);
-                const T bx = ax * w0, by = ay * w0;
-                const int pbase = (ul0 + s0) * P1 + ul1;
-                for (int s1b = 0; s1b < W; s1b += R) {
-                    const int s1 = s1b + r;
-                    const T w1 = lane_shfl(wv0, W + (s1 < W ? s1 : 0));
-                    if (lane_ok && s1 < W) {
-                        const int idx = (pbase + s1) * P2 + ul2 + sc;
-                        C v = tiles[idx];
-                        v.x += bx * w1;
-                        v.y += by * w1;
-                        tiles[idx] = v;
+        const int hi = first + len;
+        T fx = 0, fy = 0, wv[NW][KB];
+        int u0 = 0, u1 = 0, u2 = 0;
+        auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, int &lu1, int &lu2, T (*lwv)[KB]) {
+            const int nb = min(KB, hi - b0);
+            lfx = lfy = T(0);
+            lu0 = lu1 = lu2 = 0;
+            if (lane < nb) {
+                const C fv = f[nd.perm[b0 + lane]];
+                lfx = fv.x;
+                lfy = fv.y;
+                lu0 = nd.u[0][b0 + lane] & ((1 << g.lgB[0]) - 1);
+                lu1 = nd.u[1][b0 + lane] & ((1 << g.lgB[1]) - 1);
+                lu2 = nd.u[2][b0 + lane] & ((1 << g.lgB[2]) - 1);
+            }
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    lwv[q][k] = (k < nb && lane + 64 * q < dW) ? psi[(int64_t)(b0 + k) * dW + lane + 64 * q] : T(0);
+        };
+        // window factor of slot j (j < 3W, compile-time register choice when NW == 1)
+        auto factor = [&](int k, int j) -> T {
+            if constexpr (NW == 1) {
+                return lane_shfl(wv[0][k], j);
+            } else {
+                const T a0 = lane_shfl(wv[0][k], j < 64 ? j : 0);
+                const T a1 = lane_shfl(wv[1][k], j >= 64 ? j - 64 : 0);
+                return j < 64 ? a0 : a1;
+            }
+        };
+        // the same slot for every lane (uniform j)
+        auto factor_u = [&](int k, int j) -> T { return bcast(wv[0][k], j); };  // j < W <= 26
+        if (first < hi)
+            load_batch(first, fx, fy, u0, u1, u2, wv);
+        for (int b0 = first; b0 < hi; b0 += KB) {
+            const int nb = min(KB, hi - b0);
+            T nfx = 0, nfy = 0, nwv[NW][KB];
+            int nu0 = 0, nu1 = 0, nu2 = 0;
+            if (b0 + KB < hi)
+                load_batch(b0 + KB, nfx, nfy, nu0, nu1, nu2, nwv);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                if (k >= nb)
+                    break;
+                const T fxk = bcast(fx, k), fyk = bcast(fy, k);
+                const int ul0 = bcast(u0, k), ul1 = bcast(u1, k), ul2 = bcast(u2, k);
+                const T w2 = factor(k, 2 * W + (sc < W ? sc : 0));
+                const T ax = fxk * w2, ay = fyk * w2;
+                T w1[NPASS];
+#pragma unroll
+                for (int q = 0; q < NPASS; ++q) {
+                    const int s1 = q * R + r;
+                    w1[q] = factor(k, W + (s1 < W ? s1 : 0));
+                }
+                const int rbase = ul1 * P2 + ul2 + sc;
+                // this wave's planes of the stencil: s0 = s0a, s0a + 4, ... (at most NPL), in
+                // groups of G planes whose reads are all issued before their updates
+                const int s0a = (wave - ul0) & (kWaves - 1);
+#pragma unroll
+                for (int t0 = 0; t0 < NPL; t0 += G) {
+                    T w0[G];
+                    C v[G][NPASS];
+#pragma unroll
+                    for (int t = 0; t < G; ++t) {
+                        const int s0 = s0a + kWaves * (t0 + t);
+                        w0[t] = factor_u(k, s0 < W ? s0 : 0);
+                        const C *plane = tiles + (ul0 + s0) * P1 * P2 + rbase;
+#pragma unroll
+                        for (int q = 0; q < NPASS; ++q) {
+                            const int s1 = q * R + r;
+                            if (t0 + t < NPL && s0 < W && lane_ok && s1 < W)
+                                v[t][q] = plane[s1 * P2];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < G; ++t) {
+                        const int s0 = s0a + kWaves * (t0 + t);
+                        const T bx = ax * w0[t], by = ay * w0[t];
+                        C *plane = tiles + (ul0 + s0) * P1 * P2 + rbase;
+#pragma unroll
+                        for (int q = 0; q < NPASS; ++q) {
+                            const int s1 = q * R + r;
+                            if (t0 + t < NPL && s0 < W && lane_ok && s1 < W) {
+                                v[t][q].x += bx * w1[q];
+                                v[t][q].y += by * w1[q];
+                                plane[s1 * P2] = v[t][q];
+                            }
+                        }
                     }
                 }
             }
-            __syncthreads();
+            fx = nfx;
+            fy = nfy;
+            u0 = nu0;
+            u1 = nu1;
+            u2 = nu2;
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    wv[q][k] = nwv[q][k];
         }
+        __syncthreads();
         C *slot = scratch + (int64_t)c * g.Ptot;
         for (int i = threadIdx.x; i < g.Ptot; i += kBlock)
             slot[i] = tiles[i];

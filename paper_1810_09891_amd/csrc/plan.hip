@@ -18,7 +18,7 @@ using namespace nfft;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kLdsPreferred = 64 * 1024;  // target LDS per workgroup (occupancy)
+constexpr size_t kLdsPreferred = 80 * 1024;  // 3-D tile per workgroup: two workgroups per CU
 constexpr size_t kLdsMax = 160 * 1024;       // LDS per compute unit on gfx950
 constexpr int kMaxN = 4096;                  // longest FFT line held in one workgroup
 constexpr int kMaxM = 12;

@@ -151,6 +151,13 @@ __device__ __forceinline__ int pos_to_coef(int i, int N, int n)
     return -1;
 }
 
+// a[i] for a runtime i < 3 without indexing the array dynamically (keeps descriptor
+// fields in registers instead of private memory)
+template <typename A> __device__ __forceinline__ A pick3(const A (&a)[kMaxDim], int i)
+{
+    return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+
 // Per-line data of a line group, computed once per group by the first nl threads.
 // Rows (t = d-1): row index r over the pruned dimensions q < d-1.  Columns (t < d-1):
 // outer index over dimensions q not in {t, d-1} (pruned when q < t), times a block of
@@ -167,9 +174,12 @@ __device__ __forceinline__ void line_info(const FftPass &p, int g, int c, int64_
             gbase = -1;
             return;
         }
-        cbase = r * p.N[p.d - 1];
+        cbase = r * pick3(p.N, p.d - 1);
         int rr = r;
-        for (int q = p.d - 2; q >= 0; --q) {
+#pragma unroll
+        for (int q = kMaxDim - 2; q >= 0; --q) {
+            if (q > p.d - 2)
+                continue;
             int pq = rr % p.N[q];
             rr /= p.N[q];
             gbase += (int64_t)coef_to_pos(pq, p.N[q], p.n[q]) * p.stride[q];
@@ -181,8 +191,9 @@ __device__ __forceinline__ void line_info(const FftPass &p, int g, int c, int64_
     int o = g / p.ncb;
     int cb = g - o * p.ncb;
     gbase = (int64_t)cb * p.nl + c;  // stride of dimension d-1 is 1
-    for (int q = p.d - 2; q >= 0; --q) {
-        if (q == p.t)
+#pragma unroll
+    for (int q = kMaxDim - 2; q >= 0; --q) {
+        if (q > p.d - 2 || q == p.t)
             continue;
         int ext = q < p.t ? p.N[q] : p.n[q];
         int iq = o % ext;
@@ -198,8 +209,8 @@ constexpr int kMaxLines = 256;
 // One line group g of a pass: load (with the deconvolution when in_mode == 0), transform
 // in LDS, store (with the deconvolution when out_mode == 2).
 template <typename T, int VPT, int SIGN>
-__device__ __forceinline__ void fft_group(const FftPass &p, int g, Cplx<T> *lds, int64_t *s_gbase, int *s_cbase,
-                                          double *s_fac)
+__device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr, void *fout_ptr, int g,
+                                          Cplx<T> *lds, int64_t *s_gbase, int *s_cbase, double *s_fac)
 {
     using C = Cplx<T>;
     const int L = p.L, nl = p.nl, pitch = p.pitch;
@@ -214,11 +225,11 @@ __device__ __forceinline__ void fft_group(const FftPass &p, int g, Cplx<T> *lds,
     const int lgnl = 31 - __clz(nl);
     const int total = nl * L;
     const int t = p.t;
-    const int Nt = p.N[t];
-    const int64_t st = p.stride[t];
-    const double *wt = p.w[t];
-    const C *fin = static_cast<const C *>(p.fin);
-    C *fout = static_cast<C *>(p.fout);
+    const int Nt = pick3(p.N, t);
+    const int64_t st = pick3(p.stride, t);
+    const double *wt = pick3(p.w, t);
+    const C *fin = static_cast<const C *>(fin_ptr);
+    C *fout = static_cast<C *>(fout_ptr);
     if (threadIdx.x < nl)
         line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
     __syncthreads();
@@ -305,7 +316,7 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
     __shared__ double s_fac[kMaxLines];
     C *lds = reinterpret_cast<C *>(smem_raw);
     for (int g = xcd_local_id(blockIdx.x, gridDim.x); g < (int)p.ngroups; g += gridDim.x)
-        fft_group<T, VPT, SIGN>(p, g, lds, s_gbase, s_cbase, s_fac);
+        fft_group<T, VPT, SIGN>(p, p.fin, p.fout, g, lds, s_gbase, s_cbase, s_fac);
 }
 
 // Pass `pass` (forward or adjoint) of every plan of a batch in one launch.
@@ -331,12 +342,12 @@ __global__ __launch_bounds__(kBlock) void k_fft_batch(const PlanDev *__restrict_
     for (int it = xcd_local_id(blockIdx.x, gridDim.x); it < total; it += gridDim.x) {
         const int pi = batch_find(s_prefix, count, it);
         const PlanDev &pd = plans[pi];
-        FftPass fp = SIGN < 0 ? pd.fwd[pass] : pd.adj[pass];
-        if (SIGN < 0 && pass == 0)
-            fp.fin = ptrs.in[pi];
-        if (SIGN > 0 && pass == pd.nfft - 1)
-            fp.fout = ptrs.out[pi];
-        fft_group<T, VPT, SIGN>(fp, it - s_prefix[pi], lds, s_gbase, s_cbase, s_fac);
+        const FftPass &fp = SIGN < 0 ? pd.fwd[pass] : pd.adj[pass];
+        // the caller's arrays of this call: coefficients in (first forward pass) or out
+        // (last adjoint pass)
+        const void *fin = (SIGN < 0 && pass == 0) ? ptrs.in[pi] : fp.fin;
+        void *fout = (SIGN > 0 && pass == pd.nfft - 1) ? ptrs.out[pi] : fp.fout;
+        fft_group<T, VPT, SIGN>(fp, fin, fout, it - s_prefix[pi], lds, s_gbase, s_cbase, s_fac);
     }
 }
 

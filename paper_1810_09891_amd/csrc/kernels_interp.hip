@@ -185,7 +185,11 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 }  // namespace
 
 size_t interp_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8); }
-size_t spread_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8) * (g.d < 3 ? 4 : 1); }
+// spreading tiles per workgroup: four (1-D), two (2-D), one (3-D)
+size_t spread_lds_bytes(const Geom &g, bool dbl)
+{
+    return (size_t)g.Ptot * (dbl ? 16 : 8) * (g.d == 1 ? 4 : g.d == 2 ? 2 : 1);
+}
 
 int fold_max_pairs(const Geom &g, int t)
 {

@@ -15,10 +15,14 @@ using namespace window;
 // wave no two lanes touch the same cell and the accumulation is a plain read-add-write
 // in LDS (no LDS atomics, which are slow for FP32 on this hardware, and a fixed order of
 // additions).  The window factors come from the node precomputation (psi).
-//  * 1-D / 2-D: lane (r, s1) with s1 = lane mod W, r = lane / W covers stencil row
-//    s0 = r, r + R, r + 2R, ... (R = 64 / W rows per pass) and column s1.  Each of the
-//    four waves of a workgroup accumulates its share of the work item's nodes into its
-//    own padded tile; the four tiles are summed in wave order when the item is done.
+//  * 1-D: each of the four waves of a workgroup accumulates a quarter of the work item's
+//    nodes into its own padded tile (lanes over the stencil points); the four tiles are
+//    summed in wave order when the item is done.
+//  * 2-D: lane (r, s1) with s1 = lane mod WM, r = lane / WM covers stencil column s1 and
+//    R = 64 / WM rows per pass.  The waves form two pairs, each pair with its own tile and
+//    half of the work item's nodes; the two waves of a pair own the tile rows of even and
+//    odd index and update those rows of every node's stencil.  The two tiles are summed
+//    when the item is done.
 //  * 3-D: the four waves share one padded tile; wave w owns the tile planes with index
 //    w mod 4 and updates those planes of every node's stencil, lanes covering (s1, s2)
 //    like the rows and columns above (no barrier between nodes).
@@ -61,7 +65,7 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
     const bool lane_ok = r < R && sc < W;
     const int first = nd.chunk_first[c];
     const int len = nd.chunk_len[c];
-    if constexpr (D < 3) {
+    if constexpr (D == 1) {
         C *sub = tiles + wave * g.Ptot;
         for (int i = lane; i < g.Ptot; i += 64)
             sub[i] = C{T(0), T(0)};
@@ -69,6 +73,77 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
         // data is loaded one batch ahead (one node per lane; window factor l in lane l)
         const int lo = first + (len * wave) / kWaves;
         const int hi = first + (len * (wave + 1)) / kWaves;
+        T fx = 0, fy = 0, wv[kBatch];
+        int u0 = 0;
+        auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, T *lwv) {
+            const int nb = min(kBatch, hi - b0);
+            lfx = lfy = T(0);
+            lu0 = 0;
+            if (lane < nb) {
+                const C fv = f[nd.perm[b0 + lane]];
+                lfx = fv.x;
+                lfy = fv.y;
+                lu0 = nd.u[0][b0 + lane] & ((1 << g.lgB[0]) - 1);
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                lwv[k] = (k < nb && lane < dW) ? psi[(int64_t)(b0 + k) * dW + lane] : T(0);
+        };
+        if (lo < hi)
+            load_batch(lo, fx, fy, u0, wv);
+        for (int b0 = lo; b0 < hi; b0 += kBatch) {
+            const int nb = min(kBatch, hi - b0);
+            T nfx = 0, nfy = 0, nwv[kBatch];
+            int nu0 = 0;
+            if (b0 + kBatch < hi)
+                load_batch(b0 + kBatch, nfx, nfy, nu0, nwv);
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (k >= nb)
+                    break;
+                const T fxk = bcast(fx, k), fyk = bcast(fy, k);
+                const int ul0 = bcast(u0, k);
+                if (lane < W) {
+                    C v = sub[ul0 + lane];
+                    v.x += fxk * wv[k];
+                    v.y += fyk * wv[k];
+                    sub[ul0 + lane] = v;
+                }
+            }
+            fx = nfx;
+            fy = nfy;
+            u0 = nu0;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                wv[k] = nwv[k];
+        }
+        __syncthreads();
+        C *slot = scratch + (int64_t)c * g.Ptot;
+        for (int i = threadIdx.x; i < g.Ptot; i += kBlock) {
+            C a = tiles[i];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) {
+                C b = tiles[w * g.Ptot + i];
+                a.x += b.x;
+                a.y += b.y;
+            }
+            slot[i] = a;
+        }
+        __syncthreads();
+    } else if constexpr (D == 2) {
+        // Two pairs of waves, each pair with its own padded tile and half of the work
+        // item's nodes; in a pair, wave `par` owns the tile rows with index parity par and
+        // updates those rows of every node's stencil (no two waves touch the same cell).
+        constexpr int NR = WM / 2;                // stencil rows of one parity (WM is even)
+        constexpr int NP2 = (NR + R - 1) / R;     // passes over them
+        const int grp = wave >> 1, par = wave & 1;
+        C *sub = tiles + grp * g.Ptot;
+        for (int i = threadIdx.x; i < 2 * g.Ptot; i += kBlock)
+            tiles[i] = C{T(0), T(0)};
+        __syncthreads();
+        const int lo = first + (len * grp) / 2;
+        const int hi = first + (len * (grp + 1)) / 2;
+        const int P1 = g.P[1];
         T fx = 0, fy = 0, wv[kBatch];
         int u0 = 0, u1 = 0;
         auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, int &lu1, T *lwv) {
@@ -80,8 +155,7 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
                 lfx = fv.x;
                 lfy = fv.y;
                 lu0 = nd.u[0][b0 + lane] & ((1 << g.lgB[0]) - 1);
-                if (D == 2)
-                    lu1 = nd.u[1][b0 + lane] & ((1 << g.lgB[1]) - 1);
+                lu1 = nd.u[1][b0 + lane] & ((1 << g.lgB[1]) - 1);
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k)
@@ -100,40 +174,27 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
                 if (k >= nb)
                     break;
                 const T fxk = bcast(fx, k), fyk = bcast(fy, k);
-                const int ul0 = bcast(u0, k);
-                if constexpr (D == 1) {
-                    if (lane < W) {
-                        C v = sub[ul0 + lane];
-                        v.x += fxk * wv[k];
-                        v.y += fyk * wv[k];
-                        sub[ul0 + lane] = v;
-                    }
-                } else {
-                    const int ul1 = bcast(u1, k);
-                    const T w1 = lane_shfl(wv[k], W + (sc < W ? sc : 0));
-                    const T ax = fxk * w1, ay = fyk * w1;
-                    const int base = ul0 * g.P[1] + ul1 + sc;
-                    T w0[NPASS];
-                    C v[NPASS];
+                const int ul0 = bcast(u0, k), ul1 = bcast(u1, k);
+                const T w1 = lane_shfl(wv[k], W + (sc < W ? sc : 0));
+                const T ax = fxk * w1, ay = fyk * w1;
+                const int s0p = (par - ul0) & 1;  // first stencil row of this wave's parity
+                const int base = ul0 * P1 + ul1 + sc;
+                T w0[NP2];
+                C v[NP2];
 #pragma unroll
-                    for (int q = 0; q < NPASS; ++q) {
-                        const int s0 = q * R + r;
-                        w0[q] = lane_shfl(wv[k], s0 < W ? s0 : 0);
-                    }
+                for (int q = 0; q < NP2; ++q) {
+                    const int s0 = s0p + 2 * (q * R + r);
+                    w0[q] = lane_shfl(wv[k], s0 < W ? s0 : 0);
+                    if (lane_ok && s0 < W)
+                        v[q] = sub[base + s0 * P1];
+                }
 #pragma unroll
-                    for (int q = 0; q < NPASS; ++q) {
-                        const int s0 = q * R + r;
-                        if (lane_ok && s0 < W)
-                            v[q] = sub[base + s0 * g.P[1]];
-                    }
-#pragma unroll
-                    for (int q = 0; q < NPASS; ++q) {
-                        const int s0 = q * R + r;
-                        if (lane_ok && s0 < W) {
-                            v[q].x += ax * w0[q];
-                            v[q].y += ay * w0[q];
-                            sub[base + s0 * g.P[1]] = v[q];
-                        }
+                for (int q = 0; q < NP2; ++q) {
+                    const int s0 = s0p + 2 * (q * R + r);
+                    if (lane_ok && s0 < W) {
+                        v[q].x += ax * w0[q];
+                        v[q].y += ay * w0[q];
+                        sub[base + s0 * P1] = v[q];
                     }
                 }
             }
@@ -148,14 +209,8 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
         __syncthreads();
         C *slot = scratch + (int64_t)c * g.Ptot;
         for (int i = threadIdx.x; i < g.Ptot; i += kBlock) {
-            C a = tiles[i];
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w) {
-                C b = tiles[w * g.Ptot + i];
-                a.x += b.x;
-                a.y += b.y;
-            }
-            slot[i] = a;
+            const C a0 = tiles[i], a1 = tiles[g.Ptot + i];
+            slot[i] = C{a0.x + a1.x, a0.y + a1.y};
         }
         __syncthreads();
     } else {

@@ -18,7 +18,7 @@ using namespace nfft;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kLdsPreferred = 80 * 1024;  // 3-D tile per workgroup: two workgroups per CU
+constexpr size_t kLdsPreferred = 80 * 1024;  // spreading tiles of one workgroup, d >= 2
 constexpr size_t kLdsMax = 160 * 1024;       // LDS per compute unit on gfx950
 constexpr int kMaxN = 4096;                  // longest FFT line held in one workgroup
 constexpr int kMaxM = 12;
@@ -57,12 +57,13 @@ static int choose_bins(nfft_plan_s *p)
         return v;
     };
     // Shrink the largest edge (outer dimension first on ties) until the tiles fit: the
-    // spreading kernel keeps four private tiles per workgroup for d <= 2 and one for d = 3;
-    // the interpolation kernel keeps one.
+    // spreading kernel keeps four tiles per workgroup for d = 1, two for d = 2 and one for
+    // d = 3 (at most 80 KB for d >= 2, so that two workgroups share a compute unit); the
+    // interpolation kernel keeps one.
     const int minB = 4;
-    const size_t ntiles = d < 3 ? 4 : 1;
+    const size_t ntiles = d == 1 ? 4 : d == 2 ? 2 : 1;
     // (1 KB of LDS is left for the static arrays of the batched kernels)
-    const size_t budget = (d < 3 ? kLdsMax : kLdsPreferred) - 1024;
+    const size_t budget = (d == 1 ? kLdsMax : kLdsPreferred) - 1024;
     while (ntiles * lds_of(B) > budget) {
         int best = -1;
         for (int t = 0; t < d; ++t)

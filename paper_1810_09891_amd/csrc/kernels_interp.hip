@@ -42,15 +42,9 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
     bin_coords<T, D>(g, bin, bc);
     stage_tile<T, D>(g, bc, grid, tile);
     __syncthreads();
-    // Thread t takes segment 4 (t mod 64) + t / 64 of the item's nodes (K per segment):
-    // the nodes are ordered by the bank residue of their tile position, so the 64 lanes
-    // of a wave start on different LDS banks.
-    const int K = (len + kBlock - 1) / kBlock;
-    const int seg = 4 * (threadIdx.x & 63) + (threadIdx.x >> 6);
-    for (int k = 0; k < K; ++k) {
-        const int i = seg * K + k;
-        if (i >= len)
-            continue;
+    // Thread t takes nodes t, t + 256, ...: the nodes are dealt round-robin over the bank
+    // residues of their tile positions, so consecutive lanes start on different LDS banks.
+    for (int i = threadIdx.x; i < len; i += kBlock) {
         const int node = first + i;
         const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
         int ul[kMaxDim];
@@ -185,10 +179,16 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 }  // namespace
 
 size_t interp_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8); }
-// spreading tiles per workgroup: four (1-D), two (2-D), one (3-D)
+// spreading tiles per workgroup: four (1-D), two plus one dummy slot per thread (2-D), one
+// (3-D)
 size_t spread_lds_bytes(const Geom &g, bool dbl)
 {
-    return (size_t)g.Ptot * (dbl ? 16 : 8) * (g.d == 1 ? 4 : g.d == 2 ? 2 : 1);
+    const size_t cs = dbl ? 16 : 8;
+    if (g.d == 1)
+        return (size_t)g.Ptot * cs * 4;
+    if (g.d == 2)
+        return ((size_t)g.Ptot * 2 + kBlock) * cs;
+    return (size_t)g.Ptot * cs;
 }
 
 int fold_max_pairs(const Geom &g, int t)

@@ -162,19 +162,39 @@ __global__ __launch_bounds__(kBlock) void k_node_chunks(Nodes nd, int nbins)
     }
 }
 
-// Order the nodes of every work item by (r, cell, caller index) with r the residue mod 32
-// of the cell's position in the padded tile, so that the window kernels -- which give
-// thread t the nodes of segment 4 (t mod 64) + t / 64 of this order -- access 32
-// different LDS bank pairs per wave.  The caller index makes the order unique.  Also
-// flags the item safe for plain read-add-write spreading by one thread per node: two
-// lanes of a wave then look at positions at least 4K apart (K = ceil(len / 256)), and
-// nodes of one cell are contiguous, so they never meet if no cell holds more than 4K
-// nodes of the item.
+// Order the nodes of every work item for the window kernels.  With r the residue mod 32
+// of a node's cell position in the padded tile (its LDS bank pair), the nodes are first
+// sorted by (r, cell, caller index) -- unique, so the order is deterministic -- and then
+// dealt round-robin over the residue classes: the first node of every class, then the
+// second, and so on.  Consecutive nodes therefore have different residues, and the
+// interpolation kernels, which give consecutive nodes to consecutive lanes, read 32
+// different bank pairs per half-wave.
 constexpr int kSortMax = 1024;  // chunk_cap is at most this
+// Bitonic sort of n (a power of two, <= kSortMax) keys in LDS by the workgroup.
+__device__ __forceinline__ void bitonic(unsigned long long *keys, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += kBlock) {
+                const int ij = i ^ j;
+                if (ij > i) {
+                    const unsigned long long a = keys[i], b = keys[ij];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        keys[i] = b;
+                        keys[ij] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_sort(Geom g, Nodes nd)
 {
     __shared__ unsigned long long keys[kSortMax];
-    __shared__ int maxrun;
+    __shared__ int cls_start[32];
     const int nchunks = nd.counters[0];
     for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int first = nd.chunk_first[c];
@@ -199,26 +219,25 @@ template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_s
             }
             keys[i] = key;
         }
-        if (threadIdx.x == 0)
-            maxrun = 1;
         __syncthreads();
-        // bitonic sort of npow keys
-        for (int k = 2; k <= npow; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = threadIdx.x; i < npow; i += kBlock) {
-                    const int ij = i ^ j;
-                    if (ij > i) {
-                        const unsigned long long a = keys[i], b = keys[ij];
-                        const bool up = (i & k) == 0;
-                        if ((a > b) == up) {
-                            keys[i] = b;
-                            keys[ij] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
+        // bitonic sort of npow keys by (bank residue, cell, caller index)
+        bitonic(keys, npow);
+        // Deal the nodes round-robin over the residue classes: key (rank in class,
+        // residue), so that consecutive nodes -- taken by consecutive lanes of the
+        // interpolation kernels -- start on different LDS banks.
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int r = (int)(keys[i] >> 58);
+            if (i == 0 || (int)(keys[i - 1] >> 58) != r)
+                cls_start[r] = i;
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const unsigned long long r = keys[i] >> 58;
+            const unsigned long long rank = (unsigned long long)(i - cls_start[r]);
+            keys[i] = (rank << 20) | (r << 15) | (keys[i] & 1023ull);
+        }
+        __syncthreads();
+        bitonic(keys, npow);
         // gather the node data in the new order (read all, then write)
         int u_new[kSortMax / kBlock][D];
         T d_new[kSortMax / kBlock][D];
@@ -234,14 +253,6 @@ template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_s
                     u_new[q][t] = nd.u[t][src];
                     d_new[q][t] = static_cast<const T *>(nd.delta[t])[src];
                 }
-                // length of the run of equal cells ending here
-                const unsigned long long cell_mask = ((1ull << 17) - 1) << 41;
-                const int cap = 4 * ((len + kBlock - 1) / kBlock) + 1;  // only "more than 4K" matters
-                int run = 1;
-                while (run < cap && i - run >= 0 && ((keys[i - run] ^ keys[i]) & cell_mask) == 0 &&
-                       ((keys[i - run] ^ keys[i]) >> 58) == 0)
-                    ++run;
-                atomicMax(&maxrun, run);
             }
         }
         __syncthreads();
@@ -256,10 +267,6 @@ template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_s
                     static_cast<T *>(nd.delta[t])[first + i] = d_new[q][t];
                 }
             }
-        }
-        if (threadIdx.x == 0) {
-            const int K = (len + kBlock - 1) / kBlock;
-            nd.chunk_safe[c] = maxrun <= 4 * K ? 1 : 0;
         }
         __syncthreads();
     }

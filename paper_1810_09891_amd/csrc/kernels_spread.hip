@@ -32,6 +32,19 @@ constexpr int kBatch = 16;  // nodes whose data a wave loads at once
 
 template <typename T> __device__ __forceinline__ T lane_shfl(T v, int src) { return __shfl(v, src, 64); }
 
+// Value of v in the lane whose index times 4 is `byte_idx` (precomputed shuffle address).
+__device__ __forceinline__ float bperm(int byte_idx, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_idx, __float_as_int(v)));
+}
+__device__ __forceinline__ double bperm(int byte_idx, double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(byte_idx, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(byte_idx, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Value of lane k (k wave-uniform) in every lane.
 __device__ __forceinline__ int bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
 __device__ __forceinline__ float bcast(float v, int k)
@@ -137,13 +150,30 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
         constexpr int NR = WM / 2;                // stencil rows of one parity (WM is even)
         constexpr int NP2 = (NR + R - 1) / R;     // passes over them
         const int grp = wave >> 1, par = wave & 1;
-        C *sub = tiles + grp * g.Ptot;
         for (int i = threadIdx.x; i < 2 * g.Ptot; i += kBlock)
             tiles[i] = C{T(0), T(0)};
         __syncthreads();
         const int lo = first + (len * grp) / 2;
         const int hi = first + (len * (grp + 1)) / 2;
         const int P1 = g.P[1];
+        // Per-lane constants of the item, for stencil row parity p = 0, 1 and pass q: the
+        // lane's tile index relative to the node's base cell (plus the pair's tile offset),
+        // and the shuffle address of its row factor.  Lanes with nothing to update in a pass
+        // (outside the stencil) get a private dummy slot after the two tiles instead, so the
+        // per-node code runs without predication: index = ok * base + A.
+        int A[2][NP2], okv[2][NP2], widx[2][NP2];
+        const int dummy = 2 * g.Ptot + wave * 64 + lane;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < NP2; ++q) {
+                const int s0 = p + 2 * (q * R + r);
+                const bool ok = lane_ok && s0 < W;
+                A[p][q] = ok ? grp * g.Ptot + s0 * P1 + sc : dummy;
+                okv[p][q] = ok ? 1 : 0;
+                widx[p][q] = (ok ? s0 : 0) * 4;
+            }
+        const int w1idx = (W + (sc < W ? sc : 0)) * 4;
         T fx = 0, fy = 0, wv[kBatch];
         int u0 = 0, u1 = 0;
         auto load_batch = [&](int b0, T &lfx, T &lfy, int &lu0, int &lu1, T *lwv) {
@@ -175,28 +205,31 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
                     break;
                 const T fxk = bcast(fx, k), fyk = bcast(fy, k);
                 const int ul0 = bcast(u0, k), ul1 = bcast(u1, k);
-                const T w1 = lane_shfl(wv[k], W + (sc < W ? sc : 0));
+                const T w1 = bperm(w1idx, wv[k]);
                 const T ax = fxk * w1, ay = fyk * w1;
-                const int s0p = (par - ul0) & 1;  // first stencil row of this wave's parity
-                const int base = ul0 * P1 + ul1 + sc;
-                T w0[NP2];
-                C v[NP2];
+                const int base = ul0 * P1 + ul1;  // the node's first stencil cell in the tile
+                auto update = [&](const int(&Aq)[NP2], const int(&okq)[NP2], const int(&wq)[NP2]) {
+                    T w0[NP2];
+                    C v[NP2];
+                    int idx[NP2];
 #pragma unroll
-                for (int q = 0; q < NP2; ++q) {
-                    const int s0 = s0p + 2 * (q * R + r);
-                    w0[q] = lane_shfl(wv[k], s0 < W ? s0 : 0);
-                    if (lane_ok && s0 < W)
-                        v[q] = sub[base + s0 * P1];
-                }
+                    for (int q = 0; q < NP2; ++q) {
+                        idx[q] = __mul24(okq[q], base) + Aq[q];
+                        w0[q] = bperm(wq[q], wv[k]);
+                        v[q] = tiles[idx[q]];
+                    }
 #pragma unroll
-                for (int q = 0; q < NP2; ++q) {
-                    const int s0 = s0p + 2 * (q * R + r);
-                    if (lane_ok && s0 < W) {
+                    for (int q = 0; q < NP2; ++q) {
                         v[q].x += ax * w0[q];
                         v[q].y += ay * w0[q];
-                        sub[base + s0 * P1] = v[q];
+                        tiles[idx[q]] = v[q];
                     }
-                }
+                };
+                // this wave's rows of the stencil start at parity (par - ul0) mod 2
+                if (((par - ul0) & 1) == 0)
+                    update(A[0], okv[0], widx[0]);
+                else
+                    update(A[1], okv[1], widx[1]);
             }
             fx = nfx;
             fy = nfy;

@@ -188,7 +188,6 @@ struct Nodes {
     int32_t *chunk_bin;    // [max_chunks]
     int32_t *chunk_first;  // [max_chunks] first sorted node
     int32_t *chunk_len;    // [max_chunks]
-    int32_t *chunk_safe;   // [max_chunks] 1: no cell holds more than 4 ceil(len/256) nodes
     int32_t *counters;     // [0] = number of work items, [1] = non-finite node flag
     void *psi;             // window factors per sorted node: [M][d][W] (float or double)
     const double *x;       // caller node array (only used while setting nodes)

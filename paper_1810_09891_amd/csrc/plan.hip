@@ -64,7 +64,9 @@ static int choose_bins(nfft_plan_s *p)
     const size_t ntiles = d == 1 ? 4 : d == 2 ? 2 : 1;
     // (1 KB of LDS is left for the static arrays of the batched kernels)
     const size_t budget = (d == 1 ? kLdsMax : kLdsPreferred) - 1024;
-    while (ntiles * lds_of(B) > budget) {
+    // 2-D spreading also keeps one dummy complex slot per thread (kBlock) after its tiles
+    const size_t extra = d == 2 ? (size_t)kBlock * cs : 0;
+    while (ntiles * lds_of(B) + extra > budget) {
         int best = -1;
         for (int t = 0; t < d; ++t)
             if (B[t] > minB && B[t] > 1 && (best < 0 || B[t] > B[best]))
@@ -73,7 +75,7 @@ static int choose_bins(nfft_plan_s *p)
             break;
         B[best] /= 2;
     }
-    if (ntiles * lds_of(B) > kLdsMax - 1024)
+    if (ntiles * lds_of(B) + extra > kLdsMax - 1024)
         return NFFT_ERR_UNSUPPORTED;
     Geom &g = p->geom;
     g.Ptot = 1;
@@ -255,7 +257,6 @@ static void layout_workspace(nfft_plan_s *p)
     p->off_chunk_bin = take(4 * (size_t)p->max_chunks);
     p->off_chunk_first = take(4 * (size_t)p->max_chunks);
     p->off_chunk_len = take(4 * (size_t)p->max_chunks);
-    p->off_chunk_safe = take(4 * (size_t)p->max_chunks);
     p->off_counters = take(64);
     p->off_xcopy = take(sizeof(double) * (size_t)M * p->d);
     p->off_psi = take(rs * (size_t)M * p->d * (size_t)(2 * p->m + 2));
@@ -324,7 +325,12 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
         delete p;
         return st;
     }
-    p->chunk_cap = 1024;
+    // Work items hold at most chunk_cap nodes of one bin: M / 512 rounded down to a power
+    // of two, between 128 and 1024, so that a dense bin of a clustered node set is split
+    // over many workgroups while uniform node sets keep about one item per bin.
+    p->chunk_cap = 128;
+    while (p->chunk_cap < 1024 && (int64_t)p->chunk_cap * 2 * 512 <= M)
+        p->chunk_cap *= 2;
     p->max_chunks = (int)(g.nbins + (M + p->chunk_cap - 1) / p->chunk_cap);
     build_tables(p);
     // FFT passes
@@ -365,7 +371,6 @@ Nodes plan_node_view(nfft_plan_s *p)
     nd.chunk_bin = reinterpret_cast<int32_t *>(ws + p->off_chunk_bin);
     nd.chunk_first = reinterpret_cast<int32_t *>(ws + p->off_chunk_first);
     nd.chunk_len = reinterpret_cast<int32_t *>(ws + p->off_chunk_len);
-    nd.chunk_safe = reinterpret_cast<int32_t *>(ws + p->off_chunk_safe);
     nd.counters = reinterpret_cast<int32_t *>(ws + p->off_counters);
     nd.psi = ws + p->off_psi;
     nd.M = p->M;

@@ -40,7 +40,7 @@ struct nfft_plan_s {
     size_t off_u[nfft::kMaxDim] = {0, 0, 0}, off_delta[nfft::kMaxDim] = {0, 0, 0};
     size_t off_perm = 0, off_key = 0, off_rank = 0;
     size_t off_bin_count = 0, off_bin_start = 0, off_bin_chunk = 0;
-    size_t off_chunk_bin = 0, off_chunk_first = 0, off_chunk_len = 0, off_chunk_safe = 0;
+    size_t off_chunk_bin = 0, off_chunk_first = 0, off_chunk_len = 0;
     size_t off_counters = 0, off_xcopy = 0, off_scratch = 0, off_psi = 0;
     size_t ws_bytes = 0;
 

@@ -179,16 +179,14 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 }  // namespace
 
 size_t interp_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8); }
-// spreading tiles per workgroup: four (1-D), two plus one dummy slot per thread (2-D), one
-// (3-D)
+// spreading tiles per workgroup: four (1-D); two (2-D) or one (3-D) followed by one dummy
+// slot per thread
 size_t spread_lds_bytes(const Geom &g, bool dbl)
 {
     const size_t cs = dbl ? 16 : 8;
     if (g.d == 1)
         return (size_t)g.Ptot * cs * 4;
-    if (g.d == 2)
-        return ((size_t)g.Ptot * 2 + kBlock) * cs;
-    return (size_t)g.Ptot * cs;
+    return ((size_t)g.Ptot * (g.d == 2 ? 2 : 1) + kBlock) * cs;
 }
 
 int fold_max_pairs(const Geom &g, int t)

@@ -280,18 +280,25 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
                 for (int k = 0; k < KB; ++k)
                     lwv[q][k] = (k < nb && lane + 64 * q < dW) ? psi[(int64_t)(b0 + k) * dW + lane + 64 * q] : T(0);
         };
-        // window factor of slot j (j < 3W, compile-time register choice when NW == 1)
-        auto factor = [&](int k, int j) -> T {
-            if constexpr (NW == 1) {
-                return lane_shfl(wv[0][k], j);
-            } else {
-                const T a0 = lane_shfl(wv[0][k], j < 64 ? j : 0);
-                const T a1 = lane_shfl(wv[1][k], j >= 64 ? j - 64 : 0);
-                return j < 64 ? a0 : a1;
-            }
-        };
         // the same slot for every lane (uniform j)
         auto factor_u = [&](int k, int j) -> T { return bcast(wv[0][k], j); };  // j < W <= 26
+        // Per-lane constants of the item (lanes over (s1, s2) = (q R + r, sc)): the tile
+        // index relative to a plane's first stencil cell and the shuffle addresses of the
+        // lane's factors.  Lanes outside the stencil get a private dummy slot after the
+        // tile, so the per-node code runs without predication: index = ok * base + A.
+        int A3[NPASS], ok3[NPASS], w1idx[NPASS];
+        const int dummy = g.Ptot + wave * 64 + lane;
+#pragma unroll
+        for (int q = 0; q < NPASS; ++q) {
+            const int s1 = q * R + r;
+            const bool ok = lane_ok && s1 < W;
+            A3[q] = ok ? s1 * P2 + sc : dummy;
+            ok3[q] = ok ? 1 : 0;
+            w1idx[q] = (W + (ok ? s1 : 0)) * 4;  // < 2W <= 52: always in the first register
+        }
+        const int j2 = 2 * W + (sc < W ? sc : 0);
+        const int w2idx = (j2 & 63) * 4;
+        const bool w2hi = j2 >= 64;
         if (first < hi)
             load_batch(first, fx, fy, u0, u1, u2, wv);
         for (int b0 = first; b0 < hi; b0 += KB) {
@@ -306,15 +313,17 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
                     break;
                 const T fxk = bcast(fx, k), fyk = bcast(fy, k);
                 const int ul0 = bcast(u0, k), ul1 = bcast(u1, k), ul2 = bcast(u2, k);
-                const T w2 = factor(k, 2 * W + (sc < W ? sc : 0));
+                T w2 = bperm(w2idx, wv[0][k]);
+                if constexpr (NW > 1) {
+                    const T w2b = bperm(w2idx, wv[NW - 1][k]);
+                    w2 = w2hi ? w2b : w2;
+                }
                 const T ax = fxk * w2, ay = fyk * w2;
                 T w1[NPASS];
 #pragma unroll
-                for (int q = 0; q < NPASS; ++q) {
-                    const int s1 = q * R + r;
-                    w1[q] = factor(k, W + (s1 < W ? s1 : 0));
-                }
-                const int rbase = ul1 * P2 + ul2 + sc;
+                for (int q = 0; q < NPASS; ++q)
+                    w1[q] = bperm(w1idx[q], wv[0][k]);
+                const int rbase = ul1 * P2 + ul2;
                 // this wave's planes of the stencil: s0 = s0a, s0a + 4, ... (at most NPL), in
                 // groups of G planes whose reads are all issued before their updates
                 const int s0a = (wave - ul0) & (kWaves - 1);
@@ -322,30 +331,30 @@ __device__ __forceinline__ void spread_item(const Geom &g, const Nodes &nd, cons
                 for (int t0 = 0; t0 < NPL; t0 += G) {
                     T w0[G];
                     C v[G][NPASS];
+                    int idx[G][NPASS];
 #pragma unroll
                     for (int t = 0; t < G; ++t) {
                         const int s0 = s0a + kWaves * (t0 + t);
                         w0[t] = factor_u(k, s0 < W ? s0 : 0);
-                        const C *plane = tiles + (ul0 + s0) * P1 * P2 + rbase;
+                        if (t0 + t < NPL && s0 < W) {  // uniform
+                            const int pbase = (ul0 + s0) * P1 * P2 + rbase;
 #pragma unroll
-                        for (int q = 0; q < NPASS; ++q) {
-                            const int s1 = q * R + r;
-                            if (t0 + t < NPL && s0 < W && lane_ok && s1 < W)
-                                v[t][q] = plane[s1 * P2];
+                            for (int q = 0; q < NPASS; ++q) {
+                                idx[t][q] = __mul24(ok3[q], pbase) + A3[q];
+                                v[t][q] = tiles[idx[t][q]];
+                            }
                         }
                     }
 #pragma unroll
                     for (int t = 0; t < G; ++t) {
                         const int s0 = s0a + kWaves * (t0 + t);
-                        const T bx = ax * w0[t], by = ay * w0[t];
-                        C *plane = tiles + (ul0 + s0) * P1 * P2 + rbase;
+                        if (t0 + t < NPL && s0 < W) {  // uniform
+                            const T bx = ax * w0[t], by = ay * w0[t];
 #pragma unroll
-                        for (int q = 0; q < NPASS; ++q) {
-                            const int s1 = q * R + r;
-                            if (t0 + t < NPL && s0 < W && lane_ok && s1 < W) {
+                            for (int q = 0; q < NPASS; ++q) {
                                 v[t][q].x += bx * w1[q];
                                 v[t][q].y += by * w1[q];
-                                plane[s1 * P2] = v[t][q];
+                                tiles[idx[t][q]] = v[t][q];
                             }
                         }
                     }

@@ -64,8 +64,8 @@ static int choose_bins(nfft_plan_s *p)
     const size_t ntiles = d == 1 ? 4 : d == 2 ? 2 : 1;
     // (1 KB of LDS is left for the static arrays of the batched kernels)
     const size_t budget = (d == 1 ? kLdsMax : kLdsPreferred) - 1024;
-    // 2-D spreading also keeps one dummy complex slot per thread (kBlock) after its tiles
-    const size_t extra = d == 2 ? (size_t)kBlock * cs : 0;
+    // 2-D and 3-D spreading also keep one dummy complex slot per thread after their tiles
+    const size_t extra = d >= 2 ? (size_t)kBlock * cs : 0;
     while (ntiles * lds_of(B) + extra > budget) {
         int best = -1;
         for (int t = 0; t < d; ++t)

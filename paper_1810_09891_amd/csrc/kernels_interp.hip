@@ -51,64 +51,129 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
 #pragma unroll
         for (int t = 0; t < D; ++t)
             ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
-        T wl[WM];  // innermost dimension
+        // window factors of dimension t at the WM compiled points (zero beyond W), read as
+        // aligned pairs (W and WM are even; the factor table is padded past its end)
+        auto factors = [&](int t, T *w) {
+            const Pair<T> *p2 = reinterpret_cast<const Pair<T> *>(pw + t * W);
 #pragma unroll
-        for (int s = 0; s < WM; ++s)
-            wl[s] = s < W ? pw[(D - 1) * W + s] : T(0);
-        T ax = 0, ay = 0;
-        if constexpr (D == 1) {
-            const C *row = tile + ul[0];
-#pragma unroll
-            for (int s = 0; s < WM; ++s) {
-                C v = row[s];
-                ax += wl[s] * v.x;
-                ay += wl[s] * v.y;
+            for (int s = 0; s < WM / 2; ++s) {
+                const Pair<T> v = p2[s];
+                w[2 * s] = 2 * s < W ? v.x : T(0);
+                w[2 * s + 1] = 2 * s + 1 < W ? v.y : T(0);
             }
-        } else if constexpr (D == 2) {
-            T w0r[WM];
+        };
+        T wl[WM];  // innermost dimension
+        factors(D - 1, wl);
+        T ax = 0, ay = 0;
+        // Rows of the stencil (WM points along the innermost dimension) are read from LDS one
+        // row ahead of their use, so a row's reads are in flight while the previous row is
+        // summed.  Rows past 2m+1 lie inside the padded tile and carry weight zero.
+        // (complex128 rows of 18 or more points keep one buffer: two would halve occupancy)
+        constexpr bool kAhead = sizeof(T) == 4 ? WM <= 22 : WM <= 10;
+        C buf[2][WM];
+        auto load_row = [&](const C *row, C *dst) {
 #pragma unroll
             for (int s = 0; s < WM; ++s)
-                w0r[s] = s < W ? pw[s] : T(0);
+                dst[s] = row[s];
+        };
+        // without the look-ahead buffer a row is summed straight from LDS
+        auto sum_lds = [&](const C *row, T &rx, T &ry) {
+            rx = 0;
+            ry = 0;
+#pragma unroll
+            for (int s = 0; s < WM; ++s) {
+                const C v = row[s];
+                rx += wl[s] * v.x;
+                ry += wl[s] * v.y;
+            }
+        };
+        auto sum_row = [&](const C *v, T &rx, T &ry) {
+            rx = 0;
+            ry = 0;
+#pragma unroll
+            for (int s = 0; s < WM; ++s) {
+                rx += wl[s] * v[s].x;
+                ry += wl[s] * v[s].y;
+            }
+        };
+        if constexpr (D == 1) {
+            sum_lds(tile + ul[0], ax, ay);
+        } else if constexpr (D == 2) {
+            T w0r[WM];
+            factors(0, w0r);
+            const int P1 = g.P[1];
+            const C *base = tile + ul[0] * P1 + ul[1];
+            if (kAhead)
+                load_row(base, buf[0]);
 #pragma unroll
             for (int s0 = 0; s0 < WM; ++s0) {
-                if (s0 < W) {
-                    const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
-                    T rx = 0, ry = 0;
-#pragma unroll
-                    for (int s1 = 0; s1 < WM; ++s1) {
-                        C v = row[s1];
-                        rx += wl[s1] * v.x;
-                        ry += wl[s1] * v.y;
-                    }
-                    ax += w0r[s0] * rx;
-                    ay += w0r[s0] * ry;
+                T rx, ry;
+                if constexpr (kAhead) {
+                    if (s0 + 1 < WM)
+                        load_row(base + (s0 + 1) * P1, buf[(s0 + 1) & 1]);
+                    sum_row(buf[s0 & 1], rx, ry);
+                } else {
+                    sum_lds(base + s0 * P1, rx, ry);
                 }
+                ax += w0r[s0] * rx;
+                ay += w0r[s0] * ry;
             }
         } else {
             T wmid[WM];
-#pragma unroll
-            for (int s = 0; s < WM; ++s)
-                wmid[s] = s < W ? pw[W + s] : T(0);
+            factors(1, wmid);
             const int P1 = g.P[1], P2 = g.P[2];
-            for (int s0 = 0; s0 < W; ++s0) {
-                const T w0 = pw[s0];
-                const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
-                T px = 0, py = 0;
+            if constexpr (sizeof(T) == 4 || WM <= 14) {
+                // planes unrolled, their factors loaded once
+                T w0r[WM];
+                factors(0, w0r);
 #pragma unroll
-                for (int s1 = 0; s1 < WM; ++s1) {
-                    const C *row = plane + s1 * P2;
-                    T rx = 0, ry = 0;
+                for (int s0 = 0; s0 < WM; ++s0) {
+                    if (s0 < W) {  // uniform
+                        const T w0 = w0r[s0];
+                        const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
+                        if (kAhead)
+                            load_row(plane, buf[0]);
+                        T px = 0, py = 0;
 #pragma unroll
-                    for (int s2 = 0; s2 < WM; ++s2) {
-                        C v = row[s2];
-                        rx += wl[s2] * v.x;
-                        ry += wl[s2] * v.y;
+                        for (int s1 = 0; s1 < WM; ++s1) {
+                            T rx, ry;
+                            if constexpr (kAhead) {
+                                if (s1 + 1 < WM)
+                                    load_row(plane + (s1 + 1) * P2, buf[(s1 + 1) & 1]);
+                                sum_row(buf[s1 & 1], rx, ry);
+                            } else {
+                                sum_lds(plane + s1 * P2, rx, ry);
+                            }
+                            px += wmid[s1] * rx;
+                            py += wmid[s1] * ry;
+                        }
+                        ax += w0 * px;
+                        ay += w0 * py;
                     }
-                    px += wmid[s1] * rx;
-                    py += wmid[s1] * ry;
                 }
-                ax += w0 * px;
-                ay += w0 * py;
+            } else {
+                for (int s0 = 0; s0 < W; ++s0) {
+                    const T w0 = pw[s0];
+                    const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
+                    if (kAhead)
+                        load_row(plane, buf[0]);
+                    T px = 0, py = 0;
+#pragma unroll
+                    for (int s1 = 0; s1 < WM; ++s1) {
+                        T rx, ry;
+                        if constexpr (kAhead) {
+                            if (s1 + 1 < WM)
+                                load_row(plane + (s1 + 1) * P2, buf[(s1 + 1) & 1]);
+                            sum_row(buf[s1 & 1], rx, ry);
+                        } else {
+                            sum_lds(plane + s1 * P2, rx, ry);
+                        }
+                        px += wmid[s1] * rx;
+                        py += wmid[s1] * ry;
+                    }
+                    ax += w0 * px;
+                    ay += w0 * py;
+                }
             }
         }
         f[nd.perm[node]] = C{ax, ay};

@@ -17,6 +17,7 @@ template <typename T> struct CplxOf;
 template <> struct CplxOf<float> { using type = float2; };
 template <> struct CplxOf<double> { using type = double2; };
 template <typename T> using Cplx = typename CplxOf<T>::type;
+template <typename T> using Pair = Cplx<T>;  // two reals loaded together
 
 template <typename C> __host__ __device__ __forceinline__ C cmul(C a, C b)
 {

@@ -259,7 +259,9 @@ static void layout_workspace(nfft_plan_s *p)
     p->off_chunk_len = take(4 * (size_t)p->max_chunks);
     p->off_counters = take(64);
     p->off_xcopy = take(sizeof(double) * (size_t)M * p->d);
-    p->off_psi = take(rs * (size_t)M * p->d * (size_t)(2 * p->m + 2));
+    // window factors, padded so that reads of WM (>= 2m+2) factors past the last node's
+    // record stay inside the workspace
+    p->off_psi = take(rs * ((size_t)M * p->d * (size_t)(2 * p->m + 2) + 64));
     p->off_scratch = take(cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
     p->ws_bytes = off;
 }

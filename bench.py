@@ -35,6 +35,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NFFT fwd+adj nonuniform points/s at stated rel-ℓ2 error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# LDS ceilings of one MI355X measured with paper_1810_09891_amd/lib/lds_bw (conflict-free
+# 8-byte read-add-write and 8-byte reads, all 256 CUs): the bound of the window kernels
+LDS_RMW8_PEAK_GBS = 43480.0
+LDS_READ8_PEAK_GBS = 60060.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2_512_c64_m8.json")
 
 
@@ -467,6 +471,17 @@ def main():
             "algorithmic_bytes": alg,
             "avg_launch_ms": round(dom_ms, 5),
         }
+        # the window kernels are bound by LDS, not HBM: one read-add-write (spreading) or
+        # read (interpolation) of an 8-byte cell per stencil point, against the measured
+        # LDS ceilings
+        stencil = M * (2 * 8 + 2) ** 2
+        lds = {}
+        for k, per, peak in (("spread_tiles", 16, LDS_RMW8_PEAK_GBS), ("interp", 8, LDS_READ8_PEAK_GBS)):
+            if k in kt:
+                a = stencil * per / (kt[k][0] * 1e-3) / 1e9
+                lds[k] = {"achieved": round(a, 1), "peak": peak, "unit": "GB/s", "frac": round(a / peak, 4),
+                          "lds_bytes": stencil * per}
+        roofline["lds"] = lds
         for k, (avg, cnt) in sorted(kt.items()):
             bts = algorithmic_bytes(k, 2, N, n, M, cb)
             per_kernel[k] = {"avg_ms": round(avg, 5), "launches": cnt, "algorithmic_bytes": bts,

@@ -6,7 +6,8 @@ with m = 8.  Reported beside it: complex128 and m = 4 variants of the same workl
 the other workloads -- d = 1 (N = 256, M = 1024, complex128, m = 8), d = 3 radial spokes
 (N = 128^3, M = 2,097,152, complex64, m = 6), 64 uneven d = 2 plans in one batch
 (complex64, m = 6, autotuned launch shapes, against per-plan launches) and the
-differentiable d = 2 radial workload (forward + backward).
+differentiable d = 2 radial workload (forward + backward), and a Gaussian-kernel fast
+summation (adjoint NFFT, kernel product, NFFT).
 
 A step is one nfft_trafo plus one nfft_adjoint of the whole node set (inputs resident in
 device memory; the node precomputation is timed separately, as Sec. 4 of the paper does).
@@ -362,6 +363,38 @@ def bench_grad(torch, steps, warmup, check):
     return r
 
 
+def bench_fastsum(torch, steps, warmup, check):
+    """Fast summation with a Gaussian kernel: d = 2, N = (128, 128), 32768 source and
+    32768 target nodes uniform on [-1/2, 1/2)^2, complex64, m = 6, c = 0.05."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1810_09891_amd import Plan, fastsum, gaussian_coefficients, workloads as W
+
+    r = W.rng("fastsum", 0)
+    N, M, cw = (128, 128), 32768, 0.05
+    x = W.uniform_nodes(r, M, 2)
+    y = W.uniform_nodes(r, M, 2)
+    alpha = W.cgauss(r, (M,))
+    C64 = torch.complex64
+    px = Plan(N, M, m=6, dtype=C64).set_nodes(torch.as_tensor(x).cuda())
+    py = Plan(N, M, m=6, dtype=C64).set_nodes(torch.as_tensor(y).cuda())
+    bhat = gaussian_coefficients(N, cw, dtype=C64)
+    a = torch.as_tensor(alpha).to("cuda", C64)
+    out = torch.empty(M, dtype=C64, device="cuda")
+    ms = cuda_time(torch, lambda: fastsum(px, py, bhat, a, out=out), steps, warmup)
+    r_ = {"workload": "fast summation, Gaussian kernel c=0.05: d=2 N=(128,128), 32768 sources and 32768 targets "
+                      "uniform, complex64, m=6 (adjoint NFFT with the kernel product fused, then NFFT)",
+          "ms_per_step": ms, "points_per_s": 2 * M / (ms * 1e-3)}
+    if check:
+        fastsum(px, py, bhat, a, out=out)
+        g = out.cpu().numpy()
+        sel = sample(M, 512, 6)
+        ref = O.fastsum(x, y[sel], gaussian_coefficients(N, cw, device="cpu").numpy(), alpha)
+        r_["e2_vs_oracle_512_targets"] = e2(ref, g[sel])
+    return r_
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,7 +469,8 @@ def main():
     if not args.primary_only:
         check = not args.no_cpu
         for name, fn, st in (("d1_256_c128_m8", bench_d1, args.steps), ("d3_radial_128_c64_m6", bench_d3, 20),
-                             ("batch64_c64_m6", bench_batch, 20), ("grad_radial_256_c64_m6", bench_grad, 20)):
+                             ("batch64_c64_m6", bench_batch, 20), ("grad_radial_256_c64_m6", bench_grad, 20),
+                             ("fastsum_gauss_128_c64_m6", bench_fastsum, 50)):
             t0 = time.perf_counter()
             extra[name] = fn(torch, st, 3, check)
             log("%s: %.4f ms/step, %.3e points/s (%.1f s)" %

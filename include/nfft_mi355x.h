@@ -137,6 +137,22 @@ int nfft_trafo(nfft_plan p, const void *fhat, void *f, hipStream_t stream);
 /* Adjoint NFFT, Algorithm 2.2: hhat [device, shape N] = A^H f for f [device, M]. */
 int nfft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t stream);
 
+/* Fast summation (the kernel sums named in Sec. 1 as an application of the NFFT): for a
+ * kernel given as a trigonometric polynomial with the sign of eq. (1.2),
+ * K(z) = sum_{k in I_N} bhat_k e^{-2 pi i k.z},
+ *     g_j = sum_l alpha_l K(y_j - x_l),   j < M_y,
+ * computed as g = A_y (bhat (.) A_x^H alpha): the adjoint NFFT of alpha at the nodes x of
+ * plan px (its last FFT pass multiplies by bhat), then the NFFT at the nodes y of plan py.
+ *   px, py     plans with nodes set, equal d, N and dtype (px == py is allowed: y = x).
+ *   bhat       [device, shape N] kernel coefficients, centred row-major.
+ *   alpha      [device, M_x] coefficients; g [device, M_y] result.
+ *   coef_work  [device, shape N] caller-owned scratch of |I_N| complex values.
+ * Enqueued on `stream`; NFFT_ERR_STATE before both plans have nodes, NFFT_ERR_ARG on
+ * mismatched plans or null pointers.  px's forward grid is overwritten unless it was
+ * created with NFFT_KEEP_GRID. */
+int nfft_fastsum(nfft_plan px, nfft_plan py, const void *bhat, const void *alpha, void *g, void *coef_work,
+                 hipStream_t stream);
+
 /* Direct sums eq. (1.2) / (1.3) on the device, O(M |I_N|) work: f = NDFT(fhat) and
  * hhat = NDFT^H(f).  Phases k.x are formed in FP64 and reduced before the
  * exponential; the sums accumulate in the plan's precision.  Need nfft_set_nodes

@@ -165,6 +165,15 @@ def ndft_adjoint(x, f, N):
     return out
 
 
+def fastsum(x, y, bhat, alpha):
+    """Kernel sums g_j = sum_l alpha_l K(y_j - x_l) for the trigonometric polynomial
+    K(z) = sum_k bhat_k e^{-2 pi i k.z} (the sign of eq. (1.2)) -- the fast summation
+    application named in Sec. 1 -- written out through the direct sums:
+    g_j = sum_k (bhat_k sum_l alpha_l e^{2 pi i k.x_l}) e^{-2 pi i k.y_j}."""
+    c = _c128(bhat) * ndft_adjoint(x, alpha, np.shape(bhat))
+    return ndft_trafo(y, c)
+
+
 def ndft_adjoint_at(x, f, N, flat_idx):
     """hhat at the given flat (centred, row-major) coefficient positions."""
     x = _f64(x)

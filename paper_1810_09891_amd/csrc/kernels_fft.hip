@@ -230,6 +230,7 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     const double *wt = pick3(p.w, t);
     const C *fin = static_cast<const C *>(fin_ptr);
     C *fout = static_cast<C *>(fout_ptr);
+    const C *mul = static_cast<const C *>(p.mul);
     if (threadIdx.x < nl)
         line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
     __syncthreads();
@@ -300,7 +301,10 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
                 grid[gb + i * st] = val;
             } else {
                 double f = s_fac[c] * wt[pc];
-                fout[s_cbase[c] + pc] = C{(T)((double)val.x * f), (T)((double)val.y * f)};
+                C o = C{(T)((double)val.x * f), (T)((double)val.y * f)};
+                if (mul)
+                    o = cmul(o, mul[s_cbase[c] + pc]);
+                fout[s_cbase[c] + pc] = o;
             }
         }
     }

@@ -26,6 +26,7 @@ struct FftPass {
     void *grid;          // complex grid (in place)
     const void *fin;     // coefficients read by the first forward pass (mode 0)
     void *fout;          // coefficients written by the last adjoint pass (mode 2)
+    const void *mul;     // optional factors (shape N, complex) applied in that write, or null
     const double *w[kMaxDim];  // deconvolution factors per dimension, centred index
     const void *tw;      // e^{-2 pi i k / L}, k < L, for the transformed dimension
     int d, t;            // dimension count, transformed dimension

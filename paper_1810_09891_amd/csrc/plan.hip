@@ -391,6 +391,7 @@ FftPass plan_bind_pass(nfft_plan_s *p, const FftPass &tmpl, void *grid, const vo
     for (int t = 0; t < kMaxDim; ++t)
         fp.w[t] = t < p->d ? reinterpret_cast<const double *>(ws + p->off_w[t]) : nullptr;
     fp.tw = ws + p->off_tw[tmpl.t];
+    fp.mul = nullptr;
     return fp;
 }
 
@@ -458,10 +459,12 @@ static int run_forward_grid(nfft_plan_s *p, const void *fhat, void *grid, hipStr
     return NFFT_OK;
 }
 
-static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_t s)
+static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_t s, const void *mul = nullptr)
 {
     for (size_t i = 0; i < p->adj_passes.size(); ++i) {
         FftPass fp = plan_bind_pass(p, p->adj_passes[i], grid, nullptr, hhat);
+        if (i + 1 == p->adj_passes.size())
+            fp.mul = mul;
         int blocks = (int)std::min<int64_t>(fp.ngroups, 1 << 20);
         LAUNCH(p, s, i + 1 == p->adj_passes.size() ? "fft_adj_deconv" : "fft_adj",
                launch_fft_pass(fp, p->dbl, blocks, s));
@@ -663,6 +666,40 @@ int nfft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t s)
         return st;
     if (p->off_grid_adj == p->off_grid)
         p->grid_valid = false;
+    return NFFT_OK;
+}
+
+int nfft_fastsum(nfft_plan px, nfft_plan py, const void *bhat, const void *alpha, void *g, void *coef_work,
+                 hipStream_t s)
+{
+    int st = check_ready(px);
+    if (st != NFFT_OK)
+        return st;
+    if ((st = check_ready(py)) != NFFT_OK)
+        return st;
+    if (!bhat || !alpha || !g || !coef_work)
+        return NFFT_ERR_ARG;
+    if (px->d != py->d || px->dtype != py->dtype)
+        return NFFT_ERR_ARG;
+    for (int t = 0; t < px->d; ++t)
+        if (px->N[t] != py->N[t])
+            return NFFT_ERR_ARG;
+    // coefficients of the kernel sum: bhat (.) A_x^H alpha, the product taken in the
+    // adjoint's last pass
+    void *gx = static_cast<char *>(px->ws) + px->off_grid_adj;
+    if ((st = run_spread(px, alpha, gx, s)) != NFFT_OK)
+        return st;
+    if ((st = run_adjoint_coeffs(px, gx, coef_work, s, bhat)) != NFFT_OK)
+        return st;
+    if (px->off_grid_adj == px->off_grid)
+        px->grid_valid = false;
+    // g = A_y coef
+    void *gy = static_cast<char *>(py->ws) + py->off_grid;
+    if ((st = run_forward_grid(py, coef_work, gy, s)) != NFFT_OK)
+        return st;
+    if ((st = run_interp(py, gy, g, s)) != NFFT_OK)
+        return st;
+    py->grid_valid = true;
     return NFFT_OK;
 }
 

@@ -304,3 +304,33 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def fastsum(px, py, bhat, alpha, out=None):
+    """Kernel sums g_j = sum_l alpha_l K(y_j - x_l) for K(z) = sum_k bhat_k e^{-2 pi i k.z}
+    (nfft_fastsum): x are the nodes of plan px, y those of plan py (px may be py)."""
+    if px.N != py.N or px.dtype != py.dtype:
+        raise ValueError("plans must have equal N and dtype")
+    bhat = px._as(bhat, px.dtype, px.N, "bhat")
+    alpha = px._as(alpha, px.dtype, (px.M,), "alpha")
+    g = py._out(out, (py.M,))
+    work = torch.empty(px.N, dtype=px.dtype, device=px.device)
+    check(px._lib.nfft_fastsum(px._h, py._h, _ptr(bhat), _ptr(alpha), _ptr(g), _ptr(work), _stream(px.device)),
+          "nfft_fastsum")
+    if px is not py:
+        px.generation += 1
+    py.generation += 1
+    px._keep = (bhat, alpha, work)  # alive until the enqueued work has read them
+    return g
+
+
+def gaussian_coefficients(N, c, dtype=torch.complex128, device="cuda"):
+    """Fourier coefficients on I_N of the 1-periodised Gaussian exp(-|z|^2 / c^2):
+    bhat_k = (c sqrt(pi))^d exp(-pi^2 c^2 |k|^2) (centred row-major), a kernel for
+    ``fastsum``; for c well below 1/2 the periodisation is the Gaussian itself near 0."""
+    import math
+
+    grids = torch.meshgrid(*[torch.arange(-n // 2, n // 2, dtype=torch.float64) for n in N], indexing="ij")
+    k2 = sum(g * g for g in grids)
+    b = (c * math.sqrt(math.pi)) ** len(N) * torch.exp(-(math.pi ** 2) * c * c * k2)
+    return b.to(device=device, dtype=dtype)

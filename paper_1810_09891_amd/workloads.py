@@ -15,6 +15,7 @@ Workloads (sizes from the evaluation plan; node layouts as stated):
 * ``"batch"``: 64 independent d=2 plans, N_t drawn from {64,128,256,512} per
   dimension, M log-uniform in [1e3, 2e5], uniform nodes.
 * ``"grad"``: d=2, N=(256,256), M=256 spokes * 256 points with N(0, 1e-3^2) jitter.
+* ``"fastsum"``: d=2, N=(128,128), 32768 source and 32768 target nodes, uniform.
 
 "Complex Gaussian" is CN(0,1): (a + i b)/sqrt(2) with a, b standard normal.
 Seeds are 18100989100 + 10*workload_id + stream_id, PCG64.
@@ -23,7 +24,7 @@ import numpy as np
 
 SEED_BASE = 18100989100
 
-WORKLOAD_ID = {"d1": 1, "d2": 2, "d3r": 3, "batch": 4, "grad": 5, "paper": 6, "small": 7}
+WORKLOAD_ID = {"d1": 1, "d2": 2, "d3r": 3, "batch": 4, "grad": 5, "paper": 6, "small": 7, "fastsum": 8}
 
 
 def rng(workload, stream=0):

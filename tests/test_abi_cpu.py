@@ -187,3 +187,17 @@ def test_batch_create_validation(lib):
     assert lib.nfft_batch_destroy(None) == ARG
     for h in hs:
         lib.nfft_plan_destroy(h)
+
+
+def test_fastsum_argument_checks(lib):
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.nfft_fastsum(None, None, fake, fake, fake, fake, None) == ARG
+    st, h = create(lib, (16, 16), 100, None, 4)
+    assert st == OK
+    # no workspace / no nodes
+    assert lib.nfft_fastsum(h, h, fake, fake, fake, fake, None) == WS
+    nb = ctypes.c_size_t()
+    lib.nfft_workspace_bytes(h, ctypes.byref(nb))
+    assert lib.nfft_set_workspace(h, fake, nb.value) == OK
+    assert lib.nfft_fastsum(h, h, fake, fake, fake, fake, None) == STATE
+    assert lib.nfft_plan_destroy(h) == OK

@@ -394,3 +394,50 @@ def test_error_measures():
     approx = np.array([3.0, 0.0])
     assert abs(O.err_l2(ref, approx) - 4.0 / 5.0) < 1e-16
     assert abs(O.err_inf(ref, approx, 8.0) - 0.5) < 1e-16
+
+
+# ------------------------------------------------------------------ fast summation
+
+
+def _brute_fastsum(x, y, bhat, alpha):
+    """g_j = sum_l alpha_l sum_k bhat_k e^{-2 pi i k.(y_j - x_l)}, all loops explicit."""
+    N = bhat.shape
+    ks = np.stack(np.meshgrid(*[np.arange(-n // 2, n // 2) for n in N], indexing="ij"), -1).reshape(-1, len(N))
+    b = bhat.reshape(-1)
+    g = np.zeros(len(y), dtype=np.complex128)
+    for j in range(len(y)):
+        for l in range(len(x)):
+            z = y[j] - x[l]
+            g[j] += alpha[l] * np.sum(b * np.exp(-2j * np.pi * (ks @ z)))
+    return g
+
+
+@pytest.mark.parametrize("N,Mx,My", [((8,), 5, 4), ((4, 6), 6, 3), ((4, 2, 4), 3, 4)])
+def test_fastsum_matches_brute_force(N, Mx, My):
+    r = np.random.default_rng(91)
+    d = len(N)
+    x = r.random((Mx, d)) - 0.5
+    y = r.random((My, d)) - 0.5
+    bhat = W.cgauss(r, N)
+    alpha = W.cgauss(r, (Mx,))
+    ref = _brute_fastsum(x, y, bhat, alpha)
+    assert np.linalg.norm(O.fastsum(x, y, bhat, alpha) - ref) / np.linalg.norm(ref) < 1e-13
+
+
+def test_fastsum_gaussian_kernel_closed_form():
+    """With the Fourier coefficients (c sqrt(pi))^d exp(-pi^2 c^2 |k|^2) of the periodised
+    Gaussian exp(-|z|^2/c^2) and a band wide enough that the omitted coefficients are below
+    1e-28, the kernel sums equal sums of Gaussians over the nearest periodic images."""
+    r = np.random.default_rng(92)
+    N, c = (64, 64), 0.08
+    x = r.random((300, 2)) - 0.5
+    y = r.random((200, 2)) - 0.5
+    alpha = W.cgauss(r, (300,))
+    k = np.stack(np.meshgrid(*[np.arange(-n // 2, n // 2) for n in N], indexing="ij"), -1)
+    bhat = (c * np.sqrt(np.pi)) ** 2 * np.exp(-np.pi ** 2 * c * c * np.sum(k * k, -1))
+    ref = np.zeros(200, dtype=np.complex128)
+    for m0 in (-1, 0, 1):
+        for m1 in (-1, 0, 1):
+            z = y[:, None, :] - x[None, :, :] + np.array([m0, m1])
+            ref += np.exp(-np.sum(z * z, -1) / (c * c)) @ alpha
+    assert np.linalg.norm(O.fastsum(x, y, bhat, alpha) - ref) / np.linalg.norm(ref) < 1e-12

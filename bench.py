@@ -2,7 +2,8 @@
 
 Headline workload: d = 2, N = (512, 512), n = (1024, 1024) (sigma = 2), M = 262144 nodes
 uniform on [-1/2, 1/2)^2, complex Gaussian data, Kaiser-Bessel window, complex64 plan
-with m = 8.  Reported beside it: complex128 and m = 4 variants of the same workload, and
+with m = 8.  Reported beside it: complex128, m = 4 and Gaussian-window variants of the same
+workload, and
 the other workloads -- d = 1 (N = 256, M = 1024, complex128, m = 8), d = 3 radial spokes
 (N = 128^3, M = 2,097,152, complex64, m = 6), 64 uneven d = 2 plans in one batch
 (complex64, m = 6, autotuned launch shapes, against per-plan launches) and the
@@ -84,7 +85,7 @@ ROCPROF_NAME = {"interp": "k_interp_nodes", "spread_tiles": "k_spread_tiles", "s
 
 
 class Case:
-    def __init__(self, w, m, dtype, torch):
+    def __init__(self, w, m, dtype, torch, window="kaiser-bessel"):
         from paper_1810_09891_amd import Plan
 
         self.w = w
@@ -92,7 +93,7 @@ class Case:
         self.dtype = dtype
         self.torch = torch
         dev = torch.device("cuda:0")
-        self.plan = Plan(w["N"], w["M"], n=w["n"], m=m, dtype=dtype, device=dev)
+        self.plan = Plan(w["N"], w["M"], n=w["n"], m=m, dtype=dtype, device=dev, window=window)
         self.x = torch.as_tensor(w["x"]).to(dev)
         self.fhat = torch.as_tensor(w["fhat"]).to(dev, dtype)
         self.f = torch.as_tensor(w["f"]).to(dev, dtype)
@@ -167,7 +168,7 @@ class Case:
         return self.out_f.cpu().numpy(), self.out_h.cpu().numpy()
 
 
-def cpu_baseline(w, m, reps):
+def cpu_baseline(w, m, reps, window="kaiser-bessel"):
     """Serial FP64 oracle NFFT + adjoint on the full workload (one core)."""
     import numpy as np
 
@@ -177,8 +178,9 @@ def cpu_baseline(w, m, reps):
     f_ref = h_ref = None
     for _ in range(reps):
         t0 = time.perf_counter()
-        f_ref = O.nfft_trafo(w["x"], w["fhat"], w["n"], m)
-        h_ref = O.nfft_adjoint(w["x"], w["f"], w["N"], w["n"], m)
+        with O.window(window):
+            f_ref = O.nfft_trafo(w["x"], w["fhat"], w["n"], m)
+            h_ref = O.nfft_adjoint(w["x"], w["f"], w["N"], w["n"], m)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
     return {"seconds_per_step": t, "f": f_ref, "h": h_ref, "runs": reps}
@@ -428,12 +430,14 @@ def main():
         del src, dst
 
     C64, C128 = torch.complex64, torch.complex128
-    variants = [(8, C64)] + ([] if args.primary_only else [(8, C128), (4, C64), (4, C128)])
+    KB, GAUSS = "kaiser-bessel", "gaussian"
+    variants = [(8, C64, KB)] + ([] if args.primary_only else
+                                 [(8, C128, KB), (4, C64, KB), (4, C128, KB), (8, C64, GAUSS)])
     results = []
     cpu = {}
-    for i, (m, dtype) in enumerate(variants):
+    for i, (m, dtype, window) in enumerate(variants):
         w = W.workload("d2", m=m)
-        case = Case(w, m, dtype, torch)
+        case = Case(w, m, dtype, torch, window)
         t_nodes = case.set_nodes_ms()
         if args.graph:
             case.capture()
@@ -444,6 +448,7 @@ def main():
         f_gpu, h_gpu = case.outputs()
         r = {
             "m": m,
+            "window": window,
             "dtype": "c64" if dtype == C64 else "c128",
             "ms_per_step": ms,
             "ms_per_step_with_events": ms_events,
@@ -453,15 +458,15 @@ def main():
             "steps": steps,
         }
         if not args.no_cpu:
-            if m not in cpu:
-                cpu[m] = cpu_baseline(w, m, reps=3 if not cpu else 1)
-            r["e2_trafo_vs_oracle"] = e2(cpu[m]["f"], f_gpu)
-            r["e2_adjoint_vs_oracle"] = e2(cpu[m]["h"], h_gpu)
+            if (m, window) not in cpu:
+                cpu[(m, window)] = cpu_baseline(w, m, reps=3 if not cpu else 1, window=window)
+            r["e2_trafo_vs_oracle"] = e2(cpu[(m, window)]["f"], f_gpu)
+            r["e2_adjoint_vs_oracle"] = e2(cpu[(m, window)]["h"], h_gpu)
         r["_kernel_avg"] = kt
         r["_w"] = (w["N"], w["n"], w["M"])
         results.append(r)
-        log("%s m=%d: %.4f ms/step (%.4f with events), %.3e points/s, set_nodes %.3f ms" %
-            (r["dtype"], m, ms, ms_events, r["points_per_s"], t_nodes))
+        log("%s m=%d %s: %.4f ms/step (%.4f with events), %.3e points/s, set_nodes %.3f ms" %
+            (r["dtype"], m, window, ms, ms_events, r["points_per_s"], t_nodes))
         del case
         torch.cuda.empty_cache()
 
@@ -546,7 +551,7 @@ def main():
         "ms_per_step_with_events": prim["ms_per_step_with_events"],
     }
     if not args.no_cpu:
-        c = cpu[8]
+        c = cpu[(8, KB)]
         import multiprocessing
 
         out["cpu_baseline"] = {

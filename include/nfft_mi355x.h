@@ -66,8 +66,13 @@ typedef enum {
  *    spreading (the node sorting flag of Sec. 3.1, Table 3.2).  Always on; accepted
  *    for compatibility.
  *  NFFT_KEEP_GRID: keep the oversampled grid of the last nfft_trafo in the workspace
- *    (separate from the grid nfft_adjoint uses), as nfft_grad_x needs it. */
-enum { NFFT_SORT_NODES = 1u << 0, NFFT_KEEP_GRID = 1u << 1 };
+ *    (separate from the grid nfft_adjoint uses), as nfft_grad_x needs it.
+ *  NFFT_WINDOW_GAUSSIAN: use the Gaussian window instead of the Kaiser-Bessel window of
+ *    Sec. 4 (the library of Sec. 3 can be configured with either; the paper prints neither
+ *    formula): phi(z) = (pi b)^{-1/2} exp(-z^2/b) in the grid variable z = n x - l,
+ *    b = 2 sigma m / ((2 sigma - 1) pi), sigma = n/N, Fourier transform exp(-b (pi k/n)^2);
+ *    same 2m+2-point stencil.  Less accurate than Kaiser-Bessel at equal m. */
+enum { NFFT_SORT_NODES = 1u << 0, NFFT_KEEP_GRID = 1u << 1, NFFT_WINDOW_GAUSSIAN = 1u << 2 };
 
 /* Read-only description of a plan (filled by nfft_plan_get_info). */
 typedef struct {
@@ -84,8 +89,10 @@ typedef struct {
     int64_t max_chunks;     /* upper bound on work items for any node set        */
     size_t workspace_bytes; /* bytes nfft_set_workspace needs                    */
     size_t lds_bytes;       /* LDS bytes per workgroup of the window kernels       */
-    double grid_scale;      /* prod_t e^{b_t m}: factor carried by the grids of the
-                               single-step entry points (see there)               */
+    double grid_scale;      /* prod_t lambda_t: factor carried by the grids of the
+                               single-step entry points (see there); lambda_t =
+                               e^{b_t m} (Kaiser-Bessel), (pi b_t)^{-1/2} (Gaussian) */
+    int window;             /* 0 Kaiser-Bessel, 1 Gaussian                        */
 } nfft_plan_info;
 
 /* ---------------------------------------------------------------- plans */
@@ -174,11 +181,12 @@ int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t stream);
 /* The transforms above are compositions of these steps; they are exposed so each step
  * can be checked and timed on its own.  g is a caller grid [device, shape n].
  *
- * Grid scaling: the library evaluates the Kaiser-Bessel window divided by e^{b_t m} in
- * every dimension (b_t = pi (2 - N_t/n_t)), which keeps FP32 window values accurate,
- * and carries the inverse factor in the deconvolution.  The grids these steps exchange
- * are therefore the grids of Algorithms 2.1 / 2.2 multiplied by S = prod_t e^{b_t m}
- * (forward, nfft_step_grid) or divided by S (adjoint, nfft_step_spread), and
+ * Grid scaling: the library evaluates the window divided by lambda_t in every dimension
+ * (Kaiser-Bessel: lambda_t = e^{b_t m}, b_t = pi (2 - N_t/n_t), which keeps FP32 window
+ * values accurate; Gaussian: lambda_t = (pi b_t)^{-1/2}, its peak) and carries lambda_t in
+ * the deconvolution.  The grids these steps exchange are therefore the grids of
+ * Algorithms 2.1 / 2.2 multiplied by S = prod_t lambda_t (forward, nfft_step_grid) or
+ * divided by S (adjoint, nfft_step_spread), and
  * nfft_step_interp / nfft_step_coeffs expect grids scaled the same way.  S is reported
  * as nfft_plan_info.grid_scale.  Composed, the steps give exactly nfft_trafo and
  * nfft_adjoint. */

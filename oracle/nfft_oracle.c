@@ -125,6 +125,47 @@ double or_kb_phihat(long k, long n, int m, double b)
 /* ------------------------------------------------------------------------- */
 
 /* Direct O(n^2) sum; angles reduced exactly through (k*l mod n). */
+/* Gaussian window (one of the windows the NFFT library of Sec. 3 can be configured with;
+ * its formulas are not printed in the paper -- the standard pair of the NFFT literature):
+ * in the grid variable z,
+ *   phi(z) = (pi b)^{-1/2} exp(-z^2 / b),   b = 2 sigma m / ((2 sigma - 1) pi),
+ *   phihat(k) = (1/n) exp(-b (pi k / n)^2),  sigma = n / N,
+ * so that n phihat(k) is the Fourier transform of phi at frequency k/n. */
+double or_gauss_b(long N, long n, int m)
+{
+    const double sigma = (double)n / (double)N;
+    return 2.0 * sigma * (double)m / ((2.0 * sigma - 1.0) * 3.14159265358979323846);
+}
+
+double or_gauss_phi(double z, double b)
+{
+    return exp(-z * z / b) / sqrt(3.14159265358979323846 * b);
+}
+
+double or_gauss_dphi(double z, double b) { return -2.0 * z / b * or_gauss_phi(z, b); }
+
+double or_gauss_phihat(long k, long n, double b)
+{
+    const double a = 3.14159265358979323846 * (double)k / (double)n;
+    return exp(-b * a * a) / (double)n;
+}
+
+/* Window used by the NFFT functions below: 0 Kaiser-Bessel (R1), 1 Gaussian. */
+static int or_window = 0;
+void or_set_window(int w) { or_window = w; }
+int or_get_window(void) { return or_window; }
+
+static double win_b(long N, long n, int m) { return or_window == 1 ? or_gauss_b(N, n, m) : or_kb_b(N, n); }
+static double win_phi(double z, int m, double b) { return or_window == 1 ? or_gauss_phi(z, b) : or_kb_phi(z, m, b); }
+static double win_dphi(double z, int m, double b)
+{
+    return or_window == 1 ? or_gauss_dphi(z, b) : or_kb_dphi(z, m, b);
+}
+static double win_phihat(long k, long n, int m, double b)
+{
+    return or_window == 1 ? or_gauss_phihat(k, n, b) : or_kb_phihat(k, n, m, b);
+}
+
 void or_dft_naive(const cplx *in, cplx *out, long n, int sign)
 {
     for (long l = 0; l < n; ++l) {
@@ -354,14 +395,15 @@ void or_ndft_grad_x(int d, const long *N, long M, const double *x, const cplx *f
 /* NFFT, Algorithm 2.1 and Algorithm 2.2, step by step                        */
 /* ------------------------------------------------------------------------- */
 
-/* Step 1 of Algorithm 2.1: ghat[k mod n] = fhat_k / (|I_n| prod_t phihat_t(k_t))
+/* Step 1 of Algorithm 2.1 (with the window selected by or_set_window):
+ * ghat[k mod n] = fhat_k / (|I_n| prod_t phihat_t(k_t))
  * for k in I_N, zero elsewhere on I_n.  ghat has shape n (row-major). */
 void or_nfft_deconv(int d, const long *N, const long *n, int m, const cplx *fhat, cplx *ghat)
 {
     long nn = prod_l(d, n), nk = prod_l(d, N);
     double b[3];
     for (int t = 0; t < d; ++t)
-        b[t] = or_kb_b(N[t], n[t]);
+        b[t] = win_b(N[t], n[t], m);
     memset(ghat, 0, sizeof(cplx) * (size_t)nn);
     for (long idx = 0; idx < nk; ++idx) {
         long k[3];
@@ -369,7 +411,7 @@ void or_nfft_deconv(int d, const long *N, const long *n, int m, const cplx *fhat
         double c = (double)nn;
         long pos = 0;
         for (int t = 0; t < d; ++t) {
-            c *= or_kb_phihat(k[t], n[t], m, b[t]);
+            c *= win_phihat(k[t], n[t], m, b[t]);
             long l = ((k[t] % n[t]) + n[t]) % n[t];
             pos = pos * n[t] + l;
         }
@@ -383,14 +425,14 @@ void or_nfft_deconv_adj(int d, const long *N, const long *n, int m, const cplx *
     long nn = prod_l(d, n), nk = prod_l(d, N);
     double b[3];
     for (int t = 0; t < d; ++t)
-        b[t] = or_kb_b(N[t], n[t]);
+        b[t] = win_b(N[t], n[t], m);
     for (long idx = 0; idx < nk; ++idx) {
         long k[3];
         centred_k(d, N, idx, k);
         double c = (double)nn;
         long pos = 0;
         for (int t = 0; t < d; ++t) {
-            c *= or_kb_phihat(k[t], n[t], m, b[t]);
+            c *= win_phihat(k[t], n[t], m, b[t]);
             long l = ((k[t] % n[t]) + n[t]) % n[t];
             pos = pos * n[t] + l;
         }
@@ -409,14 +451,14 @@ static void node_factors(int d, const long *N, const long *n, int m, const doubl
 {
     int W = 2 * m + 2;
     for (int t = 0; t < d; ++t) {
-        double b = or_kb_b(N[t], n[t]);
+        double b = win_b(N[t], n[t], m);
         double y = (double)n[t] * xj[t];
         u[t] = (long)floor(y);
         for (int s = 0; s < W; ++s) {
             double z = y - (double)(u[t] + s - m);
-            phi[t][s] = or_kb_phi(z, m, b);
+            phi[t][s] = win_phi(z, m, b);
             if (dphi)
-                dphi[t][s] = or_kb_dphi(z, m, b);
+                dphi[t][s] = win_dphi(z, m, b);
         }
     }
 }

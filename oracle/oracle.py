@@ -49,6 +49,12 @@ def _load():
             "or_kb_phi": (D, [D, Ii, D]),
             "or_kb_dphi": (D, [D, Ii, D]),
             "or_kb_phihat": (D, [L, L, Ii, D]),
+            "or_gauss_b": (D, [L, L, Ii]),
+            "or_gauss_phi": (D, [D, D]),
+            "or_gauss_dphi": (D, [D, D]),
+            "or_gauss_phihat": (D, [L, L, D]),
+            "or_set_window": (None, [Ii]),
+            "or_get_window": (Ii, []),
             "or_dft_naive": (None, [P, P, L, Ii]),
             "or_fft_1d": (None, [P, L, Ii]),
             "or_fft_d": (None, [Ii, P, P, Ii]),
@@ -122,6 +128,42 @@ def kb_dphi(z, m, b):
 
 def kb_phihat(k, n, m, b):
     return _load().or_kb_phihat(int(k), int(n), int(m), float(b))
+
+
+def gauss_b(N, n, m):
+    return _load().or_gauss_b(int(N), int(n), int(m))
+
+
+def gauss_phi(z, b):
+    return _load().or_gauss_phi(float(z), float(b))
+
+
+def gauss_dphi(z, b):
+    return _load().or_gauss_dphi(float(z), float(b))
+
+
+def gauss_phihat(k, n, b):
+    return _load().or_gauss_phihat(int(k), int(n), float(b))
+
+
+WINDOWS = {"kaiser-bessel": 0, "gaussian": 1}
+
+
+class window:
+    """Context manager selecting the window of the oracle's NFFT functions
+    (``with window("gaussian"): ...``); Kaiser-Bessel otherwise."""
+
+    def __init__(self, name):
+        self.code = WINDOWS[name]
+
+    def __enter__(self):
+        self.prev = _load().or_get_window()
+        _load().or_set_window(self.code)
+        return self
+
+    def __exit__(self, *exc):
+        _load().or_set_window(self.prev)
+        return False
 
 
 def dft_naive(a, sign):

@@ -13,6 +13,8 @@ NFFT_C64 = 1
 NFFT_C128 = 2
 NFFT_SORT_NODES = 1 << 0
 NFFT_KEEP_GRID = 1 << 1
+NFFT_WINDOW_GAUSSIAN = 1 << 2
+WINDOW_FLAGS = {"kaiser-bessel": 0, "gaussian": NFFT_WINDOW_GAUSSIAN}
 
 STATUS = {
     0: "NFFT_OK",
@@ -56,6 +58,7 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("lds_bytes", ctypes.c_size_t),
         ("grid_scale", ctypes.c_double),
+        ("window", ctypes.c_int),
     ]
 
 

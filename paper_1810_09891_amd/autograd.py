@@ -52,6 +52,6 @@ def nfft(x, fhat, plan):
     return _NfftFunction.apply(x, fhat, plan)
 
 
-def differentiable_plan(N, M, n=None, m=8, dtype=torch.complex64, device="cuda"):
+def differentiable_plan(N, M, n=None, m=8, dtype=torch.complex64, device="cuda", window="kaiser-bessel"):
     """A plan set up for ``nfft`` (keeps the forward grid for the node gradient)."""
-    return Plan(N, M, n=n, m=m, dtype=dtype, flags=NFFT_KEEP_GRID, device=device)
+    return Plan(N, M, n=n, m=m, dtype=dtype, flags=NFFT_KEEP_GRID, device=device, window=window)

@@ -55,10 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                     acc[0].y += dwl[s] * gv.y;
                 }
             } else if constexpr (D == 2) {
-                const T m = (T)g.m, b0 = (T)g.b[0], e0 = (T)g.emb[0];
                 for (int s0 = 0; s0 < g.W; ++s0) {
-                    const T w0 = kb_point<T>(dl[0], s0, g.W, m, b0, e0);
-                    const T dw0 = kb_point_d<T>(dl[0], s0, g.W, m, b0, e0);
+                    const T w0 = win_point<T>(g, 0, dl[0], s0);
+                    const T dw0 = win_point_d<T>(g, 0, dl[0], s0);
                     const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
                     T rx = 0, ry = 0, dx = 0, dy = 0;
 #pragma unroll
@@ -77,11 +76,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
             } else {
                 T wmid[WM], dwmid[WM];
                 window_row_d<T, WM>(dl[1], g, 1, wmid, dwmid);
-                const T m = (T)g.m, b0 = (T)g.b[0], e0 = (T)g.emb[0];
                 const int P1 = g.P[1], P2 = g.P[2];
                 for (int s0 = 0; s0 < g.W; ++s0) {
-                    const T w0 = kb_point<T>(dl[0], s0, g.W, m, b0, e0);
-                    const T dw0 = kb_point_d<T>(dl[0], s0, g.W, m, b0, e0);
+                    const T w0 = win_point<T>(g, 0, dl[0], s0);
+                    const T dw0 = win_point_d<T>(g, 0, dl[0], s0);
                     const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
                     T px = 0, py = 0, qx = 0, qy = 0, hx = 0, hy = 0;
 #pragma unroll

@@ -143,7 +143,7 @@ template <typename T> __global__ __launch_bounds__(kBlock) void k_node_psi(Geom 
     int t = r / W;
     int s = r - t * W;
     T delta = static_cast<const T *>(nd.delta[t])[node];
-    static_cast<T *>(nd.psi)[q] = kb_point<T>(delta, s, W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
+    static_cast<T *>(nd.psi)[q] = win_point<T>(g, t, delta, s);
 }
 
 // One thread per bin writes the bin's work items.

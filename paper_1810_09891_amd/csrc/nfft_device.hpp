@@ -158,6 +158,20 @@ template <typename T> __device__ __forceinline__ T kb_point_d(T delta, int s, in
     return kb_interior_d(z, m, b, emb);
 }
 
+// Gaussian window (the other window with a closed-form Fourier pair that the NFFT library
+// offers; standard pair of the NFFT literature), divided by its peak (pi b)^{-1/2}:
+// exp(-z^2 / b) in the grid variable z; the peak is carried by the deconvolution table.
+template <typename T> __device__ __forceinline__ T gauss_point(T delta, int s, T m, T b)
+{
+    const T z = delta - T(s - (int)m);
+    return exp(-z * z / b);
+}
+template <typename T> __device__ __forceinline__ T gauss_point_d(T delta, int s, T m, T b)
+{
+    const T z = delta - T(s - (int)m);
+    return T(-2) * z / b * exp(-z * z / b);
+}
+
 // ------------------------------------------------------------------ parameter blocks
 
 // Geometry of a plan's window kernels.
@@ -172,9 +186,26 @@ struct Geom {
     int P[kMaxDim];    // padded tile edge B + WM - 1
     int Ptot;          // prod P
     int nbins;
-    double b[kMaxDim];    // Kaiser-Bessel shape per dimension
-    double emb[kMaxDim];  // e^{-b m} per dimension
+    int window;           // 0 Kaiser-Bessel, 1 Gaussian
+    double b[kMaxDim];    // window shape per dimension
+    double emb[kMaxDim];  // 1 / (factor the device window is divided by): e^{-b m} (Kaiser-Bessel),
+                          // (pi b)^{1/2} (Gaussian)
 };
+
+// Window factor of dimension t at stencil point s of a node with offset delta, and its
+// derivative with respect to the grid variable, for the plan's window.
+template <typename T> __device__ __forceinline__ T win_point(const Geom &g, int t, T delta, int s)
+{
+    if (g.window == 1)
+        return gauss_point<T>(delta, s, (T)g.m, (T)g.b[t]);
+    return kb_point<T>(delta, s, g.W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
+}
+template <typename T> __device__ __forceinline__ T win_point_d(const Geom &g, int t, T delta, int s)
+{
+    if (g.window == 1)
+        return gauss_point_d<T>(delta, s, (T)g.m, (T)g.b[t]);
+    return kb_point_d<T>(delta, s, g.W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
+}
 
 // Sorted node data in the workspace (written by the node kernels).
 struct Nodes {

@@ -193,18 +193,36 @@ bool plan_repack_pass(const nfft_plan_s *p, const FftPass &tmpl, int factor, Fft
 static int build_tables(nfft_plan_s *p)
 {
     const double pi = 3.14159265358979323846264338327950288;
+    const bool gauss = (p->flags & NFFT_WINDOW_GAUSSIAN) != 0;
+    p->geom.window = gauss ? 1 : 0;
     for (int t = 0; t < p->d; ++t) {
-        const double b = pi * (2.0 - (double)p->N[t] / (double)p->n[t]);
-        p->geom.b[t] = b;
-        p->geom.emb[t] = std::exp(-b * p->m);
-        // deconvolution factor e^{b m} / (n phihat(k)), n phihat(k) = I0(m sqrt(b^2 - (2 pi k/n)^2))
+        // The device evaluates the window divided by lambda and the deconvolution factor is
+        // lambda / Phi(k), Phi(k) = n phihat(k) the window's Fourier transform at k / n.
         p->wtab[t].resize((size_t)p->N[t]);
-        for (int64_t i = 0; i < p->N[t]; ++i) {
-            const double k = (double)(i - p->N[t] / 2);
-            const double w = 2.0 * pi * k / (double)p->n[t];
-            const double arg = (double)p->m * std::sqrt(b * b - w * w);
-            const double i0 = std::cyl_bessel_i(0.0, arg);
-            p->wtab[t][(size_t)i] = std::exp(b * p->m) / i0;
+        if (gauss) {
+            // b = 2 sigma m / ((2 sigma - 1) pi), Phi(k) = exp(-b (pi k / n)^2),
+            // lambda = (pi b)^{-1/2} (the window's peak)
+            const double sigma = (double)p->n[t] / (double)p->N[t];
+            const double b = 2.0 * sigma * p->m / ((2.0 * sigma - 1.0) * pi);
+            const double lambda = 1.0 / std::sqrt(pi * b);
+            p->geom.b[t] = b;
+            p->geom.emb[t] = 1.0 / lambda;
+            for (int64_t i = 0; i < p->N[t]; ++i) {
+                const double a = pi * (double)(i - p->N[t] / 2) / (double)p->n[t];
+                p->wtab[t][(size_t)i] = lambda * std::exp(b * a * a);
+            }
+        } else {
+            // b = pi (2 - 1/sigma), Phi(k) = I0(m sqrt(b^2 - (2 pi k/n)^2)), lambda = e^{b m}
+            const double b = pi * (2.0 - (double)p->N[t] / (double)p->n[t]);
+            p->geom.b[t] = b;
+            p->geom.emb[t] = std::exp(-b * p->m);
+            for (int64_t i = 0; i < p->N[t]; ++i) {
+                const double k = (double)(i - p->N[t] / 2);
+                const double w = 2.0 * pi * k / (double)p->n[t];
+                const double arg = (double)p->m * std::sqrt(b * b - w * w);
+                const double i0 = std::cyl_bessel_i(0.0, arg);
+                p->wtab[t][(size_t)i] = std::exp(b * p->m) / i0;
+            }
         }
         // twiddles e^{-2 pi i k / n}, k < n, from the exact angle of each k
         p->twd[t].resize((size_t)p->n[t]);
@@ -579,6 +597,7 @@ int nfft_plan_get_info(nfft_plan p, nfft_plan_info *info)
     for (int t = 0; t < p->d; ++t)
         sc /= p->geom.emb[t];
     info->grid_scale = sc;
+    info->window = p->geom.window;
     return NFFT_OK;
 }
 

@@ -57,20 +57,18 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const C
 template <typename T, int WM>
 __device__ __forceinline__ void window_row(T delta, const Geom &g, int t, T *w)
 {
-    const T m = (T)g.m, b = (T)g.b[t], emb = (T)g.emb[t];
 #pragma unroll
     for (int s = 0; s < WM; ++s)
-        w[s] = s < g.W ? kb_point<T>(delta, s, g.W, m, b, emb) : T(0);
+        w[s] = s < g.W ? win_point<T>(g, t, delta, s) : T(0);
 }
 
 template <typename T, int WM>
 __device__ __forceinline__ void window_row_d(T delta, const Geom &g, int t, T *w, T *dw)
 {
-    const T m = (T)g.m, b = (T)g.b[t], emb = (T)g.emb[t];
 #pragma unroll
     for (int s = 0; s < WM; ++s) {
-        w[s] = s < g.W ? kb_point<T>(delta, s, g.W, m, b, emb) : T(0);
-        dw[s] = s < g.W ? kb_point_d<T>(delta, s, g.W, m, b, emb) : T(0);
+        w[s] = s < g.W ? win_point<T>(g, t, delta, s) : T(0);
+        dw[s] = s < g.W ? win_point_d<T>(g, t, delta, s) : T(0);
     }
 }
 

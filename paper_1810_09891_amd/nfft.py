@@ -39,14 +39,18 @@ def default_n(N):
 
 class Plan:
     """NFFT plan for d-variate transforms with bandwidths N, M nodes, FFT lengths n and
-    window size m, computing in complex64 or complex128.
+    window size m, computing in complex64 or complex128, with the Kaiser-Bessel window
+    (default) or the Gaussian window.
 
     Arrays: coefficients have shape N (centred: index i holds k = i - N/2), nodes are
     (M, d) float64, values are (M,).  All tensors live on ``device``.
     """
 
-    def __init__(self, N, M, n=None, m=8, dtype=torch.complex64, flags=0, device="cuda"):
+    def __init__(self, N, M, n=None, m=8, dtype=torch.complex64, flags=0, device="cuda", window="kaiser-bessel"):
         lib = _lib.load()
+        if window not in _lib.WINDOW_FLAGS:
+            raise ValueError("window must be one of %s" % sorted(_lib.WINDOW_FLAGS))
+        flags = int(flags) | _lib.WINDOW_FLAGS[window]
         self.N = tuple(int(v) for v in N)
         self.d = len(self.N)
         self.M = int(M)
@@ -67,6 +71,7 @@ class Plan:
         self.n = tuple(int(info.n[t]) for t in range(self.d))
         self.m = int(info.m)
         self.flags = int(info.flags)
+        self.window = window
         self.workspace = None
         self._x = None
         self.nodes_set = False

@@ -441,3 +441,64 @@ def test_fastsum_gaussian_kernel_closed_form():
             z = y[:, None, :] - x[None, :, :] + np.array([m0, m1])
             ref += np.exp(-np.sum(z * z, -1) / (c * c)) @ alpha
     assert np.linalg.norm(O.fastsum(x, y, bhat, alpha) - ref) / np.linalg.norm(ref) < 1e-12
+
+
+# ------------------------------------------------------------------ Gaussian window
+
+
+def test_gaussian_fourier_pair_by_quadrature():
+    """n phihat(k) = exp(-b (pi k / n)^2) is the Fourier transform of
+    phi(z) = (pi b)^{-1/2} exp(-z^2/b) at frequency k / n (numerical quadrature)."""
+    import scipy.integrate
+
+    for N, n, m in ((32, 64, 6), (100, 256, 4)):
+        b = O.gauss_b(N, n, m)
+        assert abs(b - 2 * (n / N) * m / ((2 * n / N - 1) * np.pi)) < 1e-14
+        for k in (0, 1, 7, N // 2 - 1, N // 2):
+            q = scipy.integrate.quad(lambda z: O.gauss_phi(z, b) * np.cos(2 * np.pi * k * z / n), 0, 80,
+                                     limit=400, epsabs=1e-16, epsrel=1e-13)[0] * 2
+            assert abs(n * O.gauss_phihat(k, n, b) - q) < 1e-13
+
+
+def test_gaussian_derivative_matches_finite_differences():
+    b = O.gauss_b(64, 128, 8)
+    for z in (-8.7, -3.2, 0.0, 0.4, 5.9):
+        h = 1e-6
+        fd = (O.gauss_phi(z + h, b) - O.gauss_phi(z - h, b)) / (2 * h)
+        assert abs(fd - O.gauss_dphi(z, b)) < 1e-9
+
+
+@pytest.mark.parametrize("N", [(128,), (32, 32)])
+def test_gaussian_nfft_within_error_bound(N):
+    """The Gaussian-window NFFT (sigma = 2) stays within the error bound
+    4 exp(-m pi (1 - 1/(2 sigma - 1))) of the literature (E_inf, eq. (2.16)), its error falls
+    at that rate in m, and it is less accurate than the Kaiser-Bessel NFFT at equal m."""
+    r = np.random.default_rng(93)
+    d = len(N)
+    x = r.random((600, d)) - 0.5
+    fh = W.cgauss(r, N)
+    f = O.ndft_trafo(x, fh)
+    prev = None
+    for m in (2, 4, 6, 8):
+        with O.window("gaussian"):
+            g = O.nfft_trafo(x, fh, None, m)
+        kb = O.nfft_trafo(x, fh, None, m)
+        einf = np.max(np.abs(f - g)) / np.sum(np.abs(fh))
+        assert einf <= 4 * np.exp(-m * np.pi * (1 - 1 / 3))
+        assert np.linalg.norm(f - kb) < np.linalg.norm(f - g)
+        if prev is not None:
+            rate = np.log(prev / einf) / 2  # per unit of m; the bound's rate is 2 pi / 3
+            assert 1.6 < rate < 2.8, rate
+        prev = einf
+
+
+def test_gaussian_adjoint_identity():
+    r = np.random.default_rng(94)
+    N, M = (16, 24), 300
+    x = r.random((M, 2)) - 0.5
+    fh = W.cgauss(r, N)
+    f = W.cgauss(r, (M,))
+    with O.window("gaussian"):
+        a = np.vdot(f, O.nfft_trafo(x, fh, None, 5))
+        b = np.vdot(O.nfft_adjoint(x, f, N, None, 5), fh)
+    assert abs(a - b) / abs(a) < 1e-13

@@ -1,5 +1,4 @@
-// Window kernels: interpolation (Algorithm 2.1 step 3), spreading (Algorithm 2.2 step 1)
-// and the gradient of the interpolation with respect to the nodes.
+// Interpolation (Algorithm 2.1 step 3) and the LDS sizes of the window kernels.
 //
 // Nodes are sorted into bins of B_0 x ... x B_{d-1} grid cells and cut into work items of
 // at most chunk_cap nodes of one bin.  The stencil of a node with u = floor(n x) covers
@@ -7,14 +6,11 @@
 // every stencil of a bin lies in its padded tile: origin b*B - m, edge P = B + WM - 1
 // (WM >= 2m+2 is the compiled stencil width, extra points carry weight zero).
 //
-//  * interpolation: a workgroup stages the padded tile of its bin from the grid into LDS
-//    with coalesced row reads (indices taken mod n, Sec. 2 eq. (2.5)), then each thread
-//    takes one node and sums its (2m+2)^d stencil from LDS as nested tensor-product sums
-//    (the structure the PRE_PSI flag of Table 3.2 exploits);
-//  * spreading: a workgroup accumulates the contributions of its nodes into a padded tile
-//    in LDS (LDS atomics, no global atomics) and writes the tile to its own slot of a
-//    scratch buffer; a fold kernel then writes every grid cell once as the sum, in a fixed
-//    order, of the tile slots that cover it.
+// A workgroup stages the padded tile of its bin from the grid into LDS with coalesced row
+// reads (indices taken mod n, Sec. 2 eq. (2.5)), then each thread takes one node and sums
+// its (2m+2)^d stencil from LDS as nested tensor-product sums of the precomputed window
+// factors (the structure the PRE_PSI flag of Table 3.2 exploits).  Spreading, the other
+// window kernel, is in kernels_spread.hip.
 #include "batch_desc.hpp"
 #include "window_common.hpp"
 

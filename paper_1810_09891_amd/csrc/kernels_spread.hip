@@ -30,7 +30,6 @@ using namespace window;
 constexpr int kWaves = kBlock / 64;
 constexpr int kBatch = 16;  // nodes whose data a wave loads at once
 
-template <typename T> __device__ __forceinline__ T lane_shfl(T v, int src) { return __shfl(v, src, 64); }
 
 // Value of v in the lane whose index times 4 is `byte_idx` (precomputed shuffle address).
 __device__ __forceinline__ float bperm(int byte_idx, float v)

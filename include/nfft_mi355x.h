@@ -131,9 +131,16 @@ int nfft_set_workspace(nfft_plan p, void *ws, size_t bytes);
  * delta = n_t x - u in FP64 (stencil index set, Sec. 2 eq. (2.13)), then a counting
  * sort of the nodes into bins of grid cells.  The derived data and a copy of x (read
  * by the direct sums) live in the workspace; the caller's x is not referenced after
- * the enqueued work has run.  Non-finite coordinates give non-finite results for those
- * nodes (and, in the adjoint, for the grid cells they touch). */
+ * the enqueued work has run.  A node with a non-finite coordinate is placed at grid
+ * index 0 with a NaN offset: the forward transform and the gradient are NaN at that node
+ * only, while the adjoint (whose grid cells it touches pass through the FFT) is NaN
+ * throughout.  nfft_nodes_finite reports whether this happened. */
 int nfft_set_nodes(nfft_plan p, const double *x, hipStream_t stream);
+
+/* Whether every coordinate passed to the last nfft_set_nodes was finite: *all_finite = 1
+ * if so, 0 if any was NaN or infinite.  Waits for `stream` (the flag is written by the
+ * node precomputation enqueued there).  NFFT_ERR_STATE before nfft_set_nodes. */
+int nfft_nodes_finite(nfft_plan p, int *all_finite, hipStream_t stream);
 
 /* ---------------------------------------------------------------- transforms */
 

@@ -28,7 +28,7 @@ STATUS = {
 # every exported entry point of include/nfft_mi355x.h
 ABI_SYMBOLS = [
     "nfft_plan_create", "nfft_plan_destroy", "nfft_plan_get_info", "nfft_workspace_bytes",
-    "nfft_set_workspace", "nfft_set_nodes", "nfft_trafo", "nfft_adjoint", "nfft_fastsum", "ndft_trafo",
+    "nfft_set_workspace", "nfft_set_nodes", "nfft_nodes_finite", "nfft_trafo", "nfft_adjoint", "nfft_fastsum", "ndft_trafo",
     "ndft_adjoint", "nfft_grad_x", "nfft_step_grid", "nfft_step_interp", "nfft_step_spread",
     "nfft_step_coeffs", "nfft_profile_enable", "nfft_profile_read", "nfft_batch_create",
     "nfft_batch_get_info", "nfft_batch_workspace_bytes", "nfft_batch_set_workspace",
@@ -98,6 +98,7 @@ def load():
         "nfft_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
         "nfft_set_workspace": [P, P, ctypes.c_size_t],
         "nfft_set_nodes": [P, P, P],
+        "nfft_nodes_finite": [P, ctypes.POINTER(ctypes.c_int), P],
         "nfft_trafo": [P, P, P, P],
         "nfft_adjoint": [P, P, P, P],
         "nfft_fastsum": [P, P, P, P, P, P, P],

@@ -111,9 +111,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
             }
             const int j = nd.perm[node];
             const C vj = v[j];
+            bool finite = true;  // a non-finite node (offset NaN) gets a NaN gradient
 #pragma unroll
             for (int t = 0; t < D; ++t)
-                grad[(int64_t)j * D + t] = (T)g.n[t] * (vj.x * acc[t].x + vj.y * acc[t].y);
+                finite = finite && !isnan(dl[t]);
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                grad[(int64_t)j * D + t] =
+                    finite ? (T)g.n[t] * (vj.x * acc[t].x + vj.y * acc[t].y) : __builtin_nan("");
         }
         __syncthreads();
     }

@@ -143,7 +143,8 @@ template <typename T> __global__ __launch_bounds__(kBlock) void k_node_psi(Geom 
     int t = r / W;
     int s = r - t * W;
     T delta = static_cast<const T *>(nd.delta[t])[node];
-    static_cast<T *>(nd.psi)[q] = win_point<T>(g, t, delta, s);
+    // a non-finite node (offset NaN) gets NaN factors, so that its results are NaN too
+    static_cast<T *>(nd.psi)[q] = isnan(delta) ? delta : win_point<T>(g, t, delta, s);
 }
 
 // One thread per bin writes the bin's work items.

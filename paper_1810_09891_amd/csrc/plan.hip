@@ -644,6 +644,24 @@ int nfft_set_nodes(nfft_plan p, const double *x, hipStream_t s)
     return NFFT_OK;
 }
 
+int nfft_nodes_finite(nfft_plan p, int *all_finite, hipStream_t s)
+{
+    if (!p || !all_finite)
+        return NFFT_ERR_ARG;
+    if (!p->ws)
+        return NFFT_ERR_WORKSPACE;
+    if (!p->nodes_set)
+        return NFFT_ERR_STATE;
+    const int32_t *counters = reinterpret_cast<const int32_t *>(static_cast<char *>(p->ws) + p->off_counters);
+    int32_t flag = 0;
+    if (hipMemcpyAsync(&flag, counters + 1, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return NFFT_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess)
+        return NFFT_ERR_HIP;
+    *all_finite = flag ? 0 : 1;
+    return NFFT_OK;
+}
+
 static int check_ready(nfft_plan p)
 {
     if (!p)

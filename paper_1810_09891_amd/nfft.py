@@ -107,6 +107,12 @@ class Plan:
         self.generation += 1
         return self
 
+    def nodes_finite(self):
+        """True if every coordinate of the last set_nodes was finite (waits for the stream)."""
+        flag = ctypes.c_int(0)
+        check(self._lib.nfft_nodes_finite(self._h, ctypes.byref(flag), _stream(self.device)), "nfft_nodes_finite")
+        return bool(flag.value)
+
     # ---------------------------------------------------------------- transforms
 
     def _as(self, t, dtype, shape, name):

@@ -72,6 +72,23 @@ def test_plan_validation(lib, N, M, n, m, expect):
         assert lib.nfft_plan_destroy(h) == OK
 
 
+@pytest.mark.parametrize(
+    "N,n,m,dtype,expect",
+    [
+        ((16, 16, 16), (32, 32, 32), 8, 2, OK),  # one 21^3 complex128 tile (141 KiB) per workgroup
+        ((16, 16, 16), (32, 32, 32), 12, 1, UNSUP),  # 29^3 complex64 tile exceeds the LDS
+        ((2048,), (4096,), 12, 2, OK),  # longest line and widest stencil
+        ((2048, 8), (4096, 32), 12, 1, OK),
+    ],
+)
+def test_lds_limits(lib, N, n, m, dtype, expect):
+    """Plans whose smallest spreading tile does not fit the 160 KiB of LDS are refused."""
+    st, h = create(lib, N, 100, n, m, dtype)
+    assert st == expect
+    if st == OK:
+        assert lib.nfft_plan_destroy(h) == OK
+
+
 def test_defaults(lib):
     st, h = create(lib, (100, 64), 5, None, 0)
     assert st == OK
@@ -90,7 +107,9 @@ def test_call_order_and_workspace(lib):
     assert nbytes.value > 0
     fake = ctypes.c_void_p(1 << 20)  # never dereferenced on the host
     # no workspace yet
+    flag = ctypes.c_int(-7)
     assert lib.nfft_set_nodes(h, fake, None) == WS
+    assert lib.nfft_nodes_finite(h, ctypes.byref(flag), None) == WS
     assert lib.nfft_trafo(h, fake, fake, None) == WS
     # workspace too small / misaligned
     assert lib.nfft_set_workspace(h, fake, nbytes.value - 1) == WS
@@ -104,8 +123,12 @@ def test_call_order_and_workspace(lib):
     assert lib.nfft_step_interp(h, fake, fake, None) == STATE
     assert lib.nfft_step_spread(h, fake, fake, None) == STATE
     assert lib.nfft_grad_x(h, fake, fake, None) == STATE
+    assert lib.nfft_nodes_finite(h, ctypes.byref(flag), None) == STATE
+    assert flag.value == -7
     # null arguments
     assert lib.nfft_set_nodes(h, None, None) == ARG
+    assert lib.nfft_nodes_finite(h, None, None) == ARG
+    assert lib.nfft_nodes_finite(None, ctypes.byref(flag), None) == ARG
     assert lib.nfft_workspace_bytes(None, ctypes.byref(nbytes)) == ARG
     assert lib.nfft_plan_destroy(h) == OK
 

@@ -126,7 +126,7 @@ void build_group(nfft_batch_s *b, Group &G)
             }
         }
         G.lds_interp = std::max(G.lds_interp, interp_lds_bytes(p->geom, p->dbl));
-        G.lds_spread = std::max(G.lds_spread, spread_lds_bytes(p->geom, p->dbl));
+        G.lds_spread = std::max(G.lds_spread, spread_batch_lds_bytes(p->geom, p->dbl));
         G.chunk_bound += p->max_chunks;
         G.fold_items += (p->ngrid + kBlock - 1) / kBlock;
     }

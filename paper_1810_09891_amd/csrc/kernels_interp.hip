@@ -242,7 +242,22 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 size_t interp_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8); }
 // spreading tiles per workgroup: four (1-D); two (2-D) or one (3-D) followed by one dummy
 // slot per thread
+bool spread_in_registers(const Geom &g, bool dbl)
+{
+    return g.d == 2 && g.W == g.WM && g.lgB[0] == (dbl ? 4 : 5) && g.lgB[1] == 5 && g.P[1] <= 64;
+}
+
 size_t spread_lds_bytes(const Geom &g, bool dbl)
+{
+    const size_t cs = dbl ? 16 : 8;
+    if (spread_in_registers(g, dbl)) {
+        // the tile the four waves' columns are summed in
+        return (size_t)g.Ptot * cs;
+    }
+    return spread_batch_lds_bytes(g, dbl);
+}
+
+size_t spread_batch_lds_bytes(const Geom &g, bool dbl)
 {
     const size_t cs = dbl ? 16 : 8;
     if (g.d == 1)

@@ -270,6 +270,24 @@ template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_s
             }
         }
         __syncthreads();
+        if constexpr (D == 2) {
+            if (nd.spos) {
+                // order for the 2-D spreading kernel that keeps tile columns in registers:
+                // by tile row, ties by position in the work item
+                const int rmask = (1 << g.lgB[0]) - 1;
+                for (int i = threadIdx.x; i < npow; i += kBlock)
+                    keys[i] = i < len ? ((unsigned long long)(nd.u[0][first + i] & rmask) << 10) | (unsigned)i : ~0ull;
+                __syncthreads();
+                bitonic(keys, npow);
+                for (int i = threadIdx.x; i < len; i += kBlock) {
+                    const int k = (int)(keys[i] & 1023ull);
+                    const int r0 = (int)(keys[i] >> 10);
+                    const int c0 = nd.u[1][first + k] & 31;
+                    nd.spos[first + i] = (k << 10) | (r0 << 5) | c0;
+                }
+                __syncthreads();
+            }
+        }
     }
 }
 

@@ -1,5 +1,7 @@
 // Spreading (Algorithm 2.2 step 1): LDS tile accumulation per work item and the
 // deterministic fold of the tiles into the grid.  Geometry as in window_common.hpp.
+#include <utility>
+
 #include "batch_desc.hpp"
 #include "window_common.hpp"
 
@@ -394,6 +396,186 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
         spread_item<T, D, WM>(g, nd, f, scratch, c, tiles);
 }
 
+// ------------------------------------------------------------------ 2-D spreading in registers
+//
+// d = 2 with bins of B0 x 32 cells (B0 = 32 for complex64, 16 for complex128) and 2m+2 = WM,
+// so that the padded tile is P0 = B0 + WM - 1 rows by P1 = 32 + WM - 1 <= 64 columns.  Lane
+// c of a wave owns tile column c and keeps all P0 cells of that column in registers.  A
+// node at tile-local cell (r0, c0) adds psi_0[s0] * (psi_1[c - c0] f_j) to rows r0 + s0 of
+// column c: the row factors are the same in every lane (scalar loads, used as scalar
+// operands) and the lane's column factor is one vector load.  The node precomputation
+// lists every work item's nodes by tile row (spos); a wave walks its part of that list
+// with one unrolled update sequence per row, so every register index is a constant and no
+// tile traffic goes through LDS, and it loads the next node's data while it adds the
+// current one.  The four waves of a workgroup take a quarter of the list each; their
+// columns are summed in wave order through one LDS tile when the item is done, so the
+// result is deterministic.
+
+// Inputs of the in-register spreading of one plan.
+template <typename T> struct ColsIn {
+    const int32_t *spos, *perm;
+    const T *psi;
+    const Cplx<T> *f;
+};
+
+// Data of one node for its update.
+template <typename T, int WM> struct ColsNode {
+    T w[WM];    // row factors (wave-uniform)
+    T v;        // psi_1 at this lane's column offset, clamped into the stencil
+    bool in;    // whether that offset lies inside the stencil
+    T fx, fy;   // value f_j (wave-uniform)
+};
+
+// acc[R + s] += w[s] * g for the WM rows of a node whose stencil starts at tile row R.  The
+// column mask is applied here, at the use, so that the loads of the next node stay in
+// flight while this one is added.
+template <int R, typename T, int P0, int WM>
+__device__ __forceinline__ void cols_rows(T (&ax)[P0], T (&ay)[P0], const ColsNode<T, WM> &nv)
+{
+    const T w1 = nv.in ? nv.v : T(0);
+    const T gx = w1 * nv.fx;
+    const T gy = w1 * nv.fy;
+#pragma unroll
+    for (int s = 0; s < WM; ++s) {
+        ax[R + s] += nv.w[s] * gx;
+        ay[R + s] += nv.w[s] * gy;
+    }
+}
+
+__device__ __forceinline__ float lane_value(float v, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double lane_value(double v, int k)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Issue the loads of batch entry k (list entry e, value f_j held by lane k) of the item
+// that starts at sorted position `first`.
+template <typename T, int WM>
+__device__ __forceinline__ void cols_load(ColsNode<T, WM> &nv, int e, int k, T fxk, T fyk, int first, int lane,
+                                          const ColsIn<T> &in)
+{
+    const int node = first + (e >> 10);
+    const T *p0 = in.psi + (int64_t)node * (2 * WM);
+#pragma unroll
+    for (int s = 0; s < WM; ++s)
+        nv.w[s] = p0[s];
+    const int s1 = lane - (e & 31);
+    const int sc = min(max(s1, 0), WM - 1);
+    nv.v = p0[WM + sc];
+    nv.in = s1 == sc;
+    nv.fx = lane_value(fxk, k);
+    nv.fy = lane_value(fyk, k);
+}
+
+// Walk the batch entries whose tile row is R (they follow each other), loading entry i + 1
+// while entry i is added.
+template <int R, typename T, int P0, int WM>
+__device__ __forceinline__ void cols_row(int &i, int nb, int &e, int ek, T fxk, T fyk, ColsNode<T, WM> &cur,
+                                         int first, int lane, const ColsIn<T> &in, T (&ax)[P0], T (&ay)[P0])
+{
+    while (i < nb && ((e >> 5) & 31) == R) {
+        ColsNode<T, WM> nxt;
+        int e1 = e;
+        if (i + 1 < nb) {
+            e1 = __builtin_amdgcn_readlane(ek, i + 1);
+            cols_load<T, WM>(nxt, e1, i + 1, fxk, fyk, first, lane, in);
+        }
+        cols_rows<R, T, P0, WM>(ax, ay, cur);
+        cur = nxt;
+        e = e1;
+        ++i;
+    }
+}
+
+template <typename T, int P0, int WM, int... Rs>
+__device__ __forceinline__ void cols_walk(std::integer_sequence<int, Rs...>, int nb, int ek, T fxk, T fyk, int first,
+                                          int lane, const ColsIn<T> &in, T (&ax)[P0], T (&ay)[P0])
+{
+    int i = 0;
+    int e = __builtin_amdgcn_readlane(ek, 0);
+    ColsNode<T, WM> cur;
+    cols_load<T, WM>(cur, e, 0, fxk, fyk, first, lane, in);
+    // Wait for the first entry's scalar loads here, once per batch: scalar loads complete
+    // out of order, so a load still pending when the walk starts would make every update
+    // wait for all scalar loads in flight, the next entry's included.  (An empty statement
+    // that passes a loaded register through; without memory effects the loads stay scalar.)
+    asm("" : "+s"(cur.w[0]));
+    (cols_row<Rs, T, P0, WM>(i, nb, e, ek, fxk, fyk, cur, first, lane, in, ax, ay), ...);
+}
+
+template <typename T, int B0, int WM>
+__global__ __launch_bounds__(kBlock) void k_spread_cols(const int32_t *__restrict__ counters,
+                                                        const int32_t *__restrict__ chunk_first,
+                                                        const int32_t *__restrict__ chunk_len, ColsIn<T> in,
+                                                        Cplx<T> *__restrict__ scratch)
+{
+    using C = Cplx<T>;
+    constexpr int P0 = B0 + WM - 1;
+    constexpr int P1 = 32 + WM - 1;
+    constexpr int Ptot = P0 * P1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const int nchunks = counters[0];
+    const int nwg = min((int)gridDim.x, nchunks);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
+        const int first = chunk_first[c];
+        const int len = chunk_len[c];
+        const int lo = (len * wave) >> 2;
+        const int hi = (len * (wave + 1)) >> 2;
+        T ax[P0], ay[P0];
+#pragma unroll
+        for (int r = 0; r < P0; ++r) {
+            ax[r] = 0;
+            ay[r] = 0;
+        }
+        for (int b = lo; b < hi; b += 64) {
+            const int nb = min(64, hi - b);
+            // lane k holds the list entry and the value f_j of batch entry k
+            int ek = 0;
+            T fxk = 0, fyk = 0;
+            if (lane < nb) {
+                ek = in.spos[first + b + lane];
+                const C fv = in.f[in.perm[first + (ek >> 10)]];
+                fxk = fv.x;
+                fyk = fv.y;
+            }
+            // the entries of a batch are sorted by row
+            cols_walk<T, P0, WM>(std::make_integer_sequence<int, B0>{}, nb, ek, fxk, fyk, first, lane, in, ax, ay);
+        }
+        for (int w = 0; w < kWaves; ++w) {
+            if (wave == w && lane < P1) {
+#pragma unroll
+                for (int r = 0; r < P0; ++r) {
+                    C v;
+                    v.x = ax[r];
+                    v.y = ay[r];
+                    if (w > 0) {
+                        const C o = lds[r * P1 + lane];
+                        v.x = o.x + v.x;
+                        v.y = o.y + v.y;
+                    }
+                    lds[r * P1 + lane] = v;
+                }
+            }
+            __syncthreads();
+        }
+        C *slot = scratch + (int64_t)c * Ptot;
+        for (int i = threadIdx.x; i < Ptot; i += kBlock)
+            slot[i] = lds[i];
+        __syncthreads();
+    }
+}
+
 // All plans of a batch in one launch, items handed out by the dynamic queue.
 template <typename T, int D, int WM>
 __global__ __launch_bounds__(kBlock) void k_spread_batch(const PlanDev *__restrict__ plans, int count, BatchPtrs ptrs,
@@ -529,11 +711,33 @@ __global__ __launch_bounds__(kBlock) void k_fold_batch(const PlanDev *__restrict
     }
 }
 
+template <typename T, int B0>
+hipError_t spread_cols_typed(const Geom &g, const Nodes &nd, const void *f, void *scratch, int blocks, size_t lds,
+                             hipStream_t s)
+{
+    using C = Cplx<T>;
+    ColsIn<T> in{nd.spos, nd.perm, static_cast<const T *>(nd.psi), static_cast<const C *>(f)};
+#define CALL(W_)                                                                                       \
+    {                                                                                                  \
+        auto kf = k_spread_cols<T, B0, W_>;                                                            \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+        hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, nd.counters, nd.chunk_first,           \
+                           nd.chunk_len, in, static_cast<C *>(scratch));                               \
+    }
+    NFFT_WM_SWITCH(g.WM, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
 template <typename T, int D>
 hipError_t spread_typed(const Geom &g, const Nodes &nd, const void *f, void *scratch, int blocks, size_t lds,
                         hipStream_t s)
 {
     using C = Cplx<T>;
+    if constexpr (D == 2) {
+        if (spread_in_registers(g, sizeof(T) == 8))
+            return spread_cols_typed<T, sizeof(T) == 8 ? 16 : 32>(g, nd, f, scratch, blocks, lds, s);
+    }
 #define CALL(W_)                                                                                       \
     {                                                                                                  \
         auto kf = k_spread_tiles<T, D, W_>;                                                            \

@@ -59,7 +59,14 @@ hipError_t launch_grad_x(const Geom &g, const Nodes &nd, bool dbl, const void *g
 
 // LDS bytes per workgroup of the interpolation / spreading / gradient kernels.
 size_t interp_lds_bytes(const Geom &g, bool dbl);
+// LDS of one spreading launch for a single plan (in-register 2-D kernel or tile kernel)
 size_t spread_lds_bytes(const Geom &g, bool dbl);
+// LDS of the tile kernel (the batched spreading launch always uses it)
+size_t spread_batch_lds_bytes(const Geom &g, bool dbl);
+// Whether single-plan spreading uses the in-register 2-D kernel: d = 2, 2m+2 equal to the
+// compiled stencil width (even m), bins of 32 x 32 (complex64) or 16 x 32 (complex128)
+// cells, padded tile width at most 64.
+bool spread_in_registers(const Geom &g, bool dbl);
 // Largest number of (bin, offset) pairs a grid index can have in one dimension; the
 // fold kernel supports up to kFoldMaxPairs.
 constexpr int kFoldMaxPairs = 24;

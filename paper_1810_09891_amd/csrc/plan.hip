@@ -281,6 +281,9 @@ static void layout_workspace(nfft_plan_s *p)
     // record stay inside the workspace
     p->off_psi = take(rs * ((size_t)M * p->d * (size_t)(2 * p->m + 2) + 64));
     p->off_scratch = take(cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
+    p->spos_used = spread_in_registers(p->geom, p->dbl);
+    if (p->spos_used)
+        p->off_spos = take(4 * (size_t)M);
     p->ws_bytes = off;
 }
 
@@ -393,6 +396,7 @@ Nodes plan_node_view(nfft_plan_s *p)
     nd.chunk_len = reinterpret_cast<int32_t *>(ws + p->off_chunk_len);
     nd.counters = reinterpret_cast<int32_t *>(ws + p->off_counters);
     nd.psi = ws + p->off_psi;
+    nd.spos = p->spos_used ? reinterpret_cast<int32_t *>(ws + p->off_spos) : nullptr;
     nd.M = p->M;
     nd.chunk_cap = p->chunk_cap;
     nd.max_chunks = p->max_chunks;

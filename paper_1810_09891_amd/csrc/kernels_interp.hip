@@ -251,8 +251,13 @@ size_t spread_lds_bytes(const Geom &g, bool dbl)
 {
     const size_t cs = dbl ? 16 : 8;
     if (spread_in_registers(g, dbl)) {
-        // the tile the four waves' columns are summed in
-        return (size_t)g.Ptot * cs;
+        // two batch buffers per wave (factor records of 16 or 8 list entries, rounded up
+        // to whole 1 KB copies, and their values), and the two tiles the waves' columns are
+        // summed in, which reuse that memory
+        const int kb = dbl ? 8 : 16;
+        const int rec = 2 * g.WM * (int)(cs / 2) / 16;
+        const size_t buf = (size_t)((kb * rec + 63) / 64) * 1024 + (dbl ? 1024 : 512);
+        return std::max(4 * 2 * buf, 2 * (size_t)g.Ptot * cs);
     }
     return spread_batch_lds_bytes(g, dbl);
 }

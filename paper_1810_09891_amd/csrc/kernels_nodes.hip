@@ -283,7 +283,8 @@ template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_chunk_s
                     const int k = (int)(keys[i] & 1023ull);
                     const int r0 = (int)(keys[i] >> 10);
                     const int c0 = nd.u[1][first + k] & 31;
-                    nd.spos[first + i] = (k << 10) | (r0 << 5) | c0;
+                    nd.spos[2 * (first + i)] = (k << 10) | (r0 << 5) | c0;
+                    nd.spos[2 * (first + i) + 1] = nd.perm[first + k];
                 }
                 __syncthreads();
             }

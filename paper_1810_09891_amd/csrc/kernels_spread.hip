@@ -1,5 +1,6 @@
 // Spreading (Algorithm 2.2 step 1): LDS tile accumulation per work item and the
 // deterministic fold of the tiles into the grid.  Geometry as in window_common.hpp.
+#include <type_traits>
 #include <utility>
 
 #include "batch_desc.hpp"
@@ -402,120 +403,144 @@ __global__ __launch_bounds__(kBlock) void k_spread_tiles(Geom g, Nodes nd, const
 // so that the padded tile is P0 = B0 + WM - 1 rows by P1 = 32 + WM - 1 <= 64 columns.  Lane
 // c of a wave owns tile column c and keeps all P0 cells of that column in registers.  A
 // node at tile-local cell (r0, c0) adds psi_0[s0] * (psi_1[c - c0] f_j) to rows r0 + s0 of
-// column c: the row factors are the same in every lane (scalar loads, used as scalar
-// operands) and the lane's column factor is one vector load.  The node precomputation
-// lists every work item's nodes by tile row (spos); a wave walks its part of that list
-// with one unrolled update sequence per row, so every register index is a constant and no
-// tile traffic goes through LDS, and it loads the next node's data while it adds the
-// current one.  The four waves of a workgroup take a quarter of the list each; their
-// columns are summed in wave order through one LDS tile when the item is done, so the
-// result is deterministic.
+// column c.  The node precomputation lists every work item's nodes by tile row (spos).  A
+// wave walks its part of the list in small batches with one unrolled update sequence per
+// tile row, so every register index is a constant: per node it reads the row factors (the
+// same address in every lane), its column factor and f_j from LDS and does 2 WM
+// multiply-adds per lane.  The factor records and values of the next batch are copied
+// from global memory straight into LDS (global_load_lds: no registers, asynchronous) while
+// the current batch is walked.  The four waves of a workgroup take a quarter of the list
+// each; their columns are summed in a fixed order through two LDS tiles when the item is
+// done, so the result is deterministic.
 
 // Inputs of the in-register spreading of one plan.
 template <typename T> struct ColsIn {
-    const int32_t *spos, *perm;
+    const int32_t *spos;  // pairs (packed entry, caller index) in tile-row order
     const T *psi;
     const Cplx<T> *f;
 };
 
-// Data of one node for its update.
-template <typename T, int WM> struct ColsNode {
-    T w[WM];    // row factors (wave-uniform)
-    T v;        // psi_1 at this lane's column offset, clamped into the stencil
-    bool in;    // whether that offset lies inside the stencil
-    T fx, fy;   // value f_j (wave-uniform)
+// Geometry of the staged batches of one wave.
+template <typename T, int WM> struct ColsStage {
+    static constexpr int KB = sizeof(T) == 4 ? 16 : 8;          // list entries per batch
+    static constexpr int REC = 2 * WM * (int)sizeof(T) / 16;    // 16-byte pieces of a record
+    static constexpr int NI = (KB * REC + 63) / 64;             // record copies per batch
+    static constexpr int VAL = sizeof(T) == 4 ? 512 : 1024;     // bytes of the staged values
+    static constexpr int NV = sizeof(T) == 4 ? 2 : 1;           // value copies per batch
+    static constexpr int BUF = NI * 1024 + VAL;                 // bytes of one batch buffer
+    static constexpr int COPIES = NI + NV;                      // memory instructions per batch
 };
 
-// acc[R + s] += w[s] * g for the WM rows of a node whose stencil starts at tile row R.  The
-// column mask is applied here, at the use, so that the loads of the next node stay in
-// flight while this one is added.
-template <int R, typename T, int P0, int WM>
-__device__ __forceinline__ void cols_rows(T (&ax)[P0], T (&ay)[P0], const ColsNode<T, WM> &nv)
+using lds_void = __attribute__((address_space(3))) void;
+
+// Copy 4 or 16 bytes per lane from src into LDS at dst + 4 lane or dst + 16 lane.
+__device__ __forceinline__ void to_lds4(const void *src, unsigned char *dst)
 {
-    const T w1 = nv.in ? nv.v : T(0);
-    const T gx = w1 * nv.fx;
-    const T gy = w1 * nv.fy;
+    __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 4, 0, 0);
+}
+__device__ __forceinline__ void to_lds16(const void *src, unsigned char *dst)
+{
+    __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
+}
+
+// Wait until at most N memory instructions of this wave are outstanding (s_waitcnt vmcnt(N),
+// the other counters at their maximum).  Also keeps the compiler from moving LDS reads
+// above it, since it does not see the LDS writes of global_load_lds.
+template <int N> __device__ __forceinline__ void wait_vm()
+{
+    static_assert(N < 16, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xf << 8));
+}
+
+// Start copying batch entries bb .. bb + nbb - 1 (lanes of ex / ey hold the list entries of
+// the wave's current 64) into buf: records of 2 WM factors at buf + k * REC * 16, values
+// f_j after the records.  Every lane takes part in every copy (indices past the batch are
+// clamped to its last entry), so a batch is always exactly COPIES memory instructions.
+template <typename T, int WM>
+__device__ __forceinline__ void cols_issue(int bb, int nbb, int ex, int ey, int first, int lane, const ColsIn<T> &in,
+                                           unsigned char *buf)
+{
+    using S = ColsStage<T, WM>;
+    // records of the item start at a wave-uniform base; a lane adds a 32-bit offset
+    const unsigned char *ibase = reinterpret_cast<const unsigned char *>(in.psi + (int64_t)first * (2 * WM));
 #pragma unroll
-    for (int s = 0; s < WM; ++s) {
-        ax[R + s] += nv.w[s] * gx;
-        ay[R + s] += nv.w[s] * gy;
+    for (int j = 0; j < S::NI; ++j) {
+        const int p = j * 64 + lane;
+        const int e = min(p / S::REC, nbb - 1);
+        const int q = p - (p / S::REC) * S::REC;
+        const int off = __builtin_amdgcn_ds_bpermute((bb + e) * 4, ex) >> 10;
+        to_lds16(ibase + (unsigned)(off * (S::REC * 16) + q * 16), buf + j * 1024);
+    }
+    const int e = min(lane, nbb - 1);
+    const int cidx = __builtin_amdgcn_ds_bpermute((bb + e) * 4, ey);
+    const T *fv = reinterpret_cast<const T *>(in.f + cidx);
+    if constexpr (sizeof(T) == 4) {
+        to_lds4(fv, buf + S::NI * 1024);
+        to_lds4(fv + 1, buf + S::NI * 1024 + 256);
+    } else {
+        to_lds16(fv, buf + S::NI * 1024);
     }
 }
 
-__device__ __forceinline__ float lane_value(float v, int k)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
-__device__ __forceinline__ double lane_value(double v, int k)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Issue the loads of batch entry k (list entry e, value f_j held by lane k) of the item
-// that starts at sorted position `first`.
-template <typename T, int WM>
-__device__ __forceinline__ void cols_load(ColsNode<T, WM> &nv, int e, int k, T fxk, T fyk, int first, int lane,
-                                          const ColsIn<T> &in)
-{
-    const int node = first + (e >> 10);
-    const T *p0 = in.psi + (int64_t)node * (2 * WM);
-#pragma unroll
-    for (int s = 0; s < WM; ++s)
-        nv.w[s] = p0[s];
-    const int s1 = lane - (e & 31);
-    const int sc = min(max(s1, 0), WM - 1);
-    nv.v = p0[WM + sc];
-    nv.in = s1 == sc;
-    nv.fx = lane_value(fxk, k);
-    nv.fy = lane_value(fyk, k);
-}
-
-// Walk the batch entries whose tile row is R (they follow each other), loading entry i + 1
-// while entry i is added.
+// Add the staged batch entries i, i + 1, ... whose tile row is R (they follow each other):
+// acc[R + s] += psi_0[s] * g for the WM rows of each.
 template <int R, typename T, int P0, int WM>
-__device__ __forceinline__ void cols_row(int &i, int nb, int &e, int ek, T fxk, T fyk, ColsNode<T, WM> &cur,
-                                         int first, int lane, const ColsIn<T> &in, T (&ax)[P0], T (&ay)[P0])
+__device__ __forceinline__ void cols_row(int &i, int nb, int bb, int ex, const unsigned char *buf, int lane,
+                                         T (&ax)[P0], T (&ay)[P0])
 {
-    while (i < nb && ((e >> 5) & 31) == R) {
-        ColsNode<T, WM> nxt;
-        int e1 = e;
-        if (i + 1 < nb) {
-            e1 = __builtin_amdgcn_readlane(ek, i + 1);
-            cols_load<T, WM>(nxt, e1, i + 1, fxk, fyk, first, lane, in);
+    using S = ColsStage<T, WM>;
+    for (; i < nb; ++i) {
+        const int e = __builtin_amdgcn_readlane(ex, bb + i);
+        if (((e >> 5) & 31) != R)
+            break;
+        const T *rec = reinterpret_cast<const T *>(buf + i * S::REC * 16);
+        T w[WM];
+#pragma unroll
+        for (int s = 0; s < WM; ++s)
+            w[s] = rec[s];
+        const int s1 = lane - (e & 31);
+        const int sc = min(max(s1, 0), WM - 1);
+        const T v = rec[WM + sc];
+        const T w1 = s1 == sc ? v : T(0);
+        T fx, fy;
+        if constexpr (sizeof(T) == 4) {
+            fx = reinterpret_cast<const T *>(buf + S::NI * 1024)[i];
+            fy = reinterpret_cast<const T *>(buf + S::NI * 1024 + 256)[i];
+        } else {
+            const Cplx<T> fv = reinterpret_cast<const Cplx<T> *>(buf + S::NI * 1024)[i];
+            fx = fv.x;
+            fy = fv.y;
         }
-        cols_rows<R, T, P0, WM>(ax, ay, cur);
-        cur = nxt;
-        e = e1;
-        ++i;
+        const T gx = w1 * fx;
+        const T gy = w1 * fy;
+#pragma unroll
+        for (int s = 0; s < WM; ++s) {
+            ax[R + s] += w[s] * gx;
+            ay[R + s] += w[s] * gy;
+        }
     }
 }
 
 template <typename T, int P0, int WM, int... Rs>
-__device__ __forceinline__ void cols_walk(std::integer_sequence<int, Rs...>, int nb, int ek, T fxk, T fyk, int first,
-                                          int lane, const ColsIn<T> &in, T (&ax)[P0], T (&ay)[P0])
+__device__ __forceinline__ void cols_walk(std::integer_sequence<int, Rs...>, int nb, int bb, int ex,
+                                          const unsigned char *buf, int lane, T (&ax)[P0], T (&ay)[P0])
 {
     int i = 0;
-    int e = __builtin_amdgcn_readlane(ek, 0);
-    ColsNode<T, WM> cur;
-    cols_load<T, WM>(cur, e, 0, fxk, fyk, first, lane, in);
-    // Wait for the first entry's scalar loads here, once per batch: scalar loads complete
-    // out of order, so a load still pending when the walk starts would make every update
-    // wait for all scalar loads in flight, the next entry's included.  (An empty statement
-    // that passes a loaded register through; without memory effects the loads stay scalar.)
-    asm("" : "+s"(cur.w[0]));
-    (cols_row<Rs, T, P0, WM>(i, nb, e, ek, fxk, fyk, cur, first, lane, in, ax, ay), ...);
+    (cols_row<Rs, T, P0, WM>(i, nb, bb, ex, buf, lane, ax, ay), ...);
 }
 
+// Waves per SIMD the register allocation aims at: 4 for complex64 up to m = 8 (at most 128
+// registers; the few values that no longer fit are kept outside the walk), else whatever
+// the accumulators leave.
+template <typename T, int WM> constexpr int cols_waves() { return sizeof(T) == 4 && WM <= 18 ? 4 : 1; }
+
 template <typename T, int B0, int WM>
-__global__ __launch_bounds__(kBlock) void k_spread_cols(const int32_t *__restrict__ counters,
-                                                        const int32_t *__restrict__ chunk_first,
-                                                        const int32_t *__restrict__ chunk_len, ColsIn<T> in,
-                                                        Cplx<T> *__restrict__ scratch)
+__global__ __launch_bounds__(kBlock, (cols_waves<T, WM>())) void k_spread_cols(
+    const int32_t *__restrict__ counters, const int32_t *__restrict__ chunk_first,
+    const int32_t *__restrict__ chunk_len, ColsIn<T> in, Cplx<T> *__restrict__ scratch)
 {
     using C = Cplx<T>;
+    using S = ColsStage<T, WM>;
     constexpr int P0 = B0 + WM - 1;
     constexpr int P1 = 32 + WM - 1;
     constexpr int Ptot = P0 * P1;
@@ -527,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_cols(const int32_t *__restric
         return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned char *bufs = smem_raw + wave * 2 * S::BUF;
     for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
         const int first = chunk_first[c];
         const int len = chunk_len[c];
@@ -538,40 +564,56 @@ __global__ __launch_bounds__(kBlock) void k_spread_cols(const int32_t *__restric
             ax[r] = 0;
             ay[r] = 0;
         }
-        for (int b = lo; b < hi; b += 64) {
-            const int nb = min(64, hi - b);
-            // lane k holds the list entry and the value f_j of batch entry k
-            int ek = 0;
-            T fxk = 0, fyk = 0;
-            if (lane < nb) {
-                ek = in.spos[first + b + lane];
-                const C fv = in.f[in.perm[first + (ek >> 10)]];
-                fxk = fv.x;
-                fyk = fv.y;
+        for (int sb = lo; sb < hi; sb += 64) {
+            // lane k holds list entry sb + k (entries past the wave's part: offset 0, caller 0)
+            const int nsb = min(64, hi - sb);
+            int ex = 0, ey = 0;
+            if (lane < nsb) {
+                const int2 ent = reinterpret_cast<const int2 *>(in.spos)[first + sb + lane];
+                ex = ent.x;
+                ey = ent.y;
             }
-            // the entries of a batch are sorted by row
-            cols_walk<T, P0, WM>(std::make_integer_sequence<int, B0>{}, nb, ek, fxk, fyk, first, lane, in, ax, ay);
-        }
-        for (int w = 0; w < kWaves; ++w) {
-            if (wave == w && lane < P1) {
-#pragma unroll
-                for (int r = 0; r < P0; ++r) {
-                    C v;
-                    v.x = ax[r];
-                    v.y = ay[r];
-                    if (w > 0) {
-                        const C o = lds[r * P1 + lane];
-                        v.x = o.x + v.x;
-                        v.y = o.y + v.y;
-                    }
-                    lds[r * P1 + lane] = v;
+            const int nbat = (nsb + S::KB - 1) / S::KB;
+            cols_issue<T, WM>(0, min(S::KB, nsb), ex, ey, first, lane, in, bufs);
+            for (int j = 0; j < nbat; ++j) {
+                const int bb = j * S::KB;
+                if (j + 1 < nbat) {
+                    cols_issue<T, WM>(bb + S::KB, min(S::KB, nsb - bb - S::KB), ex, ey, first, lane, in,
+                                      bufs + ((j + 1) & 1) * S::BUF);
+                    wait_vm<S::COPIES>();
+                } else {
+                    wait_vm<0>();
                 }
+                // the entries of a batch are sorted by row
+                cols_walk<T, P0, WM>(std::make_integer_sequence<int, B0>{}, min(S::KB, nsb - bb), bb, ex,
+                                     bufs + (j & 1) * S::BUF, lane, ax, ay);
             }
-            __syncthreads();
         }
+        // Sum the four waves' columns: waves 0 and 1 store theirs in tiles A and B, waves 2
+        // and 3 add theirs to A and B, and the workgroup writes A + B to the item's slot:
+        // (w0 + w2) + (w1 + w3), a fixed order.  The tiles reuse the staging memory.
+        __syncthreads();
+        C *half = lds + (wave & 1) * Ptot;
+        if (wave < 2 && lane < P1) {
+#pragma unroll
+            for (int r = 0; r < P0; ++r)
+                half[r * P1 + lane] = C{ax[r], ay[r]};
+        }
+        __syncthreads();
+        if (wave >= 2 && lane < P1) {
+#pragma unroll
+            for (int r = 0; r < P0; ++r) {
+                const C o = half[r * P1 + lane];
+                half[r * P1 + lane] = C{o.x + ax[r], o.y + ay[r]};
+            }
+        }
+        __syncthreads();
         C *slot = scratch + (int64_t)c * Ptot;
-        for (int i = threadIdx.x; i < Ptot; i += kBlock)
-            slot[i] = lds[i];
+        for (int i = threadIdx.x; i < Ptot; i += kBlock) {
+            const C a = lds[i];
+            const C bv = lds[Ptot + i];
+            slot[i] = C{a.x + bv.x, a.y + bv.y};
+        }
         __syncthreads();
     }
 }
@@ -716,7 +758,7 @@ hipError_t spread_cols_typed(const Geom &g, const Nodes &nd, const void *f, void
                              hipStream_t s)
 {
     using C = Cplx<T>;
-    ColsIn<T> in{nd.spos, nd.perm, static_cast<const T *>(nd.psi), static_cast<const C *>(f)};
+    ColsIn<T> in{nd.spos, static_cast<const T *>(nd.psi), static_cast<const C *>(f)};
 #define CALL(W_)                                                                                       \
     {                                                                                                  \
         auto kf = k_spread_cols<T, B0, W_>;                                                            \

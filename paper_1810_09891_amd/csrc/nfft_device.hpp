@@ -223,7 +223,8 @@ struct Nodes {
     int32_t *counters;     // [0] = number of work items, [1] = non-finite node flag
     void *psi;             // window factors per sorted node: [M][d][W] (float or double)
     int32_t *spos;         // d = 2 spreading in registers, else null: per work item, its
-                           // nodes in order of tile row, packed (offset << 10) | (row << 5) | column
+                           // nodes in order of tile row as pairs ((offset << 10) | (row << 5)
+                           // | column, caller index)
     const double *x;       // caller node array (only used while setting nodes)
     int64_t M;
     int chunk_cap;

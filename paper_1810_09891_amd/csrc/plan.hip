@@ -283,7 +283,7 @@ static void layout_workspace(nfft_plan_s *p)
     p->off_scratch = take(cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
     p->spos_used = spread_in_registers(p->geom, p->dbl);
     if (p->spos_used)
-        p->off_spos = take(4 * (size_t)M);
+        p->off_spos = take(8 * (size_t)M);
     p->ws_bytes = off;
 }
 

@@ -216,9 +216,23 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     const int L = p.L, nl = p.nl, pitch = p.pitch;
     C *tw = lds + nl * pitch;  // twiddle table of this pass
     {
+        // four loads in flight per thread before their LDS stores
         const C *twg = static_cast<const C *>(p.tw);
-        for (int i = threadIdx.x; i < L; i += kBlock)
-            tw[i] = twg[i];
+        for (int b = 0; b < L; b += 4 * kBlock) {
+            C tv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = b + threadIdx.x + q * kBlock;
+                if (i < L)
+                    tv[q] = twg[i];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = b + threadIdx.x + q * kBlock;
+                if (i < L)
+                    tw[i] = tv[q];
+            }
+        }
     }
     C *grid = static_cast<C *>(p.grid);
     const int lgL = 31 - __clz(L);
@@ -234,9 +248,10 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     if (threadIdx.x < nl)
         line_info(p, g, threadIdx.x, s_gbase[threadIdx.x], s_cbase[threadIdx.x], s_fac[threadIdx.x]);
     __syncthreads();
-    // ---------------- load
-    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-        int c, i;
+    // Elements idx = base + threadIdx.x + k kBlock, k < SUB, of the nl lines: all loads of a
+    // thread are issued before the first of them is used, so their latencies overlap.
+    constexpr int SUB = VPT < 8 ? VPT : 8;
+    auto line_pos = [&](int idx, int &c, int &i) {
         if (p.rows) {
             c = idx >> lgL;
             i = idx & (L - 1);
@@ -244,24 +259,54 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
             c = idx & (nl - 1);
             i = idx >> lgnl;
         }
-        const int64_t gb = s_gbase[c];
-        C val = C{T(0), T(0)};
-        if (gb >= 0) {
-            if (p.in_mode == 0) {
-                int pc = pos_to_coef(i, Nt, L);
-                if (pc >= 0) {
-                    C a = fin[s_cbase[c] + pc];
-                    double f = s_fac[c] * wt[pc];
-                    val = C{(T)((double)a.x * f), (T)((double)a.y * f)};
-                }
-            } else if (p.in_mode == 1) {
-                if (pos_to_coef(i, Nt, L) >= 0)
-                    val = grid[gb + i * st];
-            } else {
-                val = grid[gb + i * st];
+    };
+    // ---------------- load (every load is issued, from a clamped valid address, and masked
+    // afterwards, so that no branch separates the loads of a thread)
+    for (int base = 0; base < total; base += SUB * kBlock) {
+        C a[SUB];
+        int dst[SUB];
+        bool ok[SUB];
+        if (p.in_mode == 0) {
+            // coefficients times the deconvolution factor (FP64 product, rounded once)
+            double wv[SUB], fc[SUB];
+#pragma unroll
+            for (int k = 0; k < SUB; ++k) {
+                const int idx = base + threadIdx.x + k * kBlock;
+                int c, i;
+                line_pos(min(idx, total - 1), c, i);
+                dst[k] = idx < total ? c * pitch + skew(i) : -1;
+                const int pc = pos_to_coef(i, Nt, L);
+                ok[k] = idx < total && s_gbase[c] >= 0 && pc >= 0;
+                const int pcc = ok[k] ? pc : 0;
+                a[k] = fin[ok[k] ? s_cbase[c] + pc : 0];
+                wv[k] = wt[pcc];
+                fc[k] = s_fac[c];
             }
+#pragma unroll
+            for (int k = 0; k < SUB; ++k) {
+                const double f = fc[k] * wv[k];
+                a[k] = ok[k] ? C{(T)((double)a[k].x * f), (T)((double)a[k].y * f)} : C{T(0), T(0)};
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < SUB; ++k) {
+                const int idx = base + threadIdx.x + k * kBlock;
+                int c, i;
+                line_pos(min(idx, total - 1), c, i);
+                dst[k] = idx < total ? c * pitch + skew(i) : -1;
+                const int64_t gb = s_gbase[c];
+                ok[k] = idx < total && gb >= 0 && (p.in_mode == 2 || pos_to_coef(i, Nt, L) >= 0);
+                a[k] = grid[ok[k] ? gb + i * st : 0];
+            }
+#pragma unroll
+            for (int k = 0; k < SUB; ++k)
+                if (!ok[k])
+                    a[k] = C{T(0), T(0)};
         }
-        lds[c * pitch + skew(i)] = val;
+#pragma unroll
+        for (int k = 0; k < SUB; ++k)
+            if (dst[k] >= 0)
+                lds[dst[k]] = a[k];
     }
     __syncthreads();
 
@@ -278,33 +323,44 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     }
 
     // ---------------- store
-    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-        int c, i;
-        if (p.rows) {
-            c = idx >> lgL;
-            i = idx & (L - 1);
-        } else {
-            c = idx & (nl - 1);
-            i = idx >> lgnl;
-        }
-        const int64_t gb = s_gbase[c];
-        if (gb < 0)
-            continue;
-        C val = lds[c * pitch + skew(i)];
-        if (p.out_mode == 0) {
-            grid[gb + i * st] = val;
-        } else {
-            int pc = pos_to_coef(i, Nt, L);
-            if (pc < 0)
+    if (p.out_mode != 2) {
+        for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+            int c, i;
+            line_pos(idx, c, i);
+            const int64_t gb = s_gbase[c];
+            if (gb < 0 || (p.out_mode == 1 && pos_to_coef(i, Nt, L) < 0))
                 continue;
-            if (p.out_mode == 1) {
-                grid[gb + i * st] = val;
-            } else {
-                double f = s_fac[c] * wt[pc];
-                C o = C{(T)((double)val.x * f), (T)((double)val.y * f)};
+            grid[gb + i * st] = lds[c * pitch + skew(i)];
+        }
+    } else {
+        // coefficients times the deconvolution factor (and the product coefficients when
+        // given): the factor loads of a thread are issued before the first is used
+        for (int base = 0; base < total; base += SUB * kBlock) {
+            C val[SUB], mv[SUB];
+            double wv[SUB], fc[SUB];
+            int dst[SUB];
+#pragma unroll
+            for (int k = 0; k < SUB; ++k) {
+                const int idx = base + threadIdx.x + k * kBlock;
+                int c, i;
+                line_pos(min(idx, total - 1), c, i);
+                const int pc = pos_to_coef(i, Nt, L);
+                const bool ok = idx < total && s_gbase[c] >= 0 && pc >= 0;
+                dst[k] = ok ? s_cbase[c] + pc : -1;
+                val[k] = lds[c * pitch + skew(i)];
+                wv[k] = wt[ok ? pc : 0];
+                fc[k] = s_fac[c];
+                mv[k] = mul ? mul[ok ? dst[k] : 0] : C{T(1), T(0)};
+            }
+#pragma unroll
+            for (int k = 0; k < SUB; ++k) {
+                if (dst[k] < 0)
+                    continue;
+                const double f = fc[k] * wv[k];
+                C o = C{(T)((double)val[k].x * f), (T)((double)val[k].y * f)};
                 if (mul)
-                    o = cmul(o, mul[s_cbase[c] + pc]);
-                fout[s_cbase[c] + pc] = o;
+                    o = cmul(o, mv[k]);
+                fout[dst[k]] = o;
             }
         }
     }

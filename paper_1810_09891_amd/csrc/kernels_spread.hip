@@ -664,6 +664,91 @@ __device__ __forceinline__ Cover cover_range(int l, int k, int n, int lgB, int n
     return cv;
 }
 
+// The (at most two) covering (bin, tile offset) pairs of index l in one dimension, in the
+// order of cover_range over k = -1, 0, 1.
+struct Pairs2 {
+    int b0, o0, b1, o1, n;
+};
+__device__ __forceinline__ Pairs2 cover_pairs2(int l, int n, int lgB, int nb, int m, int P)
+{
+    Pairs2 r{0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = -1; k <= 1; ++k) {
+        const Cover cv = cover_range(l, k, n, lgB, nb, m, P);
+        for (int b = cv.lo; b <= cv.hi; ++b) {
+            const int o = cv.lu - (b << lgB);
+            if (r.n == 0) {
+                r.b0 = b;
+                r.o0 = o;
+            } else {
+                r.b1 = b;
+                r.o1 = o;
+            }
+            ++r.n;
+        }
+    }
+    return r;
+}
+
+// fold_cell for plans whose tiles cover every grid index at most twice per dimension: the
+// 2^D covering bins are found first, then their work-item ranges and the first work item's
+// entries are loaded together (every load issued before the first use), and the sum is
+// taken in the same order as in fold_cell, so the result is the same.
+template <typename T, int D>
+__device__ __forceinline__ void fold_cell2(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ scratch,
+                                           Cplx<T> *__restrict__ grid, int64_t q, const int (&l)[kMaxDim])
+{
+    using C = Cplx<T>;
+    constexpr int NC = 1 << D;
+    Pairs2 pr[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        pr[t] = cover_pairs2(l[t], g.n[t], g.lgB[t], g.nb[t], g.m, g.P[t]);
+    int bin[NC], off[NC];
+    bool ok[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        int b = 0, o = 0;
+        bool v = true;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const int sel = (k >> (D - 1 - t)) & 1;  // dimension 0 outermost
+            v = v && sel < pr[t].n;
+            b = b * g.nb[t] + (sel ? pr[t].b1 : pr[t].b0);
+            o = o * g.P[t] + (sel ? pr[t].o1 : pr[t].o0);
+        }
+        ok[k] = v;
+        bin[k] = v ? b : 0;
+        off[k] = v ? o : 0;
+    }
+    int c0[NC], c1[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        c0[k] = nd.bin_chunk[bin[k]];
+        c1[k] = nd.bin_chunk[bin[k] + 1];
+    }
+    C first[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        ok[k] = ok[k] && c0[k] < c1[k];
+        first[k] = scratch[(int64_t)(ok[k] ? c0[k] : 0) * g.Ptot + off[k]];
+    }
+    T ax = 0, ay = 0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        if (!ok[k])
+            continue;
+        ax += first[k].x;
+        ay += first[k].y;
+        for (int c = c0[k] + 1; c < c1[k]; ++c) {
+            const C v = scratch[(int64_t)c * g.Ptot + off[k]];
+            ax += v.x;
+            ay += v.y;
+        }
+    }
+    grid[q] = C{ax, ay};
+}
+
 // Grid cell q of a plan: sum of the tile entries covering it, in a fixed order.
 template <typename T, int D>
 __device__ __forceinline__ void fold_cell(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ scratch,
@@ -679,6 +764,10 @@ __device__ __forceinline__ void fold_cell(const Geom &g, const Nodes &nd, const 
             l[t] = (int)(rq & (g.n[t] - 1));
             rq >>= (31 - __clz(g.n[t]));
         }
+    }
+    if (g.fold2) {
+        fold_cell2<T, D>(g, nd, scratch, grid, q, l);
+        return;
     }
     T ax = 0, ay = 0;
     auto add_bin = [&](int bin, int off) {

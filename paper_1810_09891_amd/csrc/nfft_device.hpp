@@ -187,6 +187,7 @@ struct Geom {
     int Ptot;          // prod P
     int nbins;
     int window;           // 0 Kaiser-Bessel, 1 Gaussian
+    int fold2;            // every grid index is covered by at most 2 tiles per dimension
     double b[kMaxDim];    // window shape per dimension
     double emb[kMaxDim];  // 1 / (factor the device window is divided by): e^{-b m} (Kaiser-Bessel),
                           // (pi b)^{1/2} (Gaussian)

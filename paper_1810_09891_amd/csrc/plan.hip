@@ -93,9 +93,14 @@ static int choose_bins(nfft_plan_s *p)
         g.Ptot *= g.P[t];
         g.nbins *= g.nb[t];
     }
-    for (int t = 0; t < d; ++t)
-        if (fold_max_pairs(g, t) > kFoldMaxPairs)
+    g.fold2 = 1;
+    for (int t = 0; t < d; ++t) {
+        const int pairs = fold_max_pairs(g, t);
+        if (pairs > kFoldMaxPairs)
             return NFFT_ERR_UNSUPPORTED;
+        if (pairs > 2)
+            g.fold2 = 0;
+    }
     p->lds_window = lds_of(B);
     return NFFT_OK;
 }

@@ -18,37 +18,50 @@ template <typename T, int D> __device__ __forceinline__ void bin_coords(const Ge
 }
 
 // Stage the padded tile of bin `bc` into LDS (complex, row-major P_0 x ... x P_{d-1}).
+// A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < 8: all eight loads
+// (entries past the tile read entry 0) are issued before the first LDS store, so their
+// latencies overlap.
 template <typename T, int D>
 __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
 {
+    using C = Cplx<T>;
+    constexpr int K = 8;
     int o[kMaxDim];
 #pragma unroll
     for (int t = 0; t < D; ++t)
         o[t] = (bc[t] << g.lgB[t]) - g.m + g.n[t];  // + n keeps it non-negative
-    if constexpr (D == 1) {
-        for (int i = threadIdx.x; i < g.P[0]; i += kBlock)
-            tile[i] = grid[(o[0] + i) & (g.n[0] - 1)];
-    } else if constexpr (D == 2) {
-        const int P1 = g.P[1];
-        for (int idx = threadIdx.x; idx < g.Ptot; idx += kBlock) {
-            int i0 = idx / P1;
-            int i1 = idx - i0 * P1;
-            int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
-            int c1 = (o[1] + i1) & (g.n[1] - 1);
-            tile[idx] = grid[r0 * g.n[1] + c1];
+    const int Ptot = g.Ptot;
+    auto src = [&](int idx) -> int64_t {
+        if constexpr (D == 1) {
+            return (o[0] + idx) & (g.n[0] - 1);
+        } else if constexpr (D == 2) {
+            const int i0 = idx / g.P[1];
+            const int i1 = idx - i0 * g.P[1];
+            const int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
+            return r0 * g.n[1] + ((o[1] + i1) & (g.n[1] - 1));
+        } else {
+            const int P12 = g.P[1] * g.P[2];
+            const int i0 = idx / P12;
+            const int rem = idx - i0 * P12;
+            const int i1 = rem / g.P[2];
+            const int i2 = rem - i1 * g.P[2];
+            const int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
+            const int64_t r1 = (o[1] + i1) & (g.n[1] - 1);
+            return (r0 * g.n[1] + r1) * g.n[2] + ((o[2] + i2) & (g.n[2] - 1));
         }
-    } else {
-        const int P1 = g.P[1], P2 = g.P[2];
-        const int P12 = P1 * P2;
-        for (int idx = threadIdx.x; idx < g.Ptot; idx += kBlock) {
-            int i0 = idx / P12;
-            int rem = idx - i0 * P12;
-            int i1 = rem / P2;
-            int i2 = rem - i1 * P2;
-            int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
-            int64_t r1 = (o[1] + i1) & (g.n[1] - 1);
-            int c2 = (o[2] + i2) & (g.n[2] - 1);
-            tile[idx] = grid[(r0 * g.n[1] + r1) * g.n[2] + c2];
+    };
+    for (int base = 0; base < Ptot; base += K * kBlock) {
+        C v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = base + threadIdx.x + k * kBlock;
+            v[k] = grid[src(idx < Ptot ? idx : 0)];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = base + threadIdx.x + k * kBlock;
+            if (idx < Ptot)
+                tile[idx] = v[k];
         }
     }
 }

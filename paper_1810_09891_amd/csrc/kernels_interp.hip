@@ -36,6 +36,28 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
     const int len = nd.chunk_len[c];
     int bc[kMaxDim];
     bin_coords<T, D>(g, bin, bc);
+    // Factors of the dimensions whose factors are held in registers: all of them, except
+    // dimension 0 of the 3-D complex128 kernels with more than 14 points, which read theirs
+    // plane by plane.
+    constexpr int T0 = (D == 3 && !(sizeof(T) == 4 || WM <= 14)) ? 1 : 0;
+    // Cell indices and window factors (aligned pairs; W and WM are even and the factor
+    // table is padded past its end) of the thread's next node.  The first node's are
+    // loaded before the tile is staged, so that both loads are in flight together.
+    int ul[kMaxDim];
+    Pair<T> raw[D][WM / 2];
+    auto load_node = [&](int node) {
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
+        const Pair<T> *p2 = reinterpret_cast<const Pair<T> *>(psi + (int64_t)node * dW);
+#pragma unroll
+        for (int t = T0; t < D; ++t)
+#pragma unroll
+            for (int s = 0; s < WM / 2; ++s)
+                raw[t][s] = p2[t * (W / 2) + s];
+    };
+    if ((int)threadIdx.x < len)
+        load_node(first + threadIdx.x);
     stage_tile<T, D>(g, bc, grid, tile);
     __syncthreads();
     // Thread t takes nodes t, t + 256, ...: the nodes are dealt round-robin over the bank
@@ -43,17 +65,13 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
     for (int i = threadIdx.x; i < len; i += kBlock) {
         const int node = first + i;
         const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
-        int ul[kMaxDim];
-#pragma unroll
-        for (int t = 0; t < D; ++t)
-            ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
-        // window factors of dimension t at the WM compiled points (zero beyond W), read as
-        // aligned pairs (W and WM are even; the factor table is padded past its end)
+        if (i != (int)threadIdx.x)
+            load_node(node);
+        // window factors of dimension t at the WM compiled points (zero beyond W)
         auto factors = [&](int t, T *w) {
-            const Pair<T> *p2 = reinterpret_cast<const Pair<T> *>(pw + t * W);
 #pragma unroll
             for (int s = 0; s < WM / 2; ++s) {
-                const Pair<T> v = p2[s];
+                const Pair<T> v = raw[t][s];
                 w[2 * s] = 2 * s < W ? v.x : T(0);
                 w[2 * s + 1] = 2 * s + 1 < W ? v.y : T(0);
             }

@@ -37,10 +37,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NFFT fwd+adj nonuniform points/s at stated rel-ℓ2 error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# LDS ceilings of one MI355X measured with paper_1810_09891_amd/lib/lds_bw (conflict-free
-# 8-byte read-add-write and 8-byte reads, all 256 CUs): the bound of the window kernels
-LDS_RMW8_PEAK_GBS = 43480.0
+# LDS read ceiling of one MI355X measured with paper_1810_09891_amd/lib/lds_bw (conflict-free
+# 8-byte reads, all 256 CUs): the bound of the interpolation kernel (an 8-byte LDS read
+# per stencil point)
 LDS_READ8_PEAK_GBS = 60060.0
+# Published FP32 vector peak of the MI355X (256 CUs, 2.4 GHz, packed FP32 counted): the
+# ceiling of the 2-D spreading kernel that keeps tile columns in registers (4 flops, two
+# multiply-adds, per stencil point).  Packed FP32 instructions are not generated, which
+# halves the rate this code can reach.
+FP32_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2_512_c64_m8.json")
 
 
@@ -80,8 +85,10 @@ def algorithmic_bytes(name, d, N, n, M, cbytes):
 
 
 # rocprofv3 kernel names of the library's launch labels (the FFT passes share one kernel)
-ROCPROF_NAME = {"interp": "k_interp_nodes", "spread_tiles": "k_spread_tiles", "spread_fold": "k_fold",
-                "grad_x": "k_grad_x"}
+# kernel names under rocprofv3 of each profiling label, in order of preference (2-D
+# spreading runs k_spread_cols when the plan allows it, else k_spread_tiles)
+ROCPROF_NAME = {"interp": ("k_interp_nodes",), "spread_tiles": ("k_spread_cols", "k_spread_tiles"),
+                "spread_fold": ("k_fold",), "grad_x": ("k_grad_x",)}
 
 
 class Case:
@@ -496,7 +503,11 @@ def main():
         traffic = None
         if os.path.exists(TRAFFIC_FILE):
             tr = json.load(open(TRAFFIC_FILE))
-            entry = tr.get("kernels", {}).get(ROCPROF_NAME.get(dom, ""), None)
+            entry = None
+            for kname in ROCPROF_NAME.get(dom, ()):
+                entry = tr.get("kernels", {}).get(kname)
+                if entry is not None:
+                    break
             if entry is not None and "bytes_per_launch" in entry and tr.get("source_hash") == source_hash():
                 traffic = entry["bytes_per_launch"]
         roofline = {
@@ -510,17 +521,20 @@ def main():
             "algorithmic_bytes": alg,
             "avg_launch_ms": round(dom_ms, 5),
         }
-        # the window kernels are bound by LDS, not HBM: one read-add-write (spreading) or
-        # read (interpolation) of an 8-byte cell per stencil point, against the measured
-        # LDS ceilings
+        # The window kernels are not HBM-bound: interpolation reads an 8-byte LDS cell per
+        # stencil point (against the measured LDS read ceiling); 2-D spreading in registers
+        # does two FP32 multiply-adds per stencil point (against the FP32 vector peak)
         stencil = M * (2 * 8 + 2) ** 2
-        lds = {}
-        for k, per, peak in (("spread_tiles", 16, LDS_RMW8_PEAK_GBS), ("interp", 8, LDS_READ8_PEAK_GBS)):
-            if k in kt:
-                a = stencil * per / (kt[k][0] * 1e-3) / 1e9
-                lds[k] = {"achieved": round(a, 1), "peak": peak, "unit": "GB/s", "frac": round(a / peak, 4),
-                          "lds_bytes": stencil * per}
-        roofline["lds"] = lds
+        sec = {}
+        if "spread_tiles" in kt:
+            a = stencil * 4 / (kt["spread_tiles"][0] * 1e-3) / 1e12
+            sec["spread_tiles"] = {"bound": "alu", "achieved": round(a, 3), "peak": FP32_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(a / FP32_PEAK_TFLOPS, 4), "flops": stencil * 4}
+        if "interp" in kt:
+            a = stencil * 8 / (kt["interp"][0] * 1e-3) / 1e9
+            sec["interp"] = {"bound": "lds", "achieved": round(a, 1), "peak": LDS_READ8_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(a / LDS_READ8_PEAK_GBS, 4), "lds_bytes": stencil * 8}
+        roofline["secondary"] = sec
         for k, (avg, cnt) in sorted(kt.items()):
             bts = algorithmic_bytes(k, 2, N, n, M, cb)
             per_kernel[k] = {"avg_ms": round(avg, 5), "launches": cnt, "algorithmic_bytes": bts,

@@ -49,6 +49,7 @@ struct Group {
     size_t lds_fwd[kMaxDim] = {0, 0, 0}, lds_adj[kMaxDim] = {0, 0, 0};
     int64_t items_fwd[kMaxDim] = {0, 0, 0}, items_adj[kMaxDim] = {0, 0, 0};
     size_t lds_interp = 0, lds_spread = 0;
+    bool cols = false;  // every plan's 2-D spreading runs in registers
     int64_t chunk_bound = 0, fold_items = 0;
     std::vector<PlanDev> table;
 };
@@ -89,6 +90,9 @@ void build_group(nfft_batch_s *b, Group &G)
     }
     G.lds_interp = G.lds_spread = 0;
     G.chunk_bound = G.fold_items = 0;
+    G.cols = !G.idx.empty();
+    for (int i : G.idx)
+        G.cols = G.cols && b->plans[(size_t)i]->spos_used;
     for (size_t i = 0; i < G.idx.size(); ++i) {
         nfft_plan_s *p = b->plans[(size_t)G.idx[i]];
         PlanDev &pd = G.table[i];
@@ -126,7 +130,8 @@ void build_group(nfft_batch_s *b, Group &G)
             }
         }
         G.lds_interp = std::max(G.lds_interp, interp_lds_bytes(p->geom, p->dbl));
-        G.lds_spread = std::max(G.lds_spread, spread_batch_lds_bytes(p->geom, p->dbl));
+        G.lds_spread = std::max(G.lds_spread, G.cols ? spread_lds_bytes(p->geom, p->dbl)
+                                                      : spread_batch_lds_bytes(p->geom, p->dbl));
         G.chunk_bound += p->max_chunks;
         G.fold_items += (p->ngrid + kBlock - 1) / kBlock;
     }
@@ -195,8 +200,12 @@ int run_interp(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream
 int run_spread(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream_t s)
 {
     const int blocks = blocks_for(b, G.params[kKSpread], G.chunk_bound);
-    BCHECK(launch_spread_batch(table_of(b, G), (int)G.idx.size(), ptrs, queue_of(b, G, 1), G.d, G.dbl, G.WM, blocks,
-                               G.lds_spread, s));
+    if (G.cols)
+        BCHECK(launch_spread_cols_batch(table_of(b, G), (int)G.idx.size(), ptrs, queue_of(b, G, 1), G.dbl, G.WM,
+                                        blocks, G.lds_spread, s));
+    else
+        BCHECK(launch_spread_batch(table_of(b, G), (int)G.idx.size(), ptrs, queue_of(b, G, 1), G.d, G.dbl, G.WM,
+                                   blocks, G.lds_spread, s));
     return NFFT_OK;
 }
 

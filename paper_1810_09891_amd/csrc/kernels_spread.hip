@@ -534,88 +534,123 @@ __device__ __forceinline__ void cols_walk(std::integer_sequence<int, Rs...>, int
 // the accumulators leave.
 template <typename T, int WM> constexpr int cols_waves() { return sizeof(T) == 4 && WM <= 18 ? 4 : 1; }
 
+// One work item (nodes first .. first + len - 1 of one bin) of a plan: accumulate in
+// registers, then write the summed tile to the item's slot.  Called by all threads of the
+// workgroup (it has barriers).
 template <typename T, int B0, int WM>
-__global__ __launch_bounds__(kBlock, (cols_waves<T, WM>())) void k_spread_cols(
-    const int32_t *__restrict__ counters, const int32_t *__restrict__ chunk_first,
-    const int32_t *__restrict__ chunk_len, ColsIn<T> in, Cplx<T> *__restrict__ scratch)
+__device__ __forceinline__ void cols_item(int first, int len, const ColsIn<T> &in, Cplx<T> *__restrict__ slot,
+                                          unsigned char *smem)
 {
     using C = Cplx<T>;
     using S = ColsStage<T, WM>;
     constexpr int P0 = B0 + WM - 1;
     constexpr int P1 = 32 + WM - 1;
     constexpr int Ptot = P0 * P1;
+    C *lds = reinterpret_cast<C *>(smem);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned char *bufs = smem + wave * 2 * S::BUF;
+    const int lo = (len * wave) >> 2;
+    const int hi = (len * (wave + 1)) >> 2;
+    T ax[P0], ay[P0];
+#pragma unroll
+    for (int r = 0; r < P0; ++r) {
+        ax[r] = 0;
+        ay[r] = 0;
+    }
+    for (int sb = lo; sb < hi; sb += 64) {
+        // lane k holds list entry sb + k (entries past the wave's part: offset 0, caller 0)
+        const int nsb = min(64, hi - sb);
+        int ex = 0, ey = 0;
+        if (lane < nsb) {
+            const int2 ent = reinterpret_cast<const int2 *>(in.spos)[first + sb + lane];
+            ex = ent.x;
+            ey = ent.y;
+        }
+        const int nbat = (nsb + S::KB - 1) / S::KB;
+        cols_issue<T, WM>(0, min(S::KB, nsb), ex, ey, first, lane, in, bufs);
+        for (int j = 0; j < nbat; ++j) {
+            const int bb = j * S::KB;
+            if (j + 1 < nbat) {
+                cols_issue<T, WM>(bb + S::KB, min(S::KB, nsb - bb - S::KB), ex, ey, first, lane, in,
+                                  bufs + ((j + 1) & 1) * S::BUF);
+                wait_vm<S::COPIES>();
+            } else {
+                wait_vm<0>();
+            }
+            // the entries of a batch are sorted by row
+            cols_walk<T, P0, WM>(std::make_integer_sequence<int, B0>{}, min(S::KB, nsb - bb), bb, ex,
+                                 bufs + (j & 1) * S::BUF, lane, ax, ay);
+        }
+    }
+    // Sum the four waves' columns: waves 0 and 1 store theirs in tiles A and B, waves 2
+    // and 3 add theirs to A and B, and the workgroup writes A + B to the item's slot:
+    // (w0 + w2) + (w1 + w3), a fixed order.  The tiles reuse the staging memory.
+    __syncthreads();
+    C *half = lds + (wave & 1) * Ptot;
+    if (wave < 2 && lane < P1) {
+#pragma unroll
+        for (int r = 0; r < P0; ++r)
+            half[r * P1 + lane] = C{ax[r], ay[r]};
+    }
+    __syncthreads();
+    if (wave >= 2 && lane < P1) {
+#pragma unroll
+        for (int r = 0; r < P0; ++r) {
+            const C o = half[r * P1 + lane];
+            half[r * P1 + lane] = C{o.x + ax[r], o.y + ay[r]};
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Ptot; i += kBlock) {
+        const C a = lds[i];
+        const C bv = lds[Ptot + i];
+        slot[i] = C{a.x + bv.x, a.y + bv.y};
+    }
+    __syncthreads();
+}
+
+template <typename T, int B0, int WM>
+__global__ __launch_bounds__(kBlock, (cols_waves<T, WM>())) void k_spread_cols(
+    const int32_t *__restrict__ counters, const int32_t *__restrict__ chunk_first,
+    const int32_t *__restrict__ chunk_len, ColsIn<T> in, Cplx<T> *__restrict__ scratch)
+{
+    constexpr int Ptot = (B0 + WM - 1) * (32 + WM - 1);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *lds = reinterpret_cast<C *>(smem_raw);
     const int nchunks = counters[0];
     const int nwg = min((int)gridDim.x, nchunks);
     if ((int)blockIdx.x >= nwg)
         return;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    unsigned char *bufs = smem_raw + wave * 2 * S::BUF;
-    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg) {
-        const int first = chunk_first[c];
-        const int len = chunk_len[c];
-        const int lo = (len * wave) >> 2;
-        const int hi = (len * (wave + 1)) >> 2;
-        T ax[P0], ay[P0];
-#pragma unroll
-        for (int r = 0; r < P0; ++r) {
-            ax[r] = 0;
-            ay[r] = 0;
-        }
-        for (int sb = lo; sb < hi; sb += 64) {
-            // lane k holds list entry sb + k (entries past the wave's part: offset 0, caller 0)
-            const int nsb = min(64, hi - sb);
-            int ex = 0, ey = 0;
-            if (lane < nsb) {
-                const int2 ent = reinterpret_cast<const int2 *>(in.spos)[first + sb + lane];
-                ex = ent.x;
-                ey = ent.y;
-            }
-            const int nbat = (nsb + S::KB - 1) / S::KB;
-            cols_issue<T, WM>(0, min(S::KB, nsb), ex, ey, first, lane, in, bufs);
-            for (int j = 0; j < nbat; ++j) {
-                const int bb = j * S::KB;
-                if (j + 1 < nbat) {
-                    cols_issue<T, WM>(bb + S::KB, min(S::KB, nsb - bb - S::KB), ex, ey, first, lane, in,
-                                      bufs + ((j + 1) & 1) * S::BUF);
-                    wait_vm<S::COPIES>();
-                } else {
-                    wait_vm<0>();
-                }
-                // the entries of a batch are sorted by row
-                cols_walk<T, P0, WM>(std::make_integer_sequence<int, B0>{}, min(S::KB, nsb - bb), bb, ex,
-                                     bufs + (j & 1) * S::BUF, lane, ax, ay);
-            }
-        }
-        // Sum the four waves' columns: waves 0 and 1 store theirs in tiles A and B, waves 2
-        // and 3 add theirs to A and B, and the workgroup writes A + B to the item's slot:
-        // (w0 + w2) + (w1 + w3), a fixed order.  The tiles reuse the staging memory.
-        __syncthreads();
-        C *half = lds + (wave & 1) * Ptot;
-        if (wave < 2 && lane < P1) {
-#pragma unroll
-            for (int r = 0; r < P0; ++r)
-                half[r * P1 + lane] = C{ax[r], ay[r]};
-        }
-        __syncthreads();
-        if (wave >= 2 && lane < P1) {
-#pragma unroll
-            for (int r = 0; r < P0; ++r) {
-                const C o = half[r * P1 + lane];
-                half[r * P1 + lane] = C{o.x + ax[r], o.y + ay[r]};
-            }
-        }
-        __syncthreads();
-        C *slot = scratch + (int64_t)c * Ptot;
-        for (int i = threadIdx.x; i < Ptot; i += kBlock) {
-            const C a = lds[i];
-            const C bv = lds[Ptot + i];
-            slot[i] = C{a.x + bv.x, a.y + bv.y};
-        }
-        __syncthreads();
+    for (int c = xcd_local_id(blockIdx.x, nwg); c < nchunks; c += nwg)
+        cols_item<T, B0, WM>(chunk_first[c], chunk_len[c], in, scratch + (int64_t)c * Ptot, smem_raw);
+}
+
+// All plans of a batch whose 2-D spreading runs in registers, items handed out by the
+// dynamic queue.
+template <typename T, int B0, int WM>
+__global__ __launch_bounds__(kBlock, (cols_waves<T, WM>())) void k_spread_cols_batch(
+    const PlanDev *__restrict__ plans, int count, BatchPtrs ptrs, int *queue)
+{
+    using C = Cplx<T>;
+    constexpr int Ptot = (B0 + WM - 1) * (32 + WM - 1);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_cnt[kMaxBatch];
+    __shared__ int s_prefix[kMaxBatch + 1];
+    __shared__ int s_item;
+    if ((int)threadIdx.x < count)
+        s_cnt[threadIdx.x] = plans[threadIdx.x].nd.counters[0];
+    __syncthreads();
+    batch_prefix(s_prefix, count, s_cnt);
+    const int total = s_prefix[count];
+    for (int it = queue_next(queue, &s_item); it < total; it = queue_next(queue, &s_item)) {
+        const int p = batch_find(s_prefix, count, it);
+        const PlanDev &pd = plans[p];
+        const int c = it - s_prefix[p];
+        const ColsIn<T> in{pd.nd.spos, static_cast<const T *>(pd.nd.psi), static_cast<const C *>(ptrs.in[p])};
+        cols_item<T, B0, WM>(pd.nd.chunk_first[c], pd.nd.chunk_len[c], in,
+                             static_cast<C *>(pd.scratch) + (int64_t)c * Ptot, smem_raw);
     }
+    queue_done(queue);
 }
 
 // All plans of a batch in one launch, items handed out by the dynamic queue.
@@ -919,6 +954,20 @@ hipError_t spread_batch_typed(const PlanDev *plans, int count, const BatchPtrs &
 #undef CALL
     return hipGetLastError();
 }
+template <typename T, int B0>
+hipError_t spread_cols_batch_typed(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int WMv,
+                                   int blocks, size_t lds, hipStream_t s)
+{
+#define CALL(W_)                                                                                       \
+    {                                                                                                  \
+        auto kf = k_spread_cols_batch<T, B0, W_>;                                                      \
+        (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, plans, count, ptrs, queue);         \
+    }
+    NFFT_WM_SWITCH(WMv, CALL)
+#undef CALL
+    return hipGetLastError();
+}
 template <typename T, int D> hipError_t fold_batch_typed(const PlanDev *plans, int count, int blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_fold_batch<T, D>), dim3(blocks), dim3(kBlock), 0, s, plans, count);
@@ -938,6 +987,14 @@ hipError_t launch_spread_batch(const PlanDev *plans, int count, const BatchPtrs 
     case 7: return spread_batch_typed<double, 3>(plans, count, ptrs, queue, WMv, blocks, lds, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_spread_cols_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, bool dbl,
+                                    int WMv, int blocks, size_t lds, hipStream_t s)
+{
+    if (dbl)
+        return spread_cols_batch_typed<double, 16>(plans, count, ptrs, queue, WMv, blocks, lds, s);
+    return spread_cols_batch_typed<float, 32>(plans, count, ptrs, queue, WMv, blocks, lds, s);
 }
 
 hipError_t launch_fold_batch(const PlanDev *plans, int count, int d, bool dbl, int blocks, hipStream_t s)

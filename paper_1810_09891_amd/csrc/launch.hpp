@@ -87,6 +87,10 @@ hipError_t launch_interp_batch(const PlanDev *plans, int count, const BatchPtrs 
                                bool dbl, int WMv, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_spread_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,
                                bool dbl, int WMv, int blocks, size_t lds, hipStream_t s);
+// Batched 2-D spreading with tile columns in registers (every plan of the group must satisfy
+// spread_in_registers; LDS as spread_lds_bytes).
+hipError_t launch_spread_cols_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, bool dbl,
+                                    int WMv, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_fold_batch(const PlanDev *plans, int count, int d, bool dbl, int blocks, hipStream_t s);
 
 // ------------------------------------------------------------------ direct sums

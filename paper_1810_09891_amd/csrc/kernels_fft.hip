@@ -215,20 +215,22 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     using C = Cplx<T>;
     const int L = p.L, nl = p.nl, pitch = p.pitch;
     C *tw = lds + nl * pitch;  // twiddle table of this pass
-    {
-        // four loads in flight per thread before their LDS stores
+    if (threadIdx.x >= 64) {
+        // waves 1-3 copy the twiddles (four loads in flight per thread before their LDS
+        // stores) while wave 0 sets up the lines below, so the two latencies overlap
+        constexpr int kCopy = kBlock - 64;
+        const int tid = threadIdx.x - 64;
         const C *twg = static_cast<const C *>(p.tw);
-        for (int b = 0; b < L; b += 4 * kBlock) {
+        for (int b = 0; b < L; b += 4 * kCopy) {
             C tv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = b + threadIdx.x + q * kBlock;
-                if (i < L)
-                    tv[q] = twg[i];
+                const int i = b + tid + q * kCopy;
+                tv[q] = twg[i < L ? i : 0];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = b + threadIdx.x + q * kBlock;
+                const int i = b + tid + q * kCopy;
                 if (i < L)
                     tw[i] = tv[q];
             }

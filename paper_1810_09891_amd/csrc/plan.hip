@@ -50,6 +50,10 @@ static int choose_bins(nfft_plan_s *p)
     const int start = d == 1 ? 512 : d == 2 ? 32 : 8;
     for (int t = 0; t < d; ++t)
         B[t] = (int)std::min<int64_t>(start, p->n[t]);
+    // complex128 2-D plans with even m: 16-row bins, the height at which the spreading kernel
+    // that keeps tile columns in registers fits its accumulators
+    if (d == 2 && p->dbl && 2 * p->m + 2 == p->WM)
+        B[0] = std::min(B[0], 16);
     auto lds_of = [&](const int *b) {
         size_t v = cs;
         for (int t = 0; t < d; ++t)

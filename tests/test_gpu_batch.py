@@ -105,6 +105,24 @@ def test_batch_every_launch_shape_gives_the_same_result():
             assert rel_l2(hp[i], hb[i]) <= SAME[C64], (cand, i)
 
 
+def test_batch_group_mixing_spreading_kernels():
+    """One launch group (d = 2, m = 4, complex64) with a plan whose bins are too small for
+    the spreading kernel that keeps tile columns in registers (N = 8^2, 16-cell bins) next
+    to plans that would use it alone: the group spreads with the tile kernel, and every plan
+    matches its own transforms and the oracle."""
+    announce("batch mixed spreading kernels")
+    specs = [((64, 64), 3000, 4, "uniform"), ((8, 8), 300, 4, "uniform"), ((8, 32), 500, 4, "clustered")]
+    plans, cases = setup_plans(specs, C64, seed0=140)
+    b = Batch(plans)
+    assert b.info.groups == 1
+    fb, hb = batched(b, cases, C64)
+    fp, hp = per_plan(plans, cases, C64)
+    for i, (p, c) in enumerate(zip(plans, cases)):
+        assert rel_l2(fp[i], fb[i]) <= SAME[C64], i
+        assert rel_l2(hp[i], hb[i]) <= SAME[C64], i
+        assert rel_l2(O.nfft_adjoint(c["x"], c["f"], p.N, p.n, p.m), hb[i]) < TOL[C64], i
+
+
 def test_batch_more_than_64_plans():
     announce("batch 70 plans")
     r = np.random.default_rng(11)

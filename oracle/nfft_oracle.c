@@ -150,20 +150,120 @@ double or_gauss_phihat(long k, long n, double b)
     return exp(-b * a * a) / (double)n;
 }
 
-/* Window used by the NFFT functions below: 0 Kaiser-Bessel (R1), 1 Gaussian. */
+/* Cardinal B-spline N_k of order k (degree k - 1, knots 0, 1, ..., k) at x, by the
+ * recursion N_q(x) = (x N_{q-1}(x) + (q - x) N_{q-1}(x - 1)) / (q - 1) with N_1 the indicator
+ * of [0, 1), run over the k values N_q(t + j), j = 0..q-1, that are nonzero at the
+ * fractional part t of x (de Boor's triangle; every term is a nonnegative combination, so
+ * there is no cancellation). */
+#define OR_MAXK 64
+double or_bspline_n(int k, double x)
+{
+    if (!(x >= 0.0) || x >= (double)k || k < 1 || k > OR_MAXK)
+        return 0.0;
+    const double fl = floor(x);
+    const double t = x - fl;
+    const int j = (int)fl;
+    double b[OR_MAXK + 1];
+    for (int i = 0; i <= k; ++i)
+        b[i] = 0.0;
+    b[0] = 1.0;
+    for (int q = 2; q <= k; ++q) {
+        double nb[OR_MAXK + 1];
+        for (int i = 0; i < q; ++i) {
+            const double cur = i < q - 1 ? b[i] : 0.0;
+            const double prev = i > 0 ? b[i - 1] : 0.0;
+            nb[i] = ((t + (double)i) * cur + ((double)q - t - (double)i) * prev) / (double)(q - 1);
+        }
+        for (int i = 0; i < q; ++i)
+            b[i] = nb[i];
+    }
+    return b[j];
+}
+
+/* B-spline window (another window the NFFT library of Sec. 3 can be configured with; the
+ * standard pair of the NFFT literature): in the grid variable z,
+ *   phi(z) = M_2m(z) = N_2m(z + m)  (centred B-spline of order 2m, support [-m, m]),
+ *   phihat(k) = (1/n) (sin(pi k / n) / (pi k / n))^(2m). */
+double or_bspline_phi(double z, int m) { return or_bspline_n(2 * m, z + (double)m); }
+double or_bspline_dphi(double z, int m)
+{
+    /* d/dx N_k(x) = N_{k-1}(x) - N_{k-1}(x - 1) */
+    return or_bspline_n(2 * m - 1, z + (double)m) - or_bspline_n(2 * m - 1, z + (double)m - 1.0);
+}
+double or_bspline_phihat(long k, long n, int m)
+{
+    if (k == 0)
+        return 1.0 / (double)n;
+    const double a = 3.14159265358979323846 * (double)k / (double)n;
+    return pow(sin(a) / a, 2.0 * (double)m) / (double)n;
+}
+
+/* Sinc window (the fourth configurable window; standard pair): with
+ * a = pi (2 - 1/sigma) / (2m), sigma = n / N,
+ *   phi(z) = (sin(a z) / (a z))^(2m),
+ *   phihat(k) = (1/n) (pi / a) M_2m(pi k / (n a)),
+ * the 2m-fold convolution of the box that is the transform of sin(a z)/(a z). */
+double or_sinc_a(long N, long n, int m)
+{
+    const double sigma = (double)n / (double)N;
+    return 3.14159265358979323846 * (2.0 - 1.0 / sigma) / (2.0 * (double)m);
+}
+static double or_sinc1(double x) { return fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : sin(x) / x; }
+double or_sinc_phi(double z, int m, double a) { return pow(or_sinc1(a * z), 2.0 * (double)m); }
+double or_sinc_dphi(double z, int m, double a)
+{
+    const double x = a * z;
+    /* d/dx sin(x)/x = (x cos x - sin x) / x^2, about -x/3 near 0 */
+    const double ds = fabs(x) < 1e-4 ? -x / 3.0 : (x * cos(x) - sin(x)) / (x * x);
+    return 2.0 * (double)m * pow(or_sinc1(x), 2.0 * (double)m - 1.0) * ds * a;
+}
+double or_sinc_phihat(long k, long n, int m, double a)
+{
+    const double u = 3.14159265358979323846 * (double)k / ((double)n * a);
+    return (3.14159265358979323846 / a) * or_bspline_n(2 * m, u + (double)m) / (double)n;
+}
+
+/* Window used by the NFFT functions below: 0 Kaiser-Bessel (R1), 1 Gaussian, 2 B-spline,
+ * 3 sinc. */
 static int or_window = 0;
 void or_set_window(int w) { or_window = w; }
 int or_get_window(void) { return or_window; }
 
-static double win_b(long N, long n, int m) { return or_window == 1 ? or_gauss_b(N, n, m) : or_kb_b(N, n); }
-static double win_phi(double z, int m, double b) { return or_window == 1 ? or_gauss_phi(z, b) : or_kb_phi(z, m, b); }
+static double win_b(long N, long n, int m)
+{
+    switch (or_window) {
+    case 1: return or_gauss_b(N, n, m);
+    case 2: return 0.0;
+    case 3: return or_sinc_a(N, n, m);
+    default: return or_kb_b(N, n);
+    }
+}
+static double win_phi(double z, int m, double b)
+{
+    switch (or_window) {
+    case 1: return or_gauss_phi(z, b);
+    case 2: return or_bspline_phi(z, m);
+    case 3: return or_sinc_phi(z, m, b);
+    default: return or_kb_phi(z, m, b);
+    }
+}
 static double win_dphi(double z, int m, double b)
 {
-    return or_window == 1 ? or_gauss_dphi(z, b) : or_kb_dphi(z, m, b);
+    switch (or_window) {
+    case 1: return or_gauss_dphi(z, b);
+    case 2: return or_bspline_dphi(z, m);
+    case 3: return or_sinc_dphi(z, m, b);
+    default: return or_kb_dphi(z, m, b);
+    }
 }
 static double win_phihat(long k, long n, int m, double b)
 {
-    return or_window == 1 ? or_gauss_phihat(k, n, b) : or_kb_phihat(k, n, m, b);
+    switch (or_window) {
+    case 1: return or_gauss_phihat(k, n, b);
+    case 2: return or_bspline_phihat(k, n, m);
+    case 3: return or_sinc_phihat(k, n, m, b);
+    default: return or_kb_phihat(k, n, m, b);
+    }
 }
 
 void or_dft_naive(const cplx *in, cplx *out, long n, int sign)

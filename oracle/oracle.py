@@ -53,6 +53,14 @@ def _load():
             "or_gauss_phi": (D, [D, D]),
             "or_gauss_dphi": (D, [D, D]),
             "or_gauss_phihat": (D, [L, L, D]),
+            "or_bspline_n": (D, [Ii, D]),
+            "or_bspline_phi": (D, [D, Ii]),
+            "or_bspline_dphi": (D, [D, Ii]),
+            "or_bspline_phihat": (D, [L, L, Ii]),
+            "or_sinc_a": (D, [L, L, Ii]),
+            "or_sinc_phi": (D, [D, Ii, D]),
+            "or_sinc_dphi": (D, [D, Ii, D]),
+            "or_sinc_phihat": (D, [L, L, Ii, D]),
             "or_set_window": (None, [Ii]),
             "or_get_window": (Ii, []),
             "or_dft_naive": (None, [P, P, L, Ii]),
@@ -146,12 +154,44 @@ def gauss_phihat(k, n, b):
     return _load().or_gauss_phihat(int(k), int(n), float(b))
 
 
-WINDOWS = {"kaiser-bessel": 0, "gaussian": 1}
+def bspline_n(k, x):
+    return _load().or_bspline_n(int(k), float(x))
+
+
+def bspline_phi(z, m):
+    return _load().or_bspline_phi(float(z), int(m))
+
+
+def bspline_dphi(z, m):
+    return _load().or_bspline_dphi(float(z), int(m))
+
+
+def bspline_phihat(k, n, m):
+    return _load().or_bspline_phihat(int(k), int(n), int(m))
+
+
+def sinc_a(N, n, m):
+    return _load().or_sinc_a(int(N), int(n), int(m))
+
+
+def sinc_phi(z, m, a):
+    return _load().or_sinc_phi(float(z), int(m), float(a))
+
+
+def sinc_dphi(z, m, a):
+    return _load().or_sinc_dphi(float(z), int(m), float(a))
+
+
+def sinc_phihat(k, n, m, a):
+    return _load().or_sinc_phihat(int(k), int(n), int(m), float(a))
+
+
+WINDOWS = {"kaiser-bessel": 0, "gaussian": 1, "bspline": 2, "sinc": 3}
 
 
 class window:
     """Context manager selecting the window of the oracle's NFFT functions
-    (``with window("gaussian"): ...``); Kaiser-Bessel otherwise."""
+    (``with window("gaussian"): ...``; also "bspline", "sinc"); Kaiser-Bessel otherwise."""
 
     def __init__(self, name):
         self.code = WINDOWS[name]

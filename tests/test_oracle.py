@@ -502,3 +502,123 @@ def test_gaussian_adjoint_identity():
         a = np.vdot(f, O.nfft_trafo(x, fh, None, 5))
         b = np.vdot(O.nfft_adjoint(x, f, N, None, 5), fh)
     assert abs(a - b) / abs(a) < 1e-13
+
+
+# --------------------------------------------------------------- B-spline and sinc windows
+
+
+def _bspline_exact(k, x):
+    """N_k(x) from the truncated-power definition, in exact rational arithmetic:
+    N_k(x) = 1/(k-1)! sum_{j=0}^{k} (-1)^j C(k, j) (x - j)_+^{k-1}, with (0)_+^0 = 1 (the
+    half-open support [0, k) of the recursion)."""
+    from fractions import Fraction
+    from math import comb, factorial
+
+    x = Fraction(x)
+    s = Fraction(0)
+    for j in range(k + 1):
+        if x - j >= 0:
+            s += (-1) ** j * comb(k, j) * (x - j) ** (k - 1)
+    return s / factorial(k - 1)
+
+
+def test_bspline_matches_truncated_power_formula():
+    """The oracle's B-spline (de Boor recursion) equals the exact truncated-power sum at
+    rational points, for orders 1..8 and the order 16 used with m = 8."""
+    from fractions import Fraction
+
+    for k in (1, 2, 3, 4, 5, 6, 7, 8, 16):
+        for num in range(0, 7 * k + 1, 3):
+            x = Fraction(num, 7)
+            if x >= k:
+                continue
+            exact = float(_bspline_exact(k, x))
+            assert abs(O.bspline_n(k, float(x)) - exact) < 1e-14, (k, x)
+    assert O.bspline_n(4, 2.0) == pytest.approx(2 / 3, abs=1e-15)
+    assert O.bspline_n(4, 1.0) == pytest.approx(1 / 6, abs=1e-15)
+
+
+@pytest.mark.parametrize("m", [1, 3, 8])
+def test_bspline_partition_of_unity_and_symmetry(m):
+    for z in (-0.37, 0.0, 0.25, 0.5, 0.91):
+        assert abs(sum(O.bspline_phi(z - j, m) for j in range(-m - 2, m + 3)) - 1.0) < 1e-14
+        assert abs(O.bspline_phi(z, m) - O.bspline_phi(-z, m)) < 1e-15
+    assert O.bspline_phi(m + 0.0, m) == 0.0 and O.bspline_phi(-m - 0.5, m) == 0.0
+
+
+def test_bspline_fourier_pair_by_quadrature():
+    """n phihat(k) = (sin(pi k/n)/(pi k/n))^{2m} is the Fourier transform of M_2m at
+    frequency k / n (quadrature over the polynomial pieces)."""
+    import scipy.integrate
+
+    for N, n, m in ((32, 64, 3), (100, 256, 6)):
+        for k in (0, 1, 7, N // 2 - 1, N // 2):
+            q = sum(scipy.integrate.quad(lambda z: O.bspline_phi(z, m) * np.cos(2 * np.pi * k * z / n), j, j + 1,
+                                         epsabs=1e-16, epsrel=1e-14)[0] for j in range(-m, m))
+            assert abs(n * O.bspline_phihat(k, n, m) - q) < 1e-13
+
+
+def test_bspline_derivative_matches_finite_differences():
+    for m in (2, 8):
+        for z in (-m + 0.3, -1.7, 0.0, 0.45, m - 0.2):
+            h = 1e-6
+            fd = (O.bspline_phi(z + h, m) - O.bspline_phi(z - h, m)) / (2 * h)
+            assert abs(fd - O.bspline_dphi(z, m)) < 1e-8
+
+
+def test_sinc_fourier_pair_by_quadrature():
+    """n phihat(k) = (pi/a) M_2m(pi k / (n a)) is the Fourier transform of
+    (sin(a z)/(a z))^{2m} at frequency k / n (quadrature over a long interval; the tail
+    beyond it is below 1e-11 for these m)."""
+    import scipy.integrate
+
+    for N, n, m in ((32, 64, 3), (100, 256, 6)):
+        a = O.sinc_a(N, n, m)
+        assert abs(a - np.pi * (2 - N / n) / (2 * m)) < 1e-15
+        for k in (0, 1, 7, N // 2 - 1, N // 2):
+            q = 2 * scipy.integrate.quad(lambda z: O.sinc_phi(z, m, a) * np.cos(2 * np.pi * k * z / n), 0, 600,
+                                         limit=2000, epsabs=1e-15, epsrel=1e-13)[0]
+            assert abs(n * O.sinc_phihat(k, n, m, a) - q) < 1e-10 * max(1.0, abs(q))
+
+
+def test_sinc_derivative_matches_finite_differences():
+    a = O.sinc_a(64, 128, 8)
+    for z in (-8.7, -3.2, 0.0, 1e-6, 0.4, 5.9):
+        h = 1e-6
+        fd = (O.sinc_phi(z + h, 8, a) - O.sinc_phi(z - h, 8, a)) / (2 * h)
+        assert abs(fd - O.sinc_dphi(z, 8, a)) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["bspline", "sinc"])
+def test_bspline_and_sinc_nfft_error_falls_with_m(name):
+    """With sigma = 2 the error against the direct sums stays within 4 (2 sigma - 1)^{-2m}
+    ||fhat||_1 (the literature bound of the B-spline window; the sinc window, whose transform
+    is a B-spline, is observed within it too) and falls at about that rate in m."""
+    r = np.random.default_rng(95)
+    N = (64,)
+    x = r.random((500, 1)) - 0.5
+    fh = W.cgauss(r, N)
+    f = O.ndft_trafo(x, fh)
+    prev = None
+    for m in (2, 4, 6, 8):
+        with O.window(name):
+            g = O.nfft_trafo(x, fh, None, m)
+        einf = np.max(np.abs(f - g)) / np.sum(np.abs(fh))
+        assert einf <= 4 * 3.0 ** (-2 * m), (m, einf)
+        if prev is not None:
+            rate = np.log(prev / einf) / 2  # per unit of m; the bound's rate is 2 ln 3 = 2.2
+            assert 1.5 < rate < 4.0, (m, rate)
+        prev = einf
+
+
+@pytest.mark.parametrize("name", ["bspline", "sinc"])
+def test_bspline_and_sinc_adjoint_identity(name):
+    r = np.random.default_rng(96)
+    N, M = (16, 24), 300
+    x = r.random((M, 2)) - 0.5
+    fh = W.cgauss(r, N)
+    f = W.cgauss(r, (M,))
+    with O.window(name):
+        a = np.vdot(f, O.nfft_trafo(x, fh, None, 5))
+        b = np.vdot(O.nfft_adjoint(x, f, N, None, 5), fh)
+    assert abs(a - b) / abs(a) < 1e-13

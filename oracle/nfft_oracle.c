@@ -210,11 +210,25 @@ double or_sinc_a(long N, long n, int m)
 }
 static double or_sinc1(double x) { return fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : sin(x) / x; }
 double or_sinc_phi(double z, int m, double a) { return pow(or_sinc1(a * z), 2.0 * (double)m); }
+/* d/dx sin(x)/x: the series sum_{n>=1} (-1)^n 2n x^(2n-1) / (2n+1)! for |x| < 1 (the
+ * closed form (x cos x - sin x) / x^2 loses digits to cancellation there), the closed form
+ * beyond. */
+static double or_dsinc1(double x)
+{
+    if (fabs(x) >= 1.0)
+        return (x * cos(x) - sin(x)) / (x * x);
+    double term = -x / 3.0, sum = 0.0; /* n = 1: -2x/3! */
+    for (int n = 1; n < 14; ++n) {
+        sum += term;
+        /* term_{n+1} / term_n = -x^2 (n+1) / (n (2n+2)(2n+3)) */
+        term *= -x * x * (double)(n + 1) / ((double)n * (2.0 * n + 2.0) * (2.0 * n + 3.0));
+    }
+    return sum;
+}
 double or_sinc_dphi(double z, int m, double a)
 {
     const double x = a * z;
-    /* d/dx sin(x)/x = (x cos x - sin x) / x^2, about -x/3 near 0 */
-    const double ds = fabs(x) < 1e-4 ? -x / 3.0 : (x * cos(x) - sin(x)) / (x * x);
+    const double ds = or_dsinc1(x);
     return 2.0 * (double)m * pow(or_sinc1(x), 2.0 * (double)m - 1.0) * ds * a;
 }
 double or_sinc_phihat(long k, long n, int m, double a)

@@ -622,3 +622,15 @@ def test_bspline_and_sinc_adjoint_identity(name):
         a = np.vdot(f, O.nfft_trafo(x, fh, None, 5))
         b = np.vdot(O.nfft_adjoint(x, f, N, None, 5), fh)
     assert abs(a - b) / abs(a) < 1e-13
+
+
+def test_sinc_derivative_near_zero_to_rounding():
+    """d phi / d z of the sinc window against 40-digit numerical differentiation, including
+    arguments near 0 where the closed form of d/dx sin(x)/x cancels."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    m = 8
+    a = O.sinc_a(64, 128, m)
+    for z in (1e-7, 1e-4, 0.01, 0.3, 2.0, 5.0, -3.1):
+        ref = mp.diff(lambda t: (mp.sin(a * t) / (a * t)) ** (2 * m), mp.mpf(z))
+        assert abs(O.sinc_dphi(z, m, a) - float(ref)) <= 1e-14 * abs(float(ref)), z

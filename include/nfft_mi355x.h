@@ -71,8 +71,21 @@ typedef enum {
  *    Sec. 4 (the library of Sec. 3 can be configured with either; the paper prints neither
  *    formula): phi(z) = (pi b)^{-1/2} exp(-z^2/b) in the grid variable z = n x - l,
  *    b = 2 sigma m / ((2 sigma - 1) pi), sigma = n/N, Fourier transform exp(-b (pi k/n)^2);
- *    same 2m+2-point stencil.  Less accurate than Kaiser-Bessel at equal m. */
-enum { NFFT_SORT_NODES = 1u << 0, NFFT_KEEP_GRID = 1u << 1, NFFT_WINDOW_GAUSSIAN = 1u << 2 };
+ *    same 2m+2-point stencil.  Less accurate than Kaiser-Bessel at equal m.
+ *  NFFT_WINDOW_BSPLINE: the B-spline window (the third of the library's windows, standard
+ *    pair of the NFFT literature): phi(z) = M_2m(z), the centred cardinal B-spline of order
+ *    2m (support [-m, m]), Fourier transform (sin(pi k/n) / (pi k/n))^(2m).
+ *  NFFT_WINDOW_SINC: the sinc window (the fourth): phi(z) = (sin(a z) / (a z))^(2m),
+ *    a = pi (2 - 1/sigma) / (2m), Fourier transform (pi/a) M_2m(pi k / (n a)); truncated to
+ *    the same 2m+2-point stencil.
+ *  At most one window flag may be set (NFFT_ERR_ARG otherwise). */
+enum {
+    NFFT_SORT_NODES = 1u << 0,
+    NFFT_KEEP_GRID = 1u << 1,
+    NFFT_WINDOW_GAUSSIAN = 1u << 2,
+    NFFT_WINDOW_BSPLINE = 1u << 3,
+    NFFT_WINDOW_SINC = 1u << 4
+};
 
 /* Read-only description of a plan (filled by nfft_plan_get_info). */
 typedef struct {
@@ -92,7 +105,7 @@ typedef struct {
     double grid_scale;      /* prod_t lambda_t: factor carried by the grids of the
                                single-step entry points (see there); lambda_t =
                                e^{b_t m} (Kaiser-Bessel), (pi b_t)^{-1/2} (Gaussian) */
-    int window;             /* 0 Kaiser-Bessel, 1 Gaussian                        */
+    int window;             /* 0 Kaiser-Bessel, 1 Gaussian, 2 B-spline, 3 sinc     */
 } nfft_plan_info;
 
 /* ---------------------------------------------------------------- plans */

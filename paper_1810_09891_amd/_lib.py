@@ -14,7 +14,10 @@ NFFT_C128 = 2
 NFFT_SORT_NODES = 1 << 0
 NFFT_KEEP_GRID = 1 << 1
 NFFT_WINDOW_GAUSSIAN = 1 << 2
-WINDOW_FLAGS = {"kaiser-bessel": 0, "gaussian": NFFT_WINDOW_GAUSSIAN}
+NFFT_WINDOW_BSPLINE = 1 << 3
+NFFT_WINDOW_SINC = 1 << 4
+WINDOW_FLAGS = {"kaiser-bessel": 0, "gaussian": NFFT_WINDOW_GAUSSIAN, "bspline": NFFT_WINDOW_BSPLINE,
+                "sinc": NFFT_WINDOW_SINC}
 
 STATUS = {
     0: "NFFT_OK",

@@ -172,6 +172,88 @@ template <typename T> __device__ __forceinline__ T gauss_point_d(T delta, int s,
     return T(-2) * z / b * exp(-z * z / b);
 }
 
+// B-spline window (the library's third window; standard pair): phi(z) = M_2m(z), the centred
+// cardinal B-spline of order 2m.  Stencil point s of a node with offset delta lies at
+// z = delta + m - s, so phi(z) = N_2m(delta + 2m - s): entry j = 2m - s of de Boor's
+// triangle at t = delta, which holds N_k(t + j), j = 0..k-1, and is built from N_1 = 1 on
+// [0, 1) by N_q(x) = (x N_{q-1}(x) + (q - x) N_{q-1}(x - 1)) / (q - 1) with nonnegative
+// terms only.  The loops are unrolled to the largest order (2m <= 24) so that every array
+// index is a constant; orders past k are skipped (k is the same in every lane).
+template <typename T> __device__ __forceinline__ T bspline_tri(T t, int k, int j)
+{
+    constexpr int KMAX = 24;
+    T b[KMAX];
+    b[0] = T(1);
+#pragma unroll
+    for (int i = 1; i < KMAX; ++i)
+        b[i] = T(0);
+#pragma unroll
+    for (int q = 2; q <= KMAX; ++q) {
+        if (q <= k) {
+            const T inv = T(1) / T(q - 1);
+#pragma unroll
+            for (int i = q - 1; i >= 0; --i) {
+                const T left = i > 0 ? b[i - 1] : T(0);
+                b[i] = ((t + T(i)) * b[i] + (T(q) - t - T(i)) * left) * inv;
+            }
+        }
+    }
+    T v = T(0);
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+        v = i == j ? b[i] : v;
+    return v;
+}
+template <typename T> __device__ __forceinline__ T bspline_point(T delta, int s, int m)
+{
+    return bspline_tri<T>(delta, 2 * m, 2 * m - s);
+}
+// d/dz M_2m(z) = N_{2m-1}(x) - N_{2m-1}(x - 1) at x = z + m
+template <typename T> __device__ __forceinline__ T bspline_point_d(T delta, int s, int m)
+{
+    return bspline_tri<T>(delta, 2 * m - 1, 2 * m - s) - bspline_tri<T>(delta, 2 * m - 1, 2 * m - s - 1);
+}
+
+// Sinc window (the fourth; standard pair): phi(z) = (sin(a z) / (a z))^(2m) with
+// a = pi (2 - 1/sigma) / (2m) (peak 1), truncated to the 2m+2-point stencil.
+template <typename T> __device__ __forceinline__ T sinc1(T x)
+{
+    return fabs(x) < T(1e-4) ? T(1) - x * x / T(6) : sin(x) / x;
+}
+template <typename T> __device__ __forceinline__ T sinc_point(T delta, int s, int m, T a)
+{
+    const T sc = sinc1<T>(a * (delta - T(s - m)));
+    const T r = sc * sc;
+    T v = T(1);
+    for (int i = 0; i < m; ++i)
+        v *= r;
+    return v;
+}
+// d/dx sin(x)/x: for |x| < 1 the power series (the closed form (x cos x - sin x) / x^2
+// cancels there), term n+1 = term n * (-x^2 (n+1) / (n (2n+2)(2n+3))); beyond it the closed form
+template <typename T> __device__ __forceinline__ T dsinc1(T x)
+{
+    if (fabs(x) >= T(1))
+        return (x * cos(x) - sin(x)) / (x * x);
+    T term = -x / T(3), sum = T(0);
+#pragma unroll
+    for (int n = 1; n < 14; ++n) {
+        sum += term;
+        term *= -x * x * T(n + 1) / (T(n) * T(2 * n + 2) * T(2 * n + 3));
+    }
+    return sum;
+}
+template <typename T> __device__ __forceinline__ T sinc_point_d(T delta, int s, int m, T a)
+{
+    const T x = a * (delta - T(s - m));
+    const T sc = sinc1<T>(x);
+    const T ds = dsinc1<T>(x);
+    T v = T(2 * m) * ds * a;
+    for (int i = 0; i < 2 * m - 1; ++i)
+        v *= sc;
+    return v;
+}
+
 // ------------------------------------------------------------------ parameter blocks
 
 // Geometry of a plan's window kernels.
@@ -186,7 +268,7 @@ struct Geom {
     int P[kMaxDim];    // padded tile edge B + WM - 1
     int Ptot;          // prod P
     int nbins;
-    int window;           // 0 Kaiser-Bessel, 1 Gaussian
+    int window;           // 0 Kaiser-Bessel, 1 Gaussian, 2 B-spline, 3 sinc
     int fold2;            // every grid index is covered by at most 2 tiles per dimension
     double b[kMaxDim];    // window shape per dimension
     double emb[kMaxDim];  // 1 / (factor the device window is divided by): e^{-b m} (Kaiser-Bessel),
@@ -199,12 +281,20 @@ template <typename T> __device__ __forceinline__ T win_point(const Geom &g, int 
 {
     if (g.window == 1)
         return gauss_point<T>(delta, s, (T)g.m, (T)g.b[t]);
+    if (g.window == 2)
+        return bspline_point<T>(delta, s, g.m);
+    if (g.window == 3)
+        return sinc_point<T>(delta, s, g.m, (T)g.b[t]);
     return kb_point<T>(delta, s, g.W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
 }
 template <typename T> __device__ __forceinline__ T win_point_d(const Geom &g, int t, T delta, int s)
 {
     if (g.window == 1)
         return gauss_point_d<T>(delta, s, (T)g.m, (T)g.b[t]);
+    if (g.window == 2)
+        return bspline_point_d<T>(delta, s, g.m);
+    if (g.window == 3)
+        return sinc_point_d<T>(delta, s, g.m, (T)g.b[t]);
     return kb_point_d<T>(delta, s, g.W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
 }
 

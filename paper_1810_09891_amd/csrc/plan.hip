@@ -199,16 +199,56 @@ bool plan_repack_pass(const nfft_plan_s *p, const FftPass &tmpl, int factor, Fft
     return true;
 }
 
+// Centred cardinal B-spline M_k(u) = N_k(u + k/2) in FP64 (host tables of the sinc window):
+// de Boor's triangle over the k values N_q(t + j) nonzero at the fractional part t, all
+// terms nonnegative.
+static double centred_bspline(int k, double u)
+{
+    const double x = u + 0.5 * k;
+    if (!(x >= 0.0) || x >= (double)k)
+        return 0.0;
+    const double t = x - std::floor(x);
+    const int j = (int)std::floor(x);
+    std::vector<double> b((size_t)k + 1, 0.0);
+    b[0] = 1.0;
+    for (int q = 2; q <= k; ++q)
+        for (int i = q - 1; i >= 0; --i) {
+            const double left = i > 0 ? b[(size_t)i - 1] : 0.0;
+            b[(size_t)i] = ((t + i) * b[(size_t)i] + (q - t - i) * left) / (q - 1);
+        }
+    return b[(size_t)j];
+}
+
 static int build_tables(nfft_plan_s *p)
 {
     const double pi = 3.14159265358979323846264338327950288;
     const bool gauss = (p->flags & NFFT_WINDOW_GAUSSIAN) != 0;
-    p->geom.window = gauss ? 1 : 0;
+    const bool bspline = (p->flags & NFFT_WINDOW_BSPLINE) != 0;
+    const bool sinc = (p->flags & NFFT_WINDOW_SINC) != 0;
+    p->geom.window = gauss ? 1 : bspline ? 2 : sinc ? 3 : 0;
     for (int t = 0; t < p->d; ++t) {
         // The device evaluates the window divided by lambda and the deconvolution factor is
         // lambda / Phi(k), Phi(k) = n phihat(k) the window's Fourier transform at k / n.
         p->wtab[t].resize((size_t)p->N[t]);
-        if (gauss) {
+        if (bspline) {
+            // Phi(k) = (sin(pi k/n) / (pi k/n))^(2m), lambda = 1
+            p->geom.b[t] = 0.0;
+            p->geom.emb[t] = 1.0;
+            for (int64_t i = 0; i < p->N[t]; ++i) {
+                const double a = pi * (double)(i - p->N[t] / 2) / (double)p->n[t];
+                const double s = a == 0.0 ? 1.0 : std::sin(a) / a;
+                p->wtab[t][(size_t)i] = 1.0 / std::pow(s, 2.0 * p->m);
+            }
+        } else if (sinc) {
+            // a = pi (2 - 1/sigma) / (2m), Phi(k) = (pi/a) M_2m(pi k / (n a)), lambda = 1
+            const double a = pi * (2.0 - (double)p->N[t] / (double)p->n[t]) / (2.0 * p->m);
+            p->geom.b[t] = a;
+            p->geom.emb[t] = 1.0;
+            for (int64_t i = 0; i < p->N[t]; ++i) {
+                const double u = pi * (double)(i - p->N[t] / 2) / ((double)p->n[t] * a);
+                p->wtab[t][(size_t)i] = 1.0 / ((pi / a) * centred_bspline(2 * p->m, u));
+            }
+        } else if (gauss) {
             // b = 2 sigma m / ((2 sigma - 1) pi), Phi(k) = exp(-b (pi k / n)^2),
             // lambda = (pi b)^{-1/2} (the window's peak)
             const double sigma = (double)p->n[t] / (double)p->N[t];
@@ -307,6 +347,11 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
         m = 8;
     if (m < 1)
         return NFFT_ERR_ARG;
+    {
+        const uint32_t win = flags & (NFFT_WINDOW_GAUSSIAN | NFFT_WINDOW_BSPLINE | NFFT_WINDOW_SINC);
+        if (win & (win - 1))
+            return NFFT_ERR_ARG;  // more than one window
+    }
     int64_t nn[kMaxDim];
     for (int t = 0; t < d; ++t) {
         if (N[t] < 2 || (N[t] & 1))

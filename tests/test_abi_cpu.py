@@ -89,6 +89,20 @@ def test_lds_limits(lib, N, n, m, dtype, expect):
         assert lib.nfft_plan_destroy(h) == OK
 
 
+def test_window_flags(lib):
+    """One window flag at most; each selects its window (reported in the plan info)."""
+    for flags, code in ((0, 0), (1 << 2, 1), (1 << 3, 2), (1 << 4, 3)):
+        st, h = create(lib, (16, 16), 100, None, 4, 1, flags)
+        assert st == OK
+        info = _lib.PlanInfo()
+        assert lib.nfft_plan_get_info(h, ctypes.byref(info)) == OK
+        assert info.window == code
+        assert lib.nfft_plan_destroy(h) == OK
+    for flags in ((1 << 2) | (1 << 3), (1 << 3) | (1 << 4), (1 << 2) | (1 << 4)):
+        st, h = create(lib, (16, 16), 100, None, 4, 1, flags)
+        assert st == ARG
+
+
 def test_defaults(lib):
     st, h = create(lib, (100, 64), 5, None, 0)
     assert st == OK

@@ -38,9 +38,9 @@ sys.path.insert(0, ROOT)
 METRIC = "NFFT fwd+adj nonuniform points/s at stated rel-ℓ2 error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 # LDS read ceiling of one MI355X measured with paper_1810_09891_amd/lib/lds_bw (conflict-free
-# 8-byte reads, all 256 CUs): the bound of the interpolation kernel (an 8-byte LDS read
-# per stencil point)
-LDS_READ8_PEAK_GBS = 60060.0
+# 8-byte reads issued as separate ds_read_b64, all 256 CUs; the highest 8-byte read rate it
+# measures): the bound of the interpolation kernel (an 8-byte LDS read per stencil point)
+LDS_READ8_PEAK_GBS = 128000.0
 # Published FP32 vector peak of the MI355X (256 CUs, 2.4 GHz, packed FP32 counted): the
 # ceiling of the 2-D spreading kernel that keeps tile columns in registers (4 flops, two
 # multiply-adds, per stencil point).  Packed FP32 instructions are not generated, which

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 const C *row = tile + ul[0];
 #pragma unroll
                 for (int s = 0; s < WM; ++s) {
-                    C gv = row[s];
+                    const C gv = lds_entry<T>(row + s);
                     acc[0].x += dwl[s] * gv.x;
                     acc[0].y += dwl[s] * gv.y;
                 }
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                     T rx = 0, ry = 0, dx = 0, dy = 0;
 #pragma unroll
                     for (int s1 = 0; s1 < WM; ++s1) {
-                        C gv = row[s1];
+                        const C gv = lds_entry<T>(row + s1);
                         rx += wl[s1] * gv.x;
                         ry += wl[s1] * gv.y;
                         dx += dwl[s1] * gv.x;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                         T rx = 0, ry = 0, dx = 0, dy = 0;
 #pragma unroll
                         for (int s2 = 0; s2 < WM; ++s2) {
-                            C gv = row[s2];
+                            const C gv = lds_entry<T>(row + s2);
                             rx += wl[s2] * gv.x;
                             ry += wl[s2] * gv.y;
                             dx += dwl[s2] * gv.x;

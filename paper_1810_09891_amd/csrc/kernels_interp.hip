@@ -88,7 +88,7 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
         auto load_row = [&](const C *row, C *dst) {
 #pragma unroll
             for (int s = 0; s < WM; ++s)
-                dst[s] = row[s];
+                dst[s] = lds_entry<T>(row + s);
         };
         // without the look-ahead buffer a row is summed straight from LDS
         auto sum_lds = [&](const C *row, T &rx, T &ry) {
@@ -96,7 +96,7 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
             ry = 0;
 #pragma unroll
             for (int s = 0; s < WM; ++s) {
-                const C v = row[s];
+                const C v = lds_entry<T>(row + s);
                 rx += wl[s] * v.x;
                 ry += wl[s] * v.y;
             }

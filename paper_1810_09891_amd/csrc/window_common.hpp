@@ -17,6 +17,22 @@ template <typename T, int D> __device__ __forceinline__ void bin_coords(const Ge
     }
 }
 
+// One complex entry of an LDS tile.  Single-precision entries are read with relaxed
+// 64-bit atomic loads: as ordered memory operations they are not fused into ds_read2_b64
+// pairs, which on gfx950 take about twice the LDS cycles of two ds_read_b64 for the
+// scattered stencil rows of the window kernels.  No wait is attached to a relaxed load.
+template <typename T> __device__ __forceinline__ Cplx<T> lds_entry(const Cplx<T> *p)
+{
+    if constexpr (sizeof(T) == 4) {
+        const unsigned long long u = __hip_atomic_load(
+            reinterpret_cast<unsigned long long *>(const_cast<Cplx<T> *>(p)), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_WORKGROUP);
+        return __builtin_bit_cast(Cplx<T>, u);
+    } else {
+        return *p;
+    }
+}
+
 // Stage the padded tile of bin `bc` into LDS (complex, row-major P_0 x ... x P_{d-1}).
 // A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < 8: all eight loads
 // (entries past the tile read entry 0) are issued before the first LDS store, so their

@@ -404,6 +404,40 @@ def bench_fastsum(torch, steps, warmup, check):
     return r_
 
 
+def bench_nnfft(torch, steps, warmup, check):
+    """NNFFT (nonequispaced in both domains): d = 2, N = (256, 256), 131072 frequencies and
+    131072 nodes uniform, complex64, m = 8; one step is a transform and its adjoint."""
+    from oracle import oracle as O
+    from paper_1810_09891_amd import NNPlan, workloads as W
+
+    w = W.workload("nnfft_d2")
+    C64 = torch.complex64
+    p = NNPlan(w["N"], w["K"], w["M"], m=w["m"], dtype=C64)
+    p.set_nodes(torch.as_tensor(w["x"]).cuda(), torch.as_tensor(w["v"]).cuda())
+    fh = torch.as_tensor(w["fhat"]).to("cuda", C64)
+    fv = torch.as_tensor(w["f"]).to("cuda", C64)
+    f = torch.empty(w["M"], dtype=C64, device="cuda")
+    h = torch.empty(w["K"], dtype=C64, device="cuda")
+
+    def step():
+        p.trafo(fh, out=f)
+        p.adjoint(fv, out=h)
+
+    ms = cuda_time(torch, step, steps, warmup)
+    r_ = {"workload": "NNFFT d=2 N=(256,256) (frequency grid %s, sigma1 %.3f), K=131072 frequencies and "
+                      "M=131072 nodes uniform, complex64, m=8, trafo+adjoint" % (list(p.N2), p.sigma1[0]),
+          "ms_per_step": ms, "points_per_s": (w["K"] + w["M"]) / (ms * 1e-3)}
+    if check:
+        step()
+        fo = f.cpu().numpy()
+        ho = h.cpu().numpy()
+        js = sample(w["M"], 256, 7)
+        ks = sample(w["K"], 256, 8)
+        r_["e2_trafo_vs_nndft_256"] = e2(O.nndft_trafo(w["v"], w["x"][js], w["fhat"]), fo[js])
+        r_["e2_adjoint_vs_nndft_256"] = e2(O.nndft_adjoint(w["v"][ks], w["x"], w["f"]), ho[ks])
+    return r_
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,7 +516,8 @@ def main():
         check = not args.no_cpu
         for name, fn, st in (("d1_256_c128_m8", bench_d1, args.steps), ("d3_radial_128_c64_m6", bench_d3, 20),
                              ("batch64_c64_m6", bench_batch, 20), ("grad_radial_256_c64_m6", bench_grad, 20),
-                             ("fastsum_gauss_128_c64_m6", bench_fastsum, 50)):
+                             ("fastsum_gauss_128_c64_m6", bench_fastsum, 50),
+                             ("nnfft_d2_256_c64_m8", bench_nnfft, 50)):
             t0 = time.perf_counter()
             extra[name] = fn(torch, st, 3, check)
             log("%s: %.4f ms/step, %.3e points/s (%.1f s)" %

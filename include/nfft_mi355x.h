@@ -294,6 +294,67 @@ int nfft_batch_trafo(nfft_batch b, const void *const *fhat, void *const *f, hipS
 int nfft_batch_adjoint(nfft_batch b, const void *const *f, void *const *hhat, hipStream_t stream);
 int nfft_batch_destroy(nfft_batch b);
 
+/* ---------------------------------------------------------------- NNFFT */
+
+/* NNFFT, the transform with nonequispaced nodes in both domains that Sec. 1 names as a
+ * generalisation of the NFFT: for K frequencies v_k with v_{k,t} in [-N_t/2, N_t/2) and M
+ * nodes x_j in [-1/2, 1/2)^d,
+ *     nnfft_trafo:    f_j    = sum_k fhat_k e^{-2 pi i v_k . x_j},   j < M,
+ *     nnfft_adjoint:  hhat_k = sum_j f_j    e^{+2 pi i v_k . x_j},   k < K.
+ * Computed with two inner plans sharing the window and m: plan A spreads the frequencies
+ * onto an equispaced frequency grid of N2_t points (a power of two, see sigma; plan A has
+ * N_A,t coefficients, the smallest even count with N_t N2_t / N_A,t <= N2_t - 2m - 4, i.e.
+ * oversampling sigma1_t = N2_t / N_A,t with room for the stencils, and nodes v_k / N_A),
+ * plan B is an NFFT with N2 coefficients at
+ * the nodes z_j = x_j N_A / N2, and each output is multiplied by the deconvolution factor
+ * of plan A's window taken at z_j (eq. (2.9) at a real frequency).  The adjoint runs the
+ * transposed steps in reverse.  Accuracy is that of two NFFTs with oversampling about
+ * sigma and window size m.
+ *
+ * nnfft_plan_create
+ *   N      [host] d even bandwidths >= 2 of the frequency domain.
+ *   K, M   numbers of frequencies and nodes, >= 1.
+ *   sigma  frequency-grid oversampling in (1, 16]: N2_t is the smallest power of two
+ *          >= ceil(sigma N_t) + 2m + 4.  0 selects it automatically: the smallest power
+ *          of two >= 2 N_t, doubled while sigma1_t would be below 1.5.
+ *   m      window size (0: 8), as for nfft_plan_create.
+ *   flags  one of the window flags, and NFFT_SORT_NODES, or 0.
+ *   NFFT_ERR_UNSUPPORTED when an inner plan is (N2_t > 2048, so that plan B's FFT length
+ *   2 N2_t stays within 4096).  Host only.
+ * nnfft_workspace_bytes / nnfft_set_workspace: one caller-owned device workspace
+ *   (256-byte aligned) holding both inner plans' workspaces, the scaled nodes, the
+ *   per-node factors and the frequency grid; attaching it forgets the nodes.
+ * nnfft_set_nodes
+ *   x      [device, M x d doubles] nodes; v [device, K x d doubles] frequencies.  Neither
+ *          is referenced after the enqueued work has run.  Frequencies outside
+ *          [-N_t/2, N_t/2) give wrong values (their spreading wraps around the frequency
+ *          grid); a non-finite node or frequency gives NaN outputs as for nfft_set_nodes.
+ * nnfft_trafo / nnfft_adjoint
+ *   fhat [device, K], f [device, M]; complex of the plan's precision.  Enqueued on
+ *   `stream`; NFFT_ERR_STATE before nnfft_set_nodes. */
+typedef struct nnfft_plan_s *nnfft_plan;
+
+typedef struct {
+    int d, m;
+    int64_t N[3];           /* frequency bandwidths                               */
+    int64_t K, M;           /* frequencies, nodes                                 */
+    int64_t N2[3];          /* frequency grid points = plan B's bandwidths         */
+    int64_t NA[3];          /* plan A's coefficient counts                         */
+    double sigma1[3];       /* N2 / NA: plan A's oversampling                      */
+    size_t workspace_bytes; /* bytes nnfft_set_workspace needs                     */
+    int window;             /* as nfft_plan_info.window                            */
+} nnfft_plan_info;
+
+int nnfft_plan_create(nnfft_plan *out, int d, const int64_t *N, int64_t K, int64_t M, double sigma, int m,
+                      nfft_dtype dtype, uint32_t flags);
+int nnfft_plan_destroy(nnfft_plan p);
+int nnfft_plan_get_info(nnfft_plan p, nnfft_plan_info *info);
+int nnfft_workspace_bytes(nnfft_plan p, size_t *bytes);
+int nnfft_set_workspace(nnfft_plan p, void *ws, size_t bytes);
+int nnfft_set_nodes(nnfft_plan p, const double *x, const double *v, hipStream_t stream);
+int nnfft_trafo(nnfft_plan p, const void *fhat, void *f, hipStream_t stream);
+int nnfft_adjoint(nnfft_plan p, const void *f, void *hhat, hipStream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char *nfft_status_string(int status);
 

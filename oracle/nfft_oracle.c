@@ -17,6 +17,8 @@
  *     periodised window; eq. (2.13): the stencil index set.
  *   - Sec. 2 eq. (2.15) / (2.16): the error measures E_2 and E_inf.
  *   - Sec. 4: the Kaiser-Bessel window (named, formula not printed).
+ *   - Sec. 1: the NNFFT (nonequispaced in both domains), named only; its direct sums
+ *     (or_nndft_*) are the definition with real frequencies in eq. (1.2) / (1.3).
  *
  * Readings where the paper is silent or garbled (each also listed in the
  * design notes):
@@ -473,6 +475,45 @@ void or_ndft_adjoint(int d, const long *N, long M, const double *x, const cplx *
             acc += f[j] * e;
         }
         fhat[idx] = acc;
+    }
+}
+
+/* NNDFT, the transform with nonequispaced nodes in both domains that Sec. 1 names as a
+ * generalisation of the NFFT, written out as its definition: real frequencies v_k (K x d)
+ * in place of the integer k of eq. (1.2),
+ *   f_j    = sum_k fhat_k exp(-2 pi i v_k.x_j),   j < M,
+ *   hhat_k = sum_j f_j    exp(+2 pi i v_k.x_j),   k < K.
+ * The phase v_k.x_j is accumulated in long double and reduced modulo 1 before the
+ * exponential, as in expo1. */
+static cplx expo_real(int d, const double *v, const double *x, int sign)
+{
+    long double p = 0.0L;
+    for (int t = 0; t < d; ++t)
+        p += (long double)v[t] * (long double)x[t];
+    double fr = (double)(p - floorl(p));
+    double ang = (double)sign * 2.0 * OR_PI * fr;
+    return cos(ang) + I * sin(ang);
+}
+
+void or_nndft_trafo(int d, long K, long M, const double *v, const double *x, const cplx *fhat, cplx *f)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long j = 0; j < M; ++j) {
+        cplx acc = 0.0;
+        for (long k = 0; k < K; ++k)
+            acc += fhat[k] * expo_real(d, v + k * d, x + j * d, -1);
+        f[j] = acc;
+    }
+}
+
+void or_nndft_adjoint(int d, long K, long M, const double *v, const double *x, const cplx *f, cplx *hhat)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long k = 0; k < K; ++k) {
+        cplx acc = 0.0;
+        for (long j = 0; j < M; ++j)
+            acc += f[j] * expo_real(d, v + k * d, x + j * d, +1);
+        hhat[k] = acc;
     }
 }
 

@@ -69,6 +69,8 @@ def _load():
             "or_ndft_trafo": (None, [Ii, P, L, P, P, P]),
             "or_ndft_adjoint": (None, [Ii, P, L, P, P, P]),
             "or_ndft_grad_x": (None, [Ii, P, L, P, P, P, P]),
+            "or_nndft_trafo": (None, [Ii, L, L, P, P, P, P]),
+            "or_nndft_adjoint": (None, [Ii, L, L, P, P, P, P]),
             "or_ndft_adjoint_at": (None, [Ii, P, L, P, P, L, P, P]),
             "or_nfft_deconv": (None, [Ii, P, P, Ii, P, P]),
             "or_nfft_deconv_adj": (None, [Ii, P, P, Ii, P, P]),
@@ -245,6 +247,33 @@ def ndft_adjoint(x, f, N):
     out = np.empty(tuple(N), dtype=np.complex128)
     _load().or_ndft_adjoint(d, _p(N), M, _p(x), _p(f), _p(out))
     return out
+
+
+def nndft_trafo(v, x, fhat):
+    """NNDFT (Sec. 1's generalisation with nonequispaced frequencies), by its definition:
+    f_j = sum_k fhat_k exp(-2 pi i v_k.x_j) for frequencies v (K, d) and nodes x (M, d)."""
+    v = _f64(v)
+    x = _f64(x)
+    fhat = _c128(fhat).reshape(-1)
+    K, d = v.shape
+    M, d2 = x.shape
+    assert d == d2 and fhat.shape[0] == K
+    f = np.empty(M, dtype=np.complex128)
+    _load().or_nndft_trafo(d, K, M, _p(v), _p(x), _p(fhat), _p(f))
+    return f
+
+
+def nndft_adjoint(v, x, f):
+    """hhat_k = sum_j f_j exp(+2 pi i v_k.x_j)."""
+    v = _f64(v)
+    x = _f64(x)
+    f = _c128(f).reshape(-1)
+    K, d = v.shape
+    M, d2 = x.shape
+    assert d == d2 and f.shape[0] == M
+    h = np.empty(K, dtype=np.complex128)
+    _load().or_nndft_adjoint(d, K, M, _p(v), _p(x), _p(f), _p(h))
+    return h
 
 
 def fastsum(x, y, bhat, alpha):

@@ -36,6 +36,8 @@ ABI_SYMBOLS = [
     "nfft_step_coeffs", "nfft_profile_enable", "nfft_profile_read", "nfft_batch_create",
     "nfft_batch_get_info", "nfft_batch_workspace_bytes", "nfft_batch_set_workspace",
     "nfft_batch_autotune", "nfft_batch_get_params", "nfft_batch_set_params", "nfft_batch_trafo", "nfft_batch_adjoint", "nfft_batch_destroy", "nfft_status_string",
+    "nnfft_plan_create", "nnfft_plan_destroy", "nnfft_plan_get_info", "nnfft_workspace_bytes",
+    "nnfft_set_workspace", "nnfft_set_nodes", "nnfft_trafo", "nnfft_adjoint",
 ]
 
 
@@ -71,6 +73,21 @@ class BatchInfo(ctypes.Structure):
         ("groups", ctypes.c_int),
         ("tuned", ctypes.c_int),
         ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class NNPlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("m", ctypes.c_int),
+        ("N", ctypes.c_int64 * 3),
+        ("K", ctypes.c_int64),
+        ("M", ctypes.c_int64),
+        ("N2", ctypes.c_int64 * 3),
+        ("NA", ctypes.c_int64 * 3),
+        ("sigma1", ctypes.c_double * 3),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("window", ctypes.c_int),
     ]
 
 
@@ -125,6 +142,15 @@ def load():
         "nfft_batch_trafo": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
         "nfft_batch_adjoint": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
         "nfft_batch_destroy": [P],
+        "nnfft_plan_create": [ctypes.POINTER(P), I, ctypes.POINTER(I64), I64, I64, ctypes.c_double, I, I,
+                              ctypes.c_uint32],
+        "nnfft_plan_destroy": [P],
+        "nnfft_plan_get_info": [P, ctypes.POINTER(NNPlanInfo)],
+        "nnfft_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "nnfft_set_workspace": [P, P, ctypes.c_size_t],
+        "nnfft_set_nodes": [P, P, P, P],
+        "nnfft_trafo": [P, P, P, P],
+        "nnfft_adjoint": [P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -224,6 +224,97 @@ class Plan:
             pass
 
 
+class NNPlan:
+    """NNFFT plan: nonequispaced nodes in both domains (the generalisation named in Sec. 1).
+
+    ``trafo`` computes f_j = sum_k fhat_k exp(-2 pi i v_k.x_j) for K frequencies v (K, d)
+    with v_{k,t} in [-N_t/2, N_t/2) and M nodes x (M, d) in [-1/2, 1/2)^d; ``adjoint``
+    computes hhat_k = sum_j f_j exp(+2 pi i v_k.x_j).  ``sigma`` is the oversampling of the
+    frequency grid the frequencies are spread onto (None: chosen by the library), ``m`` the
+    window size of both inner NFFT plans.  All tensors live on ``device``.
+    """
+
+    def __init__(self, N, K, M, sigma=None, m=8, dtype=torch.complex64, device="cuda", window="kaiser-bessel"):
+        lib = _lib.load()
+        if window not in _lib.WINDOW_FLAGS:
+            raise ValueError("window must be one of %s" % sorted(_lib.WINDOW_FLAGS))
+        if dtype not in _CDTYPE:
+            raise TypeError("dtype must be torch.complex64 or torch.complex128")
+        self.N = tuple(int(v) for v in N)
+        self.d = len(self.N)
+        self.K = int(K)
+        self.M = int(M)
+        self.dtype = dtype
+        self.window = window
+        self.device = torch.device(device)
+        Na = (ctypes.c_int64 * self.d)(*self.N)
+        h = ctypes.c_void_p()
+        check(lib.nnfft_plan_create(ctypes.byref(h), self.d, Na, self.K, self.M, float(sigma or 0.0), int(m),
+                                    _CDTYPE[dtype], int(_lib.WINDOW_FLAGS[window])), "nnfft_plan_create")
+        self._h = h
+        self._lib = lib
+        info = _lib.NNPlanInfo()
+        check(lib.nnfft_plan_get_info(h, ctypes.byref(info)), "nnfft_plan_get_info")
+        self.info = info
+        self.m = int(info.m)
+        self.N2 = tuple(int(info.N2[t]) for t in range(self.d))
+        self.NA = tuple(int(info.NA[t]) for t in range(self.d))
+        self.sigma1 = tuple(float(info.sigma1[t]) for t in range(self.d))
+        self.workspace = None
+        self._keep = None
+
+    def allocate(self):
+        nbytes = ctypes.c_size_t()
+        check(self._lib.nnfft_workspace_bytes(self._h, ctypes.byref(nbytes)), "nnfft_workspace_bytes")
+        ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws
+        check(self._lib.nnfft_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr() + off), nbytes.value),
+              "nnfft_set_workspace")
+        return self
+
+    def _as(self, t, dtype, shape):
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=dtype)
+        if tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape)
+        return t.contiguous()
+
+    def set_nodes(self, x, v):
+        """Nodes x (M, d) and frequencies v (K, d), float64."""
+        if self.workspace is None:
+            self.allocate()
+        x = self._as(x, torch.float64, (self.M, self.d))
+        v = self._as(v, torch.float64, (self.K, self.d))
+        check(self._lib.nnfft_set_nodes(self._h, _ptr(x), _ptr(v), _stream(self.device)), "nnfft_set_nodes")
+        self._keep = (x, v)  # alive until the enqueued work has read them
+        return self
+
+    def trafo(self, fhat, out=None):
+        fhat = self._as(fhat, self.dtype, (self.K,))
+        f = out if out is not None else torch.empty(self.M, dtype=self.dtype, device=self.device)
+        check(self._lib.nnfft_trafo(self._h, _ptr(fhat), _ptr(f), _stream(self.device)), "nnfft_trafo")
+        return f
+
+    def adjoint(self, f, out=None):
+        f = self._as(f, self.dtype, (self.M,))
+        h = out if out is not None else torch.empty(self.K, dtype=self.dtype, device=self.device)
+        check(self._lib.nnfft_adjoint(self._h, _ptr(f), _ptr(h), _stream(self.device)), "nnfft_adjoint")
+        return h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nnfft_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Many plans run together: ``trafo`` / ``adjoint`` take and return lists in the order of
     ``plans`` and launch each step kind once for all of them.  Every plan needs its nodes

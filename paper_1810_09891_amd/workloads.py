@@ -16,6 +16,8 @@ Workloads (sizes from the evaluation plan; node layouts as stated):
   dimension, M log-uniform in [1e3, 2e5], uniform nodes.
 * ``"grad"``: d=2, N=(256,256), M=256 spokes * 256 points with N(0, 1e-3^2) jitter.
 * ``"fastsum"``: d=2, N=(128,128), 32768 source and 32768 target nodes, uniform.
+* ``"nnfft_d2"``: NNFFT, d=2, N=(256,256): K=131072 frequencies uniform on
+  [-128, 128)^2 and M=131072 nodes uniform on [-1/2, 1/2)^2, m=8, complex Gaussian data.
 
 "Complex Gaussian" is CN(0,1): (a + i b)/sqrt(2) with a, b standard normal.
 Seeds are 18100989100 + 10*workload_id + stream_id, PCG64.
@@ -24,7 +26,7 @@ import numpy as np
 
 SEED_BASE = 18100989100
 
-WORKLOAD_ID = {"d1": 1, "d2": 2, "d3r": 3, "batch": 4, "grad": 5, "paper": 6, "small": 7, "fastsum": 8}
+WORKLOAD_ID = {"d1": 1, "d2": 2, "d3r": 3, "batch": 4, "grad": 5, "paper": 6, "small": 7, "fastsum": 8, "nnfft_d2": 9}
 
 
 def rng(workload, stream=0):
@@ -95,6 +97,12 @@ def workload(name, m=None, stream=0):
         x = radial_nodes_2d(r, 256, 256, 1e-3)
         M = x.shape[0]
         m = 6 if m is None else m
+    elif name == "nnfft_d2":
+        N, K, M = (256, 256), 131072, 131072
+        m = 8 if m is None else m
+        x = uniform_nodes(r, M, 2)
+        v = (r.random((K, 2)) - 0.5) * np.asarray(N, dtype=np.float64)
+        return {"N": N, "K": K, "M": M, "m": m, "x": x, "v": v, "fhat": cgauss(r, (K,)), "f": cgauss(r, (M,))}
     else:
         raise ValueError(name)
     fhat = cgauss(r, N)

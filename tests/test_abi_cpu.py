@@ -238,3 +238,93 @@ def test_fastsum_argument_checks(lib):
     assert lib.nfft_set_workspace(h, fake, nb.value) == OK
     assert lib.nfft_fastsum(h, h, fake, fake, fake, fake, None) == STATE
     assert lib.nfft_plan_destroy(h) == OK
+
+
+def nn_create(lib, N, K, M, sigma=2.0, m=8, dtype=1, flags=0):
+    h = ctypes.c_void_p()
+    d = len(N)
+    Na = (ctypes.c_int64 * d)(*N)
+    st = lib.nnfft_plan_create(ctypes.byref(h), d, Na, K, M, sigma, m, dtype, flags)
+    return st, h
+
+
+@pytest.mark.parametrize("N,sigma,m", [((64,), 2.0, 8), ((30, 48), 2.0, 4), ((16, 10, 8), 1.5, 6), ((200,), 3.0, 2)])
+def test_nnfft_plan_geometry(lib, N, sigma, m):
+    # frequency grid N2: a power of two with sigma N + 2m + 4 points; N_A the smallest even
+    # count for which sigma1 = N2 / N_A puts sigma1 [-N/2, N/2) and the stencils inside it
+    st, h = nn_create(lib, N, 100, 120, sigma, m)
+    assert st == OK
+    info = _lib.NNPlanInfo()
+    assert lib.nnfft_plan_get_info(h, ctypes.byref(info)) == OK
+    assert (info.d, info.m, info.K, info.M) == (len(N), m, 100, 120)
+    for t, Nt in enumerate(N):
+        n2, na = info.N2[t], info.NA[t]
+        assert n2 & (n2 - 1) == 0 and n2 >= -(-sigma * Nt // 1) + 2 * m + 4
+        assert n2 // 2 < -(-sigma * Nt // 1) + 2 * m + 4  # smallest such power of two
+        assert na % 2 == 0 and Nt < na < n2
+        assert Nt * n2 <= na * (n2 - 2 * m - 4)
+        assert (na - 2) * (n2 - 2 * m - 4) < Nt * n2
+        assert info.sigma1[t] == pytest.approx(n2 / na)
+    nbytes = ctypes.c_size_t()
+    assert lib.nnfft_workspace_bytes(h, ctypes.byref(nbytes)) == OK
+    assert nbytes.value == info.workspace_bytes > 0
+    assert lib.nnfft_plan_destroy(h) == OK
+
+
+@pytest.mark.parametrize("args,expect", [
+    (((63,), 10, 10, 2.0, 8, 1, 0), ARG),            # odd bandwidth
+    (((64,), 0, 10, 2.0, 8, 1, 0), ARG),             # no frequencies
+    (((64,), 10, 0, 2.0, 8, 1, 0), ARG),             # no nodes
+    (((64,), 10, 10, 1.0, 8, 1, 0), ARG),            # sigma must exceed 1
+    (((64,), 10, 10, 2.0, -1, 1, 0), ARG),           # window size
+    (((64,), 10, 10, 2.0, 8, 3, 0), ARG),            # dtype
+    (((64,), 10, 10, 2.0, 8, 1, 1 << 1), ARG),       # NFFT_KEEP_GRID is not an NNFFT flag
+    (((64,), 10, 10, 2.0, 8, 1, (1 << 2) | (1 << 3)), ARG),  # two windows
+    (((1024,), 10, 10, 2.0, 8, 1, 0), UNSUP),        # N2 = 4096: plan B's FFT length 8192
+])
+def test_nnfft_plan_validation(lib, args, expect):
+    st, h = nn_create(lib, *args)
+    assert st == expect
+    if st == OK:
+        lib.nnfft_plan_destroy(h)
+
+
+def test_nnfft_call_order(lib):
+    st, h = nn_create(lib, (32, 32), 50, 60, 2.0, 4)
+    assert st == OK
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced on the host
+    nbytes = ctypes.c_size_t()
+    assert lib.nnfft_workspace_bytes(h, ctypes.byref(nbytes)) == OK
+    assert lib.nnfft_set_nodes(h, fake, fake, None) == WS
+    assert lib.nnfft_trafo(h, fake, fake, None) == WS
+    assert lib.nnfft_set_workspace(h, fake, nbytes.value - 1) == WS
+    assert lib.nnfft_set_workspace(h, ctypes.c_void_p((1 << 20) + 8), nbytes.value) == WS
+    assert lib.nnfft_set_workspace(h, fake, nbytes.value) == OK
+    assert lib.nnfft_trafo(h, fake, fake, None) == STATE
+    assert lib.nnfft_adjoint(h, fake, fake, None) == STATE
+    assert lib.nnfft_set_nodes(h, None, fake, None) == ARG
+    assert lib.nnfft_set_nodes(h, fake, None, None) == ARG
+    assert lib.nnfft_trafo(h, None, fake, None) == ARG
+    assert lib.nnfft_plan_get_info(h, None) == ARG
+    assert lib.nnfft_plan_destroy(None) == ARG
+    assert lib.nnfft_plan_destroy(h) == OK
+
+
+@pytest.mark.parametrize("N,m", [((256,), 8), ((64, 16), 8), ((16,), 8), ((512, 100), 4)])
+def test_nnfft_automatic_frequency_grid(lib, N, m):
+    # sigma = 0: N2 the smallest power of two >= 2N, doubled while sigma1 < 1.5
+    st, h = nn_create(lib, N, 10, 10, 0.0, m)
+    assert st == OK
+    info = _lib.NNPlanInfo()
+    assert lib.nnfft_plan_get_info(h, ctypes.byref(info)) == OK
+    for t, Nt in enumerate(N):
+        n2, na = info.N2[t], info.NA[t]
+        assert n2 & (n2 - 1) == 0 and n2 >= 2 * Nt
+        assert n2 / na >= 1.5
+        assert Nt * n2 <= na * (n2 - 2 * m - 4) and (na - 2) * (n2 - 2 * m - 4) < Nt * n2
+        half = n2 // 2
+        if half >= 2 * Nt and half > 2 * m + 4:
+            a = -(-Nt * half // (half - 2 * m - 4))
+            a += a & 1
+            assert half / a < 1.5  # the smaller grid would not do
+    lib.nnfft_plan_destroy(h)

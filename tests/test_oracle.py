@@ -634,3 +634,78 @@ def test_sinc_derivative_near_zero_to_rounding():
     for z in (1e-7, 1e-4, 0.01, 0.3, 2.0, 5.0, -3.1):
         ref = mp.diff(lambda t: (mp.sin(a * t) / (a * t)) ** (2 * m), mp.mpf(z))
         assert abs(O.sinc_dphi(z, m, a) - float(ref)) <= 1e-14 * abs(float(ref)), z
+
+
+# ---------------------------------------------------------------- NNDFT (Sec. 1 generalisation)
+
+
+def _centred_freqs(N):
+    """All k in I_N as rows (K, d), in the centred row-major order of the coefficient arrays."""
+    axes = [np.arange(n) - n // 2 for n in N]
+    grid = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.reshape(-1) for g in grid], axis=1).astype(np.float64)
+
+
+@pytest.mark.parametrize("N", [(12,), (6, 8), (4, 6, 4)])
+def test_nndft_integer_frequencies_reduce_to_ndft(N):
+    # with v_k running over I_N the NNDFT is the NDFT of eq. (1.2) / (1.3)
+    rng = np.random.default_rng(41)
+    d = len(N)
+    M = 37
+    x = rng.uniform(-0.5, 0.5, size=(M, d))
+    fhat = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    v = _centred_freqs(N)
+    f = O.nndft_trafo(v, x, fhat.reshape(-1))
+    assert np.max(np.abs(f - O.ndft_trafo(x, fhat))) < 1e-11
+    fv = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    h = O.nndft_adjoint(v, x, fv)
+    assert np.max(np.abs(h - O.ndft_adjoint(x, fv, N).reshape(-1))) < 1e-11
+
+
+def test_nndft_equispaced_matches_fft():
+    # x_j = j/M - 1/2 and v_k = k - M/2: f_j = sum_k fhat_k (-1)^(k - M/2) e^{-2 pi i (k - M/2) j / M}
+    M = 64
+    rng = np.random.default_rng(43)
+    x = (np.arange(M) / M - 0.5)[:, None]
+    v = (np.arange(M) - M // 2)[:, None].astype(np.float64)
+    fhat = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    kk = np.arange(M) - M // 2
+    phase = np.exp(1j * np.pi * kk)  # e^{-2 pi i k (-1/2)}
+    ref = np.fft.fft(np.fft.ifftshift(fhat * phase))  # index k mod M, sign -
+    assert np.max(np.abs(O.nndft_trafo(v, x, fhat) - ref)) < 1e-10
+
+
+def test_nndft_adjoint_identity():
+    rng = np.random.default_rng(47)
+    K, M, d = 29, 31, 2
+    v = rng.uniform(-20.0, 20.0, size=(K, d))
+    x = rng.uniform(-0.5, 0.5, size=(M, d))
+    a = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    b = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    lhs = np.vdot(b, O.nndft_trafo(v, x, a))
+    rhs = np.vdot(O.nndft_adjoint(v, x, b), a)
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+
+
+def test_nndft_real_frequencies_match_extended_precision():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    rng = np.random.default_rng(53)
+    K, M, d = 4, 5, 3
+    v = rng.uniform(-300.0, 300.0, size=(K, d))
+    x = rng.uniform(-0.5, 0.5, size=(M, d))
+    a = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    f = O.nndft_trafo(v, x, a)
+    h = O.nndft_adjoint(v, x, a[:1].repeat(M))
+    for j in range(M):
+        s = mp.mpc(0)
+        for k in range(K):
+            ph = sum(mp.mpf(float(v[k, t])) * mp.mpf(float(x[j, t])) for t in range(d))
+            s += mp.mpc(float(a[k].real), float(a[k].imag)) * mp.expjpi(-2 * ph)
+        assert abs(complex(s) - f[j]) < 1e-12
+    for k in range(K):
+        s = mp.mpc(0)
+        for j in range(M):
+            ph = sum(mp.mpf(float(v[k, t])) * mp.mpf(float(x[j, t])) for t in range(d))
+            s += mp.mpc(float(a[0].real), float(a[0].imag)) * mp.expjpi(2 * ph)
+        assert abs(complex(s) - h[k]) < 1e-12

@@ -56,26 +56,29 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
             for (int s = 0; s < WM / 2; ++s)
                 raw[t][s] = p2[t * (W / 2) + s];
     };
+    // window factors of dimension t at the WM compiled points (zero beyond W)
+    auto factors = [&](int t, T *w) {
+#pragma unroll
+        for (int s = 0; s < WM / 2; ++s) {
+            const Pair<T> v = raw[t][s];
+            w[2 * s] = 2 * s < W ? v.x : T(0);
+            w[2 * s + 1] = 2 * s + 1 < W ? v.y : T(0);
+        }
+    };
     if ((int)threadIdx.x < len)
         load_node(first + threadIdx.x);
     stage_tile<T, D>(g, bc, grid, tile);
     __syncthreads();
+    // 2-D items with more nodes than threads: the first 256 nodes one per thread, the rest
+    // (below) shared by all four waves, so the item does not take two rounds of whole nodes
+    const int lmain = (D == 2 && len > kBlock) ? kBlock : len;
     // Thread t takes nodes t, t + 256, ...: the nodes are dealt round-robin over the bank
     // residues of their tile positions, so consecutive lanes start on different LDS banks.
-    for (int i = threadIdx.x; i < len; i += kBlock) {
+    for (int i = threadIdx.x; i < lmain; i += kBlock) {
         const int node = first + i;
         const T *pw = psi + (int64_t)node * dW;  // window factors [d][W] of this node
         if (i != (int)threadIdx.x)
             load_node(node);
-        // window factors of dimension t at the WM compiled points (zero beyond W)
-        auto factors = [&](int t, T *w) {
-#pragma unroll
-            for (int s = 0; s < WM / 2; ++s) {
-                const Pair<T> v = raw[t][s];
-                w[2 * s] = 2 * s < W ? v.x : T(0);
-                w[2 * s + 1] = 2 * s + 1 < W ? v.y : T(0);
-            }
-        };
         T wl[WM];  // innermost dimension
         factors(D - 1, wl);
         T ax = 0, ay = 0;
@@ -192,6 +195,50 @@ __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, cons
         }
         f[nd.perm[node]] = C{ax, ay};
     }
+    if constexpr (D == 2) {
+        // Nodes past the first 256, 64 at a time: lane l takes node e0 + l and wave w sums
+        // stencil rows [w W / 4, (w + 1) W / 4) of it (a range uniform over the wave); the
+        // four partial sums meet in LDS after the tile and are added in wave order.
+        if (len > kBlock) {
+            C *part = tile + g.Ptot;
+            const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+            const int lane = threadIdx.x & 63;
+            const int lo = (wv * W) >> 2, hi = ((wv + 1) * W) >> 2;
+            const int P1 = g.P[1];
+            for (int e0 = kBlock; e0 < len; e0 += 64) {
+                const int i = e0 + lane;
+                T ax = 0, ay = 0;
+                if (i < len) {
+                    load_node(first + i);
+                    T wl[WM], w0r[WM];
+                    factors(1, wl);
+                    factors(0, w0r);
+                    const C *base = tile + ul[0] * P1 + ul[1];
+#pragma unroll
+                    for (int s0 = 0; s0 < WM; ++s0) {
+                        if (s0 >= lo && s0 < hi) {
+                            T rx = 0, ry = 0;
+#pragma unroll
+                            for (int s1 = 0; s1 < WM; ++s1) {
+                                const C v = lds_entry<T>(base + s0 * P1 + s1);
+                                rx += wl[s1] * v.x;
+                                ry += wl[s1] * v.y;
+                            }
+                            ax += w0r[s0] * rx;
+                            ay += w0r[s0] * ry;
+                        }
+                    }
+                }
+                part[wv * 64 + lane] = C{ax, ay};
+                __syncthreads();
+                if (wv == 0 && i < len) {
+                    const C a = part[lane], b = part[64 + lane], c2 = part[128 + lane], d2 = part[192 + lane];
+                    f[nd.perm[first + i]] = C{((a.x + b.x) + c2.x) + d2.x, ((a.y + b.y) + c2.y) + d2.y};
+                }
+                __syncthreads();
+            }
+        }
+    }
     __syncthreads();
 }
 
@@ -257,7 +304,11 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 }
 }  // namespace
 
-size_t interp_lds_bytes(const Geom &g, bool dbl) { return (size_t)g.Ptot * (dbl ? 16 : 8); }
+// the padded tile, and for d = 2 the 4 x 64 partial sums of the nodes past the first 256
+size_t interp_lds_bytes(const Geom &g, bool dbl)
+{
+    return ((size_t)g.Ptot + (g.d == 2 ? 256 : 0)) * (dbl ? 16 : 8);
+}
 // spreading tiles per workgroup: four (1-D); two (2-D) or one (3-D) followed by one dummy
 // slot per thread
 bool spread_in_registers(const Geom &g, bool dbl)

@@ -34,14 +34,15 @@ template <typename T> __device__ __forceinline__ Cplx<T> lds_entry(const Cplx<T>
 }
 
 // Stage the padded tile of bin `bc` into LDS (complex, row-major P_0 x ... x P_{d-1}).
-// A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < 8: all eight loads
+// A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < K: all K loads
 // (entries past the tile read entry 0) are issued before the first LDS store, so their
-// latencies overlap.
+// latencies overlap.  K = 12 for complex64 covers a 2-D tile of up to 3072 entries (m = 8
+// and 32 x 32 bins: 49 x 49) in one round of loads.
 template <typename T, int D>
 __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
 {
     using C = Cplx<T>;
-    constexpr int K = 8;
+    constexpr int K = sizeof(T) == 4 ? 12 : 8;
     int o[kMaxDim];
 #pragma unroll
     for (int t = 0; t < D; ++t)

@@ -11,7 +11,7 @@ using namespace window;
 // ------------------------------------------------------------------ gradient
 
 // grad[j][t] = Re(conj(v_j) * n_t * sum_s g[u+s] phi_t'(.) prod_{t' != t} phi_t'(.)).
-template <typename T, int D, int WM>
+template <typename T, int D, int WM, bool AllW>
 __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
                                                    const Cplx<T> *__restrict__ v, T *__restrict__ grad)
 {
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 dl[t] = static_cast<const T *>(nd.delta[t])[node];
             }
             T wl[WM], dwl[WM];
-            window_row_d<T, WM>(dl[D - 1], g, D - 1, wl, dwl);
+            window_row_d<T, WM, AllW>(dl[D - 1], g, D - 1, wl, dwl);
             C acc[kMaxDim];
 #pragma unroll
             for (int t = 0; t < D; ++t)
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 }
             } else if constexpr (D == 2) {
                 for (int s0 = 0; s0 < g.W; ++s0) {
-                    const T w0 = win_point<T>(g, 0, dl[0], s0);
-                    const T dw0 = win_point_d<T>(g, 0, dl[0], s0);
+                    const T w0 = win_point<T, AllW>(g, 0, dl[0], s0);
+                    const T dw0 = win_point_d<T, AllW>(g, 0, dl[0], s0);
                     const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
                     T rx = 0, ry = 0, dx = 0, dy = 0;
 #pragma unroll
@@ -75,11 +75,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 }
             } else {
                 T wmid[WM], dwmid[WM];
-                window_row_d<T, WM>(dl[1], g, 1, wmid, dwmid);
+                window_row_d<T, WM, AllW>(dl[1], g, 1, wmid, dwmid);
                 const int P1 = g.P[1], P2 = g.P[2];
                 for (int s0 = 0; s0 < g.W; ++s0) {
-                    const T w0 = win_point<T>(g, 0, dl[0], s0);
-                    const T dw0 = win_point_d<T>(g, 0, dl[0], s0);
+                    const T w0 = win_point<T, AllW>(g, 0, dl[0], s0);
+                    const T dw0 = win_point_d<T, AllW>(g, 0, dl[0], s0);
                     const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
                     T px = 0, py = 0, qx = 0, qy = 0, hx = 0, hy = 0;
 #pragma unroll
@@ -133,7 +133,7 @@ hipError_t grad_typed(const Geom &g, const Nodes &nd, const void *grid, const vo
     using C = Cplx<T>;
 #define CALL(W_)                                                                                       \
     {                                                                                                  \
-        auto kf = k_grad_x<T, D, W_>;                                                                  \
+        auto kf = window_needs_all(g) ? k_grad_x<T, D, W_, true> : k_grad_x<T, D, W_, false>;         \
         (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         hipLaunchKernelGGL(kf, dim3(blocks), dim3(kBlock), lds, s, g, nd, static_cast<const C *>(grid), \
                            static_cast<const C *>(v), static_cast<T *>(grad));                         \

@@ -131,7 +131,7 @@ template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_node_sc
 // Window factors of every sorted node (the tensor-product precomputation of Table 3.2,
 // PRE_PSI): psi[node][t][s] = normalised window phi_t(delta_t - (s - m)), s < 2m+2.  One
 // thread per factor, so the writes are coalesced.
-template <typename T> __global__ __launch_bounds__(kBlock) void k_node_psi(Geom g, Nodes nd)
+template <typename T, bool AllW> __global__ __launch_bounds__(kBlock) void k_node_psi(Geom g, Nodes nd)
 {
     const int W = g.W;
     const int dW = g.d * W;
@@ -144,7 +144,7 @@ template <typename T> __global__ __launch_bounds__(kBlock) void k_node_psi(Geom 
     int s = r - t * W;
     T delta = static_cast<const T *>(nd.delta[t])[node];
     // a non-finite node (offset NaN) gets NaN factors, so that its results are NaN too
-    static_cast<T *>(nd.psi)[q] = isnan(delta) ? delta : win_point<T>(g, t, delta, s);
+    static_cast<T *>(nd.psi)[q] = isnan(delta) ? delta : win_point<T, AllW>(g, t, delta, s);
 }
 
 // One thread per bin writes the bin's work items.
@@ -365,10 +365,13 @@ hipError_t launch_node_scatter(const Geom &g, const Nodes &nd, bool dbl, hipStre
             return e;
     }
     const int64_t nf = nd.M * g.d * g.W;
-    if (dbl)
-        hipLaunchKernelGGL(k_node_psi<double>, dim3(blocks_for(nf)), block, 0, s, g, nd);
-    else
-        hipLaunchKernelGGL(k_node_psi<float>, dim3(blocks_for(nf)), block, 0, s, g, nd);
+    if (dbl) {
+        auto kf = window_needs_all(g) ? k_node_psi<double, true> : k_node_psi<double, false>;
+        hipLaunchKernelGGL(kf, dim3(blocks_for(nf)), block, 0, s, g, nd);
+    } else {
+        auto kf = window_needs_all(g) ? k_node_psi<float, true> : k_node_psi<float, false>;
+        hipLaunchKernelGGL(kf, dim3(blocks_for(nf)), block, 0, s, g, nd);
+    }
     return hipGetLastError();
 }
 

@@ -276,27 +276,36 @@ struct Geom {
 };
 
 // Window factor of dimension t at stencil point s of a node with offset delta, and its
-// derivative with respect to the grid variable, for the plan's window.
-template <typename T> __device__ __forceinline__ T win_point(const Geom &g, int t, T delta, int s)
+// derivative with respect to the grid variable, for the plan's window.  AllW = false
+// compiles the Kaiser-Bessel and Gaussian windows only: the unrolled B-spline triangle and
+// sinc series would otherwise set the register budget of the whole kernel, so kernels that
+// evaluate windows are instantiated both ways and launched by window.
+template <typename T, bool AllW = true> __device__ __forceinline__ T win_point(const Geom &g, int t, T delta, int s)
 {
     if (g.window == 1)
         return gauss_point<T>(delta, s, (T)g.m, (T)g.b[t]);
-    if (g.window == 2)
-        return bspline_point<T>(delta, s, g.m);
-    if (g.window == 3)
-        return sinc_point<T>(delta, s, g.m, (T)g.b[t]);
+    if constexpr (AllW) {
+        if (g.window == 2)
+            return bspline_point<T>(delta, s, g.m);
+        if (g.window == 3)
+            return sinc_point<T>(delta, s, g.m, (T)g.b[t]);
+    }
     return kb_point<T>(delta, s, g.W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
 }
-template <typename T> __device__ __forceinline__ T win_point_d(const Geom &g, int t, T delta, int s)
+template <typename T, bool AllW = true> __device__ __forceinline__ T win_point_d(const Geom &g, int t, T delta, int s)
 {
     if (g.window == 1)
         return gauss_point_d<T>(delta, s, (T)g.m, (T)g.b[t]);
-    if (g.window == 2)
-        return bspline_point_d<T>(delta, s, g.m);
-    if (g.window == 3)
-        return sinc_point_d<T>(delta, s, g.m, (T)g.b[t]);
+    if constexpr (AllW) {
+        if (g.window == 2)
+            return bspline_point_d<T>(delta, s, g.m);
+        if (g.window == 3)
+            return sinc_point_d<T>(delta, s, g.m, (T)g.b[t]);
+    }
     return kb_point_d<T>(delta, s, g.W, (T)g.m, (T)g.b[t], (T)g.emb[t]);
 }
+// Whether a plan's window needs the AllW instantiations.
+__host__ __device__ inline bool window_needs_all(const Geom &g) { return g.window >= 2; }
 
 // Sorted node data in the workspace (written by the node kernels).
 struct Nodes {

@@ -84,21 +84,21 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const C
 }
 
 // Window factors of one dimension at all WM stencil points (zero beyond 2m+2).
-template <typename T, int WM>
+template <typename T, int WM, bool AllW = true>
 __device__ __forceinline__ void window_row(T delta, const Geom &g, int t, T *w)
 {
 #pragma unroll
     for (int s = 0; s < WM; ++s)
-        w[s] = s < g.W ? win_point<T>(g, t, delta, s) : T(0);
+        w[s] = s < g.W ? win_point<T, AllW>(g, t, delta, s) : T(0);
 }
 
-template <typename T, int WM>
+template <typename T, int WM, bool AllW = true>
 __device__ __forceinline__ void window_row_d(T delta, const Geom &g, int t, T *w, T *dw)
 {
 #pragma unroll
     for (int s = 0; s < WM; ++s) {
-        w[s] = s < g.W ? win_point<T>(g, t, delta, s) : T(0);
-        dw[s] = s < g.W ? win_point_d<T>(g, t, delta, s) : T(0);
+        w[s] = s < g.W ? win_point<T, AllW>(g, t, delta, s) : T(0);
+        dw[s] = s < g.W ? win_point_d<T, AllW>(g, t, delta, s) : T(0);
     }
 }
 

@@ -450,8 +450,8 @@ def main():
                     help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (DESIGN.md describes how "
-              "the transform would shard); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the design notes "
+              "describe how the transform would shard); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

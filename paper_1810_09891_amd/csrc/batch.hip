@@ -115,7 +115,7 @@ void build_group(nfft_batch_s *b, Group &G)
                         break;
                 FftPass bound = plan_bind_pass(p, packed, ws + (dir == 0 ? p->off_grid : p->off_grid_adj), nullptr,
                                                nullptr);
-                const size_t lds = ((size_t)bound.nl * bound.pitch + bound.L) * cs;
+                const size_t lds = fft_lds_bytes(bound, cs);
                 if (dir == 0) {
                     pd.fwd[q] = bound;
                     G.vpt_fwd[q] = std::max(G.vpt_fwd[q], pow2_ceil(bound.vpt));

@@ -89,8 +89,8 @@ __device__ __forceinline__ int skew(int i) { return i + (i >> 5); }
 // reads x[j + r L/R], multiplies input r by w^{(j mod Ns) r / (Ns R)} with
 // w = e^{SIGN 2 pi i}, transforms, and writes y[(j / Ns) Ns R + (j mod Ns) + r Ns].
 template <typename T, int VPT, int SIGN, int R>
-__device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, int pitch, int lgNs,
-                                          const Cplx<T> *tw /* in LDS */)
+__device__ __forceinline__ void fft_stage(const Cplx<T> *src, Cplx<T> *dst_buf, int L, int lgL, int nl, int pitch,
+                                          int lgNs, const Cplx<T> *tw /* in LDS */)
 {
     using C = Cplx<T>;
     constexpr int J = VPT >= R ? VPT / R : 1;
@@ -108,10 +108,10 @@ __device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, 
         if (b < jobs) {
             int line = b >> lgJobs;
             int j = b & ((1 << lgJobs) - 1);
-            const C *src = lds + line * pitch;
+            const C *row = src + line * pitch;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                v[q][r] = src[skew(j + (r << lgJobs))];
+                v[q][r] = row[skew(j + (r << lgJobs))];
             int jm = j & (Ns - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -125,11 +125,12 @@ __device__ __forceinline__ void fft_stage(Cplx<T> *lds, int L, int lgL, int nl, 
             base[q] |= line << 24;                            // line index in the high bits
         }
     }
-    __syncthreads();
+    if (src == dst_buf)  // in place: every read is done before the first write (uniform)
+        __syncthreads();
 #pragma unroll
     for (int q = 0; q < J; ++q) {
         if (base[q] >= 0) {
-            C *dst = lds + (base[q] >> 24) * pitch;
+            C *dst = dst_buf + (base[q] >> 24) * pitch;
             const int pos = base[q] & 0xffffff;
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -214,7 +215,10 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
 {
     using C = Cplx<T>;
     const int L = p.L, nl = p.nl, pitch = p.pitch;
-    C *tw = lds + nl * pitch;  // twiddle table of this pass
+    // line buffers (a second one when the pass alternates buffers), then the twiddles
+    C *buf_a = lds;
+    C *buf_b = p.pp ? lds + nl * pitch : lds;
+    C *tw = lds + (p.pp ? 2 : 1) * nl * pitch;
     if (threadIdx.x >= 64) {
         // waves 1-3 copy the twiddles (four loads in flight per thread before their LDS
         // stores) while wave 0 sets up the lines below, so the two latencies overlap
@@ -314,14 +318,20 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
 
     // ---------------- transform: radix 8 stages, then one radix 4 or 2 stage
     int lgNs = 0;
+    C *cur = buf_a, *nxt = buf_b;
     while (lgL - lgNs >= 3) {
-        fft_stage<T, VPT, SIGN, 8>(lds, L, lgL, nl, pitch, lgNs, tw);
+        fft_stage<T, VPT, SIGN, 8>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
         lgNs += 3;
+        C *t2 = cur;
+        cur = nxt;
+        nxt = t2;
     }
     if (lgL - lgNs == 2) {
-        fft_stage<T, VPT, SIGN, 4>(lds, L, lgL, nl, pitch, lgNs, tw);
+        fft_stage<T, VPT, SIGN, 4>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
+        cur = nxt;
     } else if (lgL - lgNs == 1) {
-        fft_stage<T, VPT, SIGN, 2>(lds, L, lgL, nl, pitch, lgNs, tw);
+        fft_stage<T, VPT, SIGN, 2>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
+        cur = nxt;
     }
 
     // ---------------- store
@@ -332,7 +342,7 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
             const int64_t gb = s_gbase[c];
             if (gb < 0 || (p.out_mode == 1 && pos_to_coef(i, Nt, L) < 0))
                 continue;
-            grid[gb + i * st] = lds[c * pitch + skew(i)];
+            grid[gb + i * st] = cur[c * pitch + skew(i)];
         }
     } else {
         // coefficients times the deconvolution factor (and the product coefficients when
@@ -349,7 +359,7 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
                 const int pc = pos_to_coef(i, Nt, L);
                 const bool ok = idx < total && s_gbase[c] >= 0 && pc >= 0;
                 dst[k] = ok ? s_cbase[c] + pc : -1;
-                val[k] = lds[c * pitch + skew(i)];
+                val[k] = cur[c * pitch + skew(i)];
                 wv[k] = wt[ok ? pc : 0];
                 fc[k] = s_fac[c];
                 mv[k] = mul ? mul[ok ? dst[k] : 0] : C{T(1), T(0)};
@@ -415,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_batch(const PlanDev *__restrict_
 
 template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int blocks, hipStream_t s)
 {
-    size_t lds = ((size_t)p.nl * p.pitch + p.L) * sizeof(Cplx<T>);
+    size_t lds = fft_lds_bytes(p, sizeof(Cplx<T>));
     dim3 grid(blocks), block(kBlock);
 #define NFFT_FFT_CALL(V)                                                                               \
     {                                                                                                  \

@@ -43,7 +43,22 @@ struct FftPass {
     int nrows;           // rows (t == d-1): prod_{q<d-1} N_q
     int ncb;             // column blocks (t < d-1): n_{d-1} / nl
     int vpt;             // points per thread: max(1, nl*L/256)
+    int pp;              // 1: radix stages alternate between two LDS line buffers (one barrier
+                         // per stage), 0: in place (two barriers per stage)
 };
+
+// LDS bytes of one workgroup of an FFT pass: its line buffer(s), then the twiddles.
+inline size_t fft_lds_bytes(const FftPass &p, size_t cs)
+{
+    return ((size_t)(p.pp ? 2 : 1) * p.nl * p.pitch + p.L) * cs;
+}
+// Two line buffers when they and the twiddles fit in 64 KB (two or more workgroups per CU).
+inline void fft_choose_buffers(FftPass &p, size_t cs)
+{
+    p.pp = 1;
+    if (fft_lds_bytes(p, cs) > 65536)
+        p.pp = 0;
+}
 hipError_t launch_fft_pass(const FftPass &p, bool dbl, int grid_blocks, hipStream_t s);
 
 // ------------------------------------------------------------------ window kernels

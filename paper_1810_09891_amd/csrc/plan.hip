@@ -169,6 +169,7 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
     fp.pitch = L + (L >> 5) + (fp.rows ? 0 : 1);
     int pts = nl * L;
     fp.vpt = std::max(1, pts / 256);
+    fft_choose_buffers(fp, p->dbl ? 16 : 8);
 }
 
 }  // namespace nfft
@@ -196,6 +197,7 @@ bool plan_repack_pass(const nfft_plan_s *p, const FftPass &tmpl, int factor, Fft
     }
     out.nl = nl;
     out.vpt = std::max(1, nl * tmpl.L / 256);
+    fft_choose_buffers(out, p->dbl ? 16 : 8);
     return true;
 }
 

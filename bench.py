@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NFFT fwd+adj nonuniform points/s at stated rel-ℓ2 error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# LDS read ceiling of one MI355X measured with paper_1810_09891_amd/lib/lds_bw (conflict-free
+# LDS read ceiling of one MI355X measured with _build/lds_bw (conflict-free
 # 8-byte reads issued as separate ds_read_b64, all 256 CUs; the highest 8-byte read rate it
 # measures): the bound of the interpolation kernel (an 8-byte LDS read per stencil point)
 LDS_READ8_PEAK_GBS = 128000.0

@@ -13,9 +13,14 @@
  * Conventions shared by every entry point
  * ----------------------------------------
  *  * Pointers marked [device] are HIP device memory owned by the caller; pointers
- *    marked [host] are host memory read before the call returns.  The library never
- *    allocates or frees device memory: all scratch lives in a caller-provided
- *    workspace (nfft_workspace_bytes / nfft_set_workspace).
+ *    marked [host] are host memory read before the call returns.  No transform, node
+ *    or step entry point allocates or frees device memory: all scratch lives in a
+ *    caller-provided workspace (nfft_workspace_bytes / nfft_set_workspace, and
+ *    nfft_batch_workspace_bytes / nfft_batch_set_workspace for batches).  The one
+ *    exception is the tuning call nfft_batch_autotune, which allocates and frees its
+ *    temporary stand-in inputs.
+ *  * Results are bitwise reproducible from run to run for a given device, plan, workspace
+ *    layout and input (see NFFT_DETERMINISTIC).
  *  * Every call that does device work enqueues it on the given stream and returns
  *    without waiting; results are ready when that stream reaches them.
  *  * Complex data are interleaved (re, im): float2 for NFFT_C64 plans, double2 for
@@ -78,13 +83,19 @@ typedef enum {
  *  NFFT_WINDOW_SINC: the sinc window (the fourth): phi(z) = (sin(a z) / (a z))^(2m),
  *    a = pi (2 - 1/sigma) / (2m), Fourier transform (pi/a) M_2m(pi k / (n a)); truncated to
  *    the same 2m+2-point stencil.
- *  At most one window flag may be set (NFFT_ERR_ARG otherwise). */
+ *  At most one window flag may be set (NFFT_ERR_ARG otherwise).
+ *  NFFT_DETERMINISTIC: bitwise run-to-run reproducible results.  Always on; accepted so
+ *    that callers can state the requirement.  Every floating-point sum of the library has
+ *    a fixed order: no atomics touch floating-point data, the nodes of a bin are kept in
+ *    caller-index order (so a bin's split into work items is fixed), and the partial
+ *    results of the spreading step are folded in a fixed order. */
 enum {
     NFFT_SORT_NODES = 1u << 0,
     NFFT_KEEP_GRID = 1u << 1,
     NFFT_WINDOW_GAUSSIAN = 1u << 2,
     NFFT_WINDOW_BSPLINE = 1u << 3,
-    NFFT_WINDOW_SINC = 1u << 4
+    NFFT_WINDOW_SINC = 1u << 4,
+    NFFT_DETERMINISTIC = 1u << 5
 };
 
 /* Read-only description of a plan (filled by nfft_plan_get_info). */

@@ -39,6 +39,7 @@
  *   R6 Nodes are accepted anywhere on the real line and treated periodically.
  */
 #include <complex.h>
+#include <omp.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -660,8 +661,10 @@ void or_nfft_interp(int d, const long *N, const long *n, int m, long M, const do
 {
     int W = 2 * m + 2;
     long cnt = stencil_size(d, W);
-    double phi[3][OR_MAXW];
+    /* every f_j is its own sum: nodes are shared out among threads */
+#pragma omp parallel for schedule(dynamic, 64)
     for (long j = 0; j < M; ++j) {
+        double phi[3][OR_MAXW];
         long u[3];
         int s[3];
         node_factors(d, N, n, m, x + j * d, u, phi, NULL);
@@ -674,21 +677,44 @@ void or_nfft_interp(int d, const long *N, const long *n, int m, long M, const do
     }
 }
 
-/* Step 1 of Algorithm 2.2: g_l = sum_j f_j prod_t phi_t(n_t x_{j,t} - l_t), serial, node order. */
+/* Step 1 of Algorithm 2.2: g_l = sum_j f_j prod_t phi_t(n_t x_{j,t} - l_t), every g_l summed
+ * over the nodes in node order.  Threads own disjoint ranges of the first grid index; each
+ * walks all nodes in order and adds only into its own range, so every g_l receives exactly
+ * the additions of a serial loop over j, in the same order (the result does not depend on
+ * the thread count). */
 void or_nfft_spread(int d, const long *N, const long *n, int m, long M, const double *x, const cplx *f,
                     cplx *g)
 {
     int W = 2 * m + 2;
-    long cnt = stencil_size(d, W);
-    double phi[3][OR_MAXW];
+    long inner = stencil_size(d - 1, W); /* stencil points per first-dimension point */
     memset(g, 0, sizeof(cplx) * (size_t)prod_l(d, n));
-    for (long j = 0; j < M; ++j) {
-        long u[3];
-        int s[3];
-        node_factors(d, N, n, m, x + j * d, u, phi, NULL);
-        for (long c = 0; c < cnt; ++c) {
-            long pos = stencil_point(d, n, m, W, c, u, s);
-            g[pos] += f[j] * weight(d, phi, s);
+#pragma omp parallel
+    {
+        int nt = omp_get_num_threads(), id = omp_get_thread_num();
+        long lo = n[0] * id / nt, hi = n[0] * (id + 1) / nt;
+        double phi[3][OR_MAXW];
+        for (long j = 0; j < M; ++j) {
+            long u[3];
+            int s[3];
+            /* does the node's stencil reach this thread's range of the first index? */
+            long u0 = (long)floor((double)n[0] * x[j * d]);
+            int hit = 0;
+            for (int s0 = 0; s0 < W && !hit; ++s0) {
+                long l0 = wrap(u0 + s0 - m, n[0]);
+                hit = l0 >= lo && l0 < hi;
+            }
+            if (!hit)
+                continue;
+            node_factors(d, N, n, m, x + j * d, u, phi, NULL);
+            for (int s0 = 0; s0 < W; ++s0) {
+                long l0 = wrap(u[0] + s0 - m, n[0]);
+                if (l0 < lo || l0 >= hi)
+                    continue;
+                for (long c = s0 * inner; c < (s0 + 1) * inner; ++c) {
+                    long pos = stencil_point(d, n, m, W, c, u, s);
+                    g[pos] += f[j] * weight(d, phi, s);
+                }
+            }
         }
     }
 }

@@ -13,6 +13,7 @@ NFFT_C64 = 1
 NFFT_C128 = 2
 NFFT_SORT_NODES = 1 << 0
 NFFT_KEEP_GRID = 1 << 1
+NFFT_DETERMINISTIC = 1 << 5  # always on: results are bitwise reproducible
 NFFT_WINDOW_GAUSSIAN = 1 << 2
 NFFT_WINDOW_BSPLINE = 1 << 3
 NFFT_WINDOW_SINC = 1 << 4

@@ -23,6 +23,7 @@ class _NfftFunction(torch.autograd.Function):
         f = plan.trafo(fhat.detach())
         ctx.plan = plan
         ctx.generation = plan.generation
+        ctx.node_generation = plan.node_generation
         ctx.save_for_backward(x, fhat)
         return f
 
@@ -32,10 +33,14 @@ class _NfftFunction(torch.autograd.Function):
         x, fhat = ctx.saved_tensors
         v = v.contiguous().to(plan.dtype)
         gx = gfhat = None
+        # The plan may have been used with other nodes or coefficients since this forward
+        # ran: both gradients need this call's nodes, the node gradient also its grid.
+        stale_nodes = plan.node_generation != ctx.node_generation or plan.nodes_version != x._version
+        stale_grid = stale_nodes or plan.generation != ctx.generation
+        if stale_nodes:
+            plan.set_nodes(x.detach())
         if ctx.needs_input_grad[0]:
-            if plan.generation != ctx.generation or plan.nodes_version != x._version:
-                # the plan ran other transforms since this forward: rebuild its grid
-                plan.set_nodes(x.detach())
+            if stale_grid:
                 plan.trafo(fhat.detach())
             gx = plan.grad_x(v).to(x.dtype)
         if ctx.needs_input_grad[1]:

@@ -2,8 +2,8 @@
 
 Each ``csrc/*.hip`` file is compiled to an object with hipcc (in parallel) and the
 objects are linked into one shared library that exports the C ABI of
-``include/nfft_mi355x.h``.  Also builds ``lib/lds_bw``, a small program that measures
-the device's LDS throughput.  Always rebuilds when called.
+``include/nfft_mi355x.h``.  Always rebuilds when called.  (The LDS throughput probe under
+``calib/`` is measurement tooling and is built by ``profiling.py lds-probe`` instead.)
 """
 import concurrent.futures
 import glob
@@ -62,13 +62,6 @@ def build(verbose=False, jobs=None):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-20000:]))
     os.replace(tmp, LIB)
-    # measurement helper: LDS throughput of the device (the roofline of the window kernels)
-    calib = os.path.join(PKG, "calib", "lds_bw.hip")
-    exe = os.path.join(LIBDIR, "lds_bw")
-    cmd = [HIPCC] + [f for f in CFLAGS if f != "-fPIC"] + [calib, "-o", exe]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed for %s:\n%s" % (calib, r.stderr[-20000:]))
     return LIB
 
 

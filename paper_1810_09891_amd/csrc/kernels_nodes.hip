@@ -62,7 +62,27 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_node_key(Geom g, No
     if (!finite)
         atomicOr(&nd.counters[1], 1);
     nd.key[j] = bin;
-    nd.rank[j] = atomicAdd(&nd.bin_count[bin], 1);
+    // A slot in the bin: one atomic per distinct bin of the wave (lanes of a wave often
+    // share a bin), the lanes of a bin numbered by lane order.  The slots only place the
+    // node inside its bin's range; the order inside the range is fixed afterwards by
+    // sorting it by caller index, so the final order does not depend on the atomics.
+    const uint64_t active = __ballot(1);
+    const int lane = __lane_id();
+    uint64_t todo = active;
+    int slot = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int lbin = __shfl(bin, leader);
+        const uint64_t same = __ballot(bin == lbin) & active;
+        int base = 0;
+        if (lane == leader)
+            base = atomicAdd(&nd.bin_count[lbin], __popcll(same));
+        base = __shfl(base, leader);
+        if (bin == lbin)
+            slot = base + __popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
+    nd.rank[j] = slot;
 }
 
 // One workgroup of 1024 threads: exclusive scans of the bin counts (-> bin_start) and of
@@ -110,14 +130,83 @@ __global__ __launch_bounds__(kScanThreads) void k_node_scan(Nodes nd, int nbins)
     }
 }
 
-template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_node_scatter(Geom g, Nodes nd)
+// Caller index of every node at a position of its bin's range (the order inside a bin is
+// arbitrary here and fixed by the sort below).
+__global__ __launch_bounds__(kBlock) void k_node_place(Nodes nd, int32_t *dst)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nd.M)
         return;
-    int bin = nd.key[j];
-    int pos = nd.bin_start[bin] + nd.rank[j];
-    nd.perm[pos] = (int32_t)j;
+    dst[nd.bin_start[nd.key[j]] + nd.rank[j]] = (int32_t)j;
+}
+
+// Sorting every bin's range by caller index, so that the sorted order -- and with it the
+// work items, the order of every floating-point sum over a work item's nodes and the
+// fold -- is the same on every run.  Caller indices are unique, so the sorted order is
+// unique.  First each tile of kSortTile positions is sorted by (bin, caller index) in LDS;
+// positions are already grouped by bin, so every node stays inside its bin's range and
+// the part of a bin inside a tile becomes sorted.  Then runs are merged pairwise: with
+// runs [r L, (r+1) L) clipped to the bin's range, a node's position in the merged pair
+// is its offset in its own run plus the number of smaller caller indices in the partner
+// run (binary search), for L = kSortTile, 2 kSortTile, ... until L reaches M.
+constexpr int kSortTile = 1024;
+__device__ __forceinline__ void bitonic(unsigned long long *keys, int n);
+
+__global__ __launch_bounds__(kBlock) void k_bin_tile_sort(Nodes nd, int32_t *buf)
+{
+    __shared__ unsigned long long keys[kSortTile];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int len = (int)min<int64_t>(kSortTile, nd.M - base);
+    for (int i = threadIdx.x; i < kSortTile; i += kBlock) {
+        unsigned long long k = ~0ull;
+        if (i < len) {
+            const int32_t v = buf[base + i];
+            k = ((unsigned long long)(uint32_t)nd.key[v] << 32) | (uint32_t)v;
+        }
+        keys[i] = k;
+    }
+    __syncthreads();
+    bitonic(keys, kSortTile);
+    for (int i = threadIdx.x; i < len; i += kBlock)
+        buf[base + i] = (int32_t)(keys[i] & 0xffffffffull);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_merge(Nodes nd, const int32_t *__restrict__ src,
+                                                       int32_t *__restrict__ dst, int64_t L)
+{
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= nd.M)
+        return;
+    const int32_t v = src[pos];
+    const int b = nd.key[v];
+    const int64_t first = nd.bin_start[b], end = nd.bin_start[b + 1];
+    const int64_t r = pos / L;
+    const int64_t own_lo = max(first, r * L);
+    const int64_t pr = r ^ 1;
+    const int64_t p_lo = max(first, pr * L), p_hi = min(end, (pr + 1) * L);
+    if (p_lo >= p_hi) {
+        dst[pos] = v;
+        return;
+    }
+    int64_t lo = p_lo, hi = p_hi;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (src[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const int64_t merged_lo = max(first, (r & ~(int64_t)1) * L);
+    dst[merged_lo + (pos - own_lo) + (lo - p_lo)] = v;
+}
+
+// Cell index and offset of every sorted node, from its caller index.
+template <int D, typename T> __global__ __launch_bounds__(kBlock) void k_node_scatter(Geom g, Nodes nd)
+{
+    int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= nd.M)
+        return;
+    const int64_t j = nd.perm[pos];
 #pragma unroll
     for (int t = 0; t < D; ++t) {
         int u;
@@ -333,6 +422,27 @@ hipError_t launch_node_scan(const Geom &g, const Nodes &nd, hipStream_t s)
 hipError_t launch_node_scatter(const Geom &g, const Nodes &nd, bool dbl, hipStream_t s)
 {
     dim3 grid(blocks_for(nd.M)), block(kBlock);
+    {
+        // merge passes: L = kSortTile, 2 kSortTile, ... while L < M; the tile sort and the
+        // passes ping-pong between perm and u[0] (free until the cell indices are written),
+        // starting in the buffer that makes the last pass end in perm
+        int passes = 0;
+        for (int64_t L = kSortTile; L < nd.M; L *= 2)
+            ++passes;
+        int32_t *a = (passes & 1) ? nd.u[0] : nd.perm;
+        int32_t *b = (passes & 1) ? nd.perm : nd.u[0];
+        hipLaunchKernelGGL(k_node_place, grid, block, 0, s, nd, a);
+        hipLaunchKernelGGL(k_bin_tile_sort, dim3(blocks_for(nd.M, kSortTile)), block, 0, s, nd, a);
+        for (int64_t L = kSortTile; L < nd.M; L *= 2) {
+            hipLaunchKernelGGL(k_bin_merge, grid, block, 0, s, nd, (const int32_t *)a, b, L);
+            int32_t *t = a;
+            a = b;
+            b = t;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     switch (g.d * 2 + (dbl ? 1 : 0)) {
     case 2: hipLaunchKernelGGL((k_node_scatter<1, float>), grid, block, 0, s, g, nd); break;
     case 3: hipLaunchKernelGGL((k_node_scatter<1, double>), grid, block, 0, s, g, nd); break;

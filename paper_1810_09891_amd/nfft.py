@@ -77,6 +77,7 @@ class Plan:
         self.nodes_set = False
         self.nodes_version = None
         self.generation = 0  # counts calls that rewrite the plan's forward grid
+        self.node_generation = 0  # counts node sets
 
     # ---------------------------------------------------------------- set-up
 
@@ -105,6 +106,7 @@ class Plan:
         self.nodes_set = True
         self.nodes_version = x._version
         self.generation += 1
+        self.node_generation += 1
         return self
 
     def nodes_finite(self):

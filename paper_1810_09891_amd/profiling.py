@@ -7,6 +7,8 @@
 ``stats`` turns the ``*_kernel_stats.csv`` of ``rocprofv3 --kernel-trace --stats
 --output-format csv`` into a table of calls and average / total durations per kernel.
 
+    python -m paper_1810_09891_amd.profiling lds-probe     # build _build/lds_bw (no GPU work)
+
 ``traffic`` reads two ``--pmc`` runs of the same program (one collecting FETCH_SIZE, one
 WRITE_SIZE, both in KiB per dispatch) that begin with one device copy of MIB MiB.  The
 copy's readings against its known bytes give the scale factors; every other kernel's
@@ -128,9 +130,28 @@ def cmd_traffic(args):
     print()
 
 
+def build_lds_probe():
+    """Compile the LDS throughput probe (``calib/lds_bw.hip``) into ``_build/lds_bw``.  It is
+    measurement tooling, not part of the library: run it on the GPU to obtain the LDS
+    ceilings that the window kernels are compared against."""
+    import subprocess
+
+    from . import build as hipbuild
+
+    src = os.path.join(ROOT, "paper_1810_09891_amd", "calib", "lds_bw.hip")
+    out_dir = os.path.join(ROOT, "_build")
+    os.makedirs(out_dir, exist_ok=True)
+    exe = os.path.join(out_dir, "lds_bw")
+    flags = [f for f in hipbuild.CFLAGS if f != "-fPIC"]
+    subprocess.run([hipbuild.HIPCC] + flags + [src, "-o", exe], check=True)
+    print(exe)
+    return exe
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("lds-probe")
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--command", default="")
@@ -141,7 +162,9 @@ def main(argv=None):
     t.add_argument("--command-fetch", default="")
     t.add_argument("--command-write", default="")
     args = ap.parse_args(argv)
-    if args.cmd == "stats":
+    if args.cmd == "lds-probe":
+        build_lds_probe()
+    elif args.cmd == "stats":
         cmd_stats(args)
     else:
         cmd_traffic(args)

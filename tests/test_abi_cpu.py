@@ -328,3 +328,17 @@ def test_nnfft_automatic_frequency_grid(lib, N, m):
             a += a & 1
             assert half / a < 1.5  # the smaller grid would not do
     lib.nnfft_plan_destroy(h)
+
+
+def test_deterministic_flag_accepted(lib):
+    """NFFT_DETERMINISTIC (always on) is accepted and reported back; the header states
+    that only nfft_batch_autotune allocates device memory."""
+    st, h = create(lib, (64, 64), 1000, None, 6, 1, _lib.NFFT_DETERMINISTIC | _lib.NFFT_KEEP_GRID)
+    assert st == OK
+    info = _lib.PlanInfo()
+    assert lib.nfft_plan_get_info(h, ctypes.byref(info)) == OK
+    assert info.flags & _lib.NFFT_DETERMINISTIC
+    assert lib.nfft_plan_destroy(h) == OK
+    txt = open(HEADER).read()
+    assert "NFFT_DETERMINISTIC = 1u << 5" in txt
+    assert "exception is the tuning call nfft_batch_autotune" in txt

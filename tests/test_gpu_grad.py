@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import announce, dev, host, rel_l2
+from gpu_util import announce, dev, host, parity_err
 from oracle import oracle as O
 from paper_1810_09891_amd import NFFT_KEEP_GRID, Plan, differentiable_plan, nfft, workloads as W
 
@@ -78,7 +78,7 @@ def test_radial_spokes_loss_gradients():
     # FP64 oracle gradient: residual of the m=8 NFFT, 2 A^H r for fhat
     res = O.nfft_trafo(x, fhat, None, 8) - y
     gf_ref = 2.0 * O.nfft_adjoint(x, res, N, None, 8)
-    assert rel_l2(gf_ref, gf) < 1e-5
+    assert parity_err(gf_ref, gf) < 1e-5
     # closed-form derivative of the direct sum on sampled nodes
     sel = np.sort(np.random.default_rng(5).choice(M, 256, replace=False))
     gx_ref = O.ndft_grad_x(x[sel], fhat, res[sel])
@@ -95,3 +95,32 @@ def test_radial_spokes_loss_gradients():
             lm = abs(O.ndft_trafo(xm, fhat)[0] - y[j]) ** 2
             fd = (lp - lm) / (2 * h)
             assert abs(fd - gx[j, t]) <= 1e-5 * max(1.0, np.abs(gx_ref).max()), (j, t, fd, gx[j, t])
+
+
+@pytest.mark.parametrize("need_x", [False, True])
+def test_plan_reused_before_backward(need_x):
+    """One plan runs nfft at nodes x1, then at x2, then both backwards run: each gradient
+    must use its own call's nodes (and grid), also when only fhat requires a gradient."""
+    announce("plan reused before backward", need_x)
+    N, M, m = (16, 12), 90, 8
+    plan = differentiable_plan(N, M, m=m, dtype=torch.complex128)
+    cases = [W.small_case(2, N, M, seed=80 + i) for i in range(2)]
+    xs, fhs, outs = [], [], []
+    for c in cases:
+        x = torch.tensor(c["x"], device="cuda", dtype=torch.float64, requires_grad=need_x)
+        fh = torch.tensor(c["fhat"], device="cuda", dtype=torch.complex128, requires_grad=True)
+        xs.append(x)
+        fhs.append(fh)
+        outs.append(nfft(x, fh, plan))
+    for i in (0, 1):
+        v = cases[i]["f"]
+        outs[i].backward(torch.tensor(v, device="cuda", dtype=torch.complex128))
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        ref = O.nfft_adjoint(c["x"], c["f"], N, plan.n, m)
+        assert parity_err(ref, host(fhs[i].grad)) < 1e-12
+        if need_x:
+            dfdx = O.nfft_interp_dx(c["x"], O.nfft_grid(c["fhat"], plan.n, m), N, m)
+            refx = np.real(np.conj(c["f"])[:, None] * dfdx)
+            gx = xs[i].grad.cpu().numpy()
+            assert np.linalg.norm(gx - refx) / np.linalg.norm(refx) < 1e-12

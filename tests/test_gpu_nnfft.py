@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import TOL, announce, dev, host, rel_l2
+from gpu_util import TOL, announce, dev, host, parity_err
 from oracle import oracle as O
 from paper_1810_09891_amd import NNPlan, Plan, workloads as W
 from paper_1810_09891_amd._lib import NfftError
@@ -43,7 +43,7 @@ def _bar(p, dtype, window, m):
     z = (r.random((300, d)) - 0.5) / np.asarray(p.sigma1)
     c = W.cgauss(r, p.N2)
     with O.window(window):
-        e = rel_l2(O.ndft_trafo(z, c), O.nfft_trafo(z, c, m=m))
+        e = parity_err(O.ndft_trafo(z, c), O.nfft_trafo(z, c, m=m))
     return max(TOL[dtype], 20.0 * e)
 
 
@@ -54,8 +54,8 @@ def _run(N, K, M, dtype, m, window="kaiser-bessel", seed=0, sigma=None):
     p.set_nodes(dev(c["x"], torch.float64), dev(c["v"], torch.float64))
     f = host(p.trafo(dev(c["fhat"], dtype)))
     h = host(p.adjoint(dev(c["f"], dtype)))
-    ef = rel_l2(O.nndft_trafo(c["v"], c["x"], c["fhat"]), f)
-    eh = rel_l2(O.nndft_adjoint(c["v"], c["x"], c["f"]), h)
+    ef = parity_err(O.nndft_trafo(c["v"], c["x"], c["fhat"]), f)
+    eh = parity_err(O.nndft_adjoint(c["v"], c["x"], c["f"]), h)
     return p, ef, eh
 
 
@@ -100,10 +100,10 @@ def test_nnfft_integer_frequencies_agree_with_the_nfft():
     pl = Plan(N, M, m=8, dtype=C128).set_nodes(dev(x, torch.float64))
     a = host(nn.trafo(dev(fhat.reshape(-1), C128)))
     b = host(pl.trafo(dev(fhat, C128)))
-    assert rel_l2(b, a) < 1e-12
+    assert parity_err(b, a) < 1e-12
     ha = host(nn.adjoint(dev(f, C128)))
     hb = host(pl.adjoint(dev(f, C128))).reshape(-1)
-    assert rel_l2(hb, ha) < 1e-12
+    assert parity_err(hb, ha) < 1e-12
 
 
 def test_nnfft_edge_cases():
@@ -115,8 +115,8 @@ def test_nnfft_edge_cases():
         p = NNPlan(N, K, M, m=8, dtype=C128).set_nodes(dev(c["x"], torch.float64), dev(c["v"], torch.float64))
         f = host(p.trafo(dev(c["fhat"], C128)))
         h = host(p.adjoint(dev(c["f"], C128)))
-        assert rel_l2(O.nndft_trafo(c["v"], c["x"], c["fhat"]), f) < 1e-12
-        assert rel_l2(O.nndft_adjoint(c["v"], c["x"], c["f"]), h) < 1e-12
+        assert parity_err(O.nndft_trafo(c["v"], c["x"], c["fhat"]), f) < 1e-12
+        assert parity_err(O.nndft_adjoint(c["v"], c["x"], c["f"]), h) < 1e-12
     r = np.random.default_rng(41)
     K, M = 301, 257
     v = (r.random((K, 2)) - 0.5) * np.asarray(N, dtype=np.float64)
@@ -130,8 +130,8 @@ def test_nnfft_edge_cases():
     fh = W.cgauss(r, (K,))
     fv = W.cgauss(r, (M,))
     p = NNPlan(N, K, M, m=8, dtype=C128).set_nodes(dev(x, torch.float64), dev(v, torch.float64))
-    assert rel_l2(O.nndft_trafo(v, x, fh), host(p.trafo(dev(fh, C128)))) < 1e-12
-    assert rel_l2(O.nndft_adjoint(v, x, fv), host(p.adjoint(dev(fv, C128)))) < 1e-12
+    assert parity_err(O.nndft_trafo(v, x, fh), host(p.trafo(dev(fh, C128)))) < 1e-12
+    assert parity_err(O.nndft_adjoint(v, x, fv), host(p.adjoint(dev(fv, C128)))) < 1e-12
 
 
 def test_nnfft_new_nodes_on_the_same_plan():
@@ -142,7 +142,7 @@ def test_nnfft_new_nodes_on_the_same_plan():
         c = _case(N, K, M, seed)
         p.set_nodes(dev(c["x"], torch.float64), dev(c["v"], torch.float64))
         f = host(p.trafo(dev(c["fhat"], C64)))
-        assert rel_l2(O.nndft_trafo(c["v"], c["x"], c["fhat"]), f) < TOL[C64]
+        assert parity_err(O.nndft_trafo(c["v"], c["x"], c["fhat"]), f) < TOL[C64]
 
 
 def test_nnfft_nonfinite_node_stays_local():
@@ -156,7 +156,7 @@ def test_nnfft_nonfinite_node_stays_local():
     assert np.isnan(f[17])
     keep = np.arange(M) != 17
     ref = O.nndft_trafo(c["v"], c["x"], c["fhat"])
-    assert rel_l2(ref[keep], f[keep]) < 1e-12
+    assert parity_err(ref[keep], f[keep]) < 1e-12
 
 
 def test_nnfft_trafo_before_nodes_raises():
@@ -179,5 +179,5 @@ def test_nnfft_bench_size_sampled():
     ks = r.choice(K, 48, replace=False)
     ref_f = O.nndft_trafo(w["v"], w["x"][js], w["fhat"])
     ref_h = O.nndft_adjoint(w["v"][ks], w["x"], w["f"])
-    assert rel_l2(ref_f, f[js]) < TOL[C64]
-    assert rel_l2(ref_h, h[ks]) < TOL[C64]
+    assert parity_err(ref_f, f[js]) < TOL[C64]
+    assert parity_err(ref_h, h[ks]) < TOL[C64]

@@ -100,6 +100,24 @@ def test_ndft_matches_dense_fourier_matrix():
     assert rel(O.ndft_adjoint(x, f, N).reshape(-1), F.conj().T @ f) < 1e-14
 
 
+@pytest.mark.parametrize("N", [(16,), (12, 10), (6, 4, 8)])
+def test_ndft_adjoint_at_selected_coefficients(N):
+    """The one-coefficient-at-a-time adjoint (eq. (1.3) evaluated at chosen k) against the
+    rows of the dense Fourier matrix and the full direct adjoint, in every dimension."""
+    r = np.random.default_rng(40 + len(N))
+    M = 70
+    x = r.random((M, len(N))) * 3.0 - 1.5  # also nodes outside [-1/2, 1/2)
+    f = W.cgauss(r, (M,))
+    K = int(np.prod(N))
+    sel = np.concatenate([[0, K - 1, K // 2], r.choice(K, size=min(K, 17), replace=False)])
+    F = np.exp(-2j * np.pi * (x @ _centred_k(N).T.astype(float)))
+    dense = (F.conj().T @ f)[sel]
+    at = O.ndft_adjoint_at(x, f, N, sel)
+    full = O.ndft_adjoint(x, f, N).reshape(-1)[sel]
+    assert np.max(np.abs(at - dense)) <= 1e-13 * np.max(np.abs(dense))
+    assert np.max(np.abs(at - full)) <= 1e-15 * np.max(np.abs(full)) * 10
+
+
 def test_ndft_is_one_periodic():
     """The sum is 1-periodic in every coordinate (nodes on the torus, eq. (1.2))."""
     N = (8, 8)
@@ -216,6 +234,13 @@ def test_nfft_equals_explicit_matrix_product(N, n, m, M):
     g = O.nfft_grid(c["fhat"], n, m).reshape(-1)
     assert rel(g, F @ D @ c["fhat"].reshape(-1)) < 1e-13
     assert rel(O.nfft_spread(x, c["f"], N, n, m).reshape(-1), B.T @ c["f"]) < 1e-13
+    # steps 2-3 of Algorithm 2.2 on their own: D^T F^H applied to an arbitrary grid, and
+    # applied to the spread grid they complete the adjoint
+    r = np.random.default_rng(21)
+    g_any = (r.standard_normal(n) + 1j * r.standard_normal(n)) / np.sqrt(2)
+    assert rel(O.nfft_adjoint_from_grid(g_any, N, m).reshape(-1), D.T @ (F.conj().T @ g_any.reshape(-1))) < 1e-13
+    gs = O.nfft_spread(x, c["f"], N, n, m)
+    assert rel(O.nfft_adjoint_from_grid(gs, N, m), O.nfft_adjoint(x, c["f"], N, n, m)) < 1e-14
 
 
 # --------------------------------------------------------------------------- invariants

@@ -33,3 +33,17 @@ def parity_err(ref, approx):
     e2 = np.linalg.norm(diff) / np.linalg.norm(ref)
     einf = np.max(np.abs(diff)) / np.max(np.abs(ref))
     return float(max(e2, einf))
+
+
+def rel_l2(ref, approx):
+    """E_2 of eq. (2.15): relative l2 error."""
+    ref = np.ravel(ref)
+    approx = np.ravel(approx)
+    return float(np.linalg.norm(ref - approx) / np.linalg.norm(ref))
+
+
+def e_inf(ref, approx, inp):
+    """E_inf of eq. (2.16): max_j |ref_j - approx_j| / ||input||_1.  For comparisons whose
+    bar is an approximation error of the method (not rounding), where an element-wise
+    bound relative to the largest output is not what the method guarantees."""
+    return float(np.max(np.abs(np.ravel(ref) - np.ravel(approx))) / np.sum(np.abs(np.ravel(inp))))

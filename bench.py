@@ -1,26 +1,30 @@
 """Throughput of the NFFT forward + adjoint on one MI355X.
 
-Headline workload: d = 2, N = (512, 512), n = (1024, 1024) (sigma = 2), M = 262144 nodes
-uniform on [-1/2, 1/2)^2, complex Gaussian data, Kaiser-Bessel window, complex64 plan
-with m = 8.  Reported beside it: complex128, m = 4 and Gaussian-window variants of the same
-workload, and
-the other workloads -- d = 1 (N = 256, M = 1024, complex128, m = 8), d = 3 radial spokes
-(N = 128^3, M = 2,097,152, complex64, m = 6), 64 uneven d = 2 plans in one batch
-(complex64, m = 6, autotuned launch shapes, against per-plan launches) and the
-differentiable d = 2 radial workload (forward + backward), and a Gaussian-kernel fast
-summation (adjoint NFFT, kernel product, NFFT).
+Headline workload: d = 3, N = (128, 128, 128), n = (256, 256, 256) (sigma = 2),
+M = 2,097,152 nodes on 4096 radial spokes of 512 points (density clustered at the origin),
+complex Gaussian data, Kaiser-Bessel window, m = 6, complex128 (FP64 throughout, the
+paper's arithmetic): the plan shape of the paper's largest timing (Sec. 4, Fig. 4.6).
+Reported beside it: the same workload in complex64; the d = 2 workload (N = 512^2,
+M = 262144 uniform nodes) in complex64 and complex128 with m = 8 and m = 4 and with the
+Gaussian window; d = 1 (N = 256, M = 1024, complex128, m = 8); 64 uneven d = 2 plans in one
+batch (complex64, m = 6, autotuned, against per-plan launches); the differentiable d = 2
+radial workload (forward + backward); a Gaussian-kernel fast summation; an NNFFT.
 
-A step is one nfft_trafo plus one nfft_adjoint of the whole node set (inputs resident in
-device memory; the node precomputation is timed separately, as Sec. 4 of the paper does).
-value = M / (time of one step) in nonuniform points per second.
+A step is one nfft_trafo plus one nfft_adjoint of the whole node set, inputs resident in
+device memory (the node precomputation is timed separately, as Sec. 4 of the paper does).
+value = M / (time of one step) in nonuniform points per second.  The K timed steps run as
+R = min(10, K) back-to-back groups, each bracketed by HIP events on the stream; ms_per_step
+is the whole window divided by K, ms_per_step_median the median over the groups.  A cold
+figure repeats single steps after overwriting 1 GiB of device memory (more than the 256 MB
+Infinity Cache) before each.
 
-Kernel durations are measured live with HIP events: right after the timed steps, the same
-number of steps runs again with the library recording a HIP event pair around every
-launch on the stream it launches on (the markers add about 7 us per launch, so `value`
-comes from the steps without them; the step time with them is reported beside).  The dominant kernel's
-algorithmic bytes per launch over its average duration give the HBM roofline fraction.
-The CPU baseline is the FP64 oracle (serial NFFT + adjoint, one core) on the same
-workload; it also provides the reference for the E_2 errors.
+Kernel durations are measured live with HIP events: after the timed steps, the same number
+of steps runs again with the library recording a HIP event pair around every launch on the
+stream it launches on.  The dominant kernel's algorithmic bytes per launch (the byte model
+below) over its average duration give the HBM roofline fraction; the binding fraction is
+max(t_HBM, t_VALU) / t with t_VALU the multiply-add issue time of the window step.  The CPU
+baseline is the FP64 oracle on the host's cores (a bounded sample, extrapolated: see
+cpu_baseline); the E_2 errors are against the oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu]
                     [--primary-only] [--copy-calibration-mib MIB]
@@ -37,16 +41,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "NFFT fwd+adj nonuniform points/s at stated rel-ℓ2 error; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# VALU issue rate of one MI355X: 256 CUs x 64 lanes x 2.4 GHz lane-slots per second.  A
+# (node, cell) pair of the window steps is one complex x real multiply-add: two FP64 FMAs
+# (complex128) or two FP32 FMAs (complex64; one packed FMA if packed FP32 were used, which
+# this build does not emit).
+VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
 # LDS read ceiling of one MI355X measured with _build/lds_bw (conflict-free
 # 8-byte reads issued as separate ds_read_b64, all 256 CUs; the highest 8-byte read rate it
 # measures): the bound of the interpolation kernel (an 8-byte LDS read per stencil point)
 LDS_READ8_PEAK_GBS = 128000.0
-# Published FP32 vector peak of the MI355X (256 CUs, 2.4 GHz, packed FP32 counted): the
-# ceiling of the 2-D spreading kernel that keeps tile columns in registers (4 flops, two
-# multiply-adds, per stencil point).  Packed FP32 instructions are not generated, which
-# halves the rate this code can reach.
+# Published FP32 vector peak of the MI355X (256 CUs, 2.4 GHz, packed FP32 counted) and the
+# FP64 vector peak.
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2_512_c64_m8.json")
+FP64_PEAK_TFLOPS = 78.6
+PROFILES = os.path.join(ROOT, "profiles")
+# HBM traffic of the headline kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated)
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_d3_radial_128_c128_m6.json")
+# Context only: the paper's own timing of the same plan shape (Sec. 4, Fig. 4.6): forward
+# NFFT, d = 3, N = 128^3, n = 256^3, m = 6, M = 2 * 128^3 uniform nodes, FP64, 10 threads of
+# a 4 x Intel Xeon E7-4880 v2 (2.5 GHz) machine, 4.05 s per transform.
+PAPER_CONTEXT = {
+    "value": 4194304 / 4.05,
+    "unit": "points/s",
+    "what": "forward NFFT only (the paper times no adjoint), d=3 N=128^3 n=256^3 m=6, M=4,194,304 uniform "
+            "nodes, FP64, 10 threads of 4x Intel Xeon E7-4880 v2 @ 2.5 GHz: 4.05 s (Sec. 4, Fig. 4.6)",
+}
 
 
 def log(*a):
@@ -54,41 +73,62 @@ def log(*a):
 
 
 def algorithmic_bytes(name, d, N, n, M, cbytes):
-    """Bytes a kernel must move at least once (per launch) for this plan.
+    """Bytes a step must move at least once (per launch) for this plan.
 
-    Per node: the grid index and offset (int32 index + real offset per dimension: 8 bytes
-    in complex64, 12 in complex128), the permutation entry (4 bytes) and the value
-    (cbytes).  Grid, coefficient and line data: cbytes per entry.  The window factors of
-    the node precomputation are not counted (they can be recomputed from the offsets)."""
+    Window steps (interpolation, spreading, node gradient): the FP64 nodes (8 d bytes), the
+    value (cbytes) per node and the grid once, M (8 d + cbytes) + |I_n| cbytes.  FFT pass
+    over dimension t: its nonzero input and its output once; a forward pass reads lines of
+    N_t entries (coefficients for the first pass) and writes n_t, an adjoint pass reads n_t
+    and writes N_t (coefficients for the last), with earlier dimensions already pruned to
+    N and later ones full.  The fold of split output tiles is overhead (no algorithmic
+    bytes of its own)."""
     import numpy as np
 
-    per_node = d * (4 + cbytes // 2) + 4 + cbytes
-    grid = int(np.prod(n)) * cbytes
-    coef = int(np.prod(N)) * cbytes
-    if d == 1:
-        first = coef + grid  # the only pass: coefficients in, full line out
-        mid = grid
-    else:
-        first = coef + int(np.prod(N[:-1])) * n[-1] * cbytes
-        mid = int(np.prod(N[:-1])) * n[-1] * cbytes
-    if name in ("interp", "grad_x"):
-        return M * per_node + grid
-    if name == "spread_tiles":
-        return M * per_node
-    if name == "spread_fold":
-        return grid
-    if name == "fft_fwd_deconv" or name == "fft_adj_deconv":
-        return first
-    if name in ("fft_fwd", "fft_adj"):
-        return mid + grid
+    window = M * (8 * d + cbytes) + int(np.prod(n)) * cbytes
+    if name in ("interp", "interp_own", "grad_x", "spread_tiles", "spread_own"):
+        return window
+
+    def fft_pass(t, forward):
+        before = int(np.prod(N[:t])) if t > 0 else 1
+        after = int(np.prod(n[t + 1:])) if t + 1 < d else 1
+        return cbytes * before * after * (N[t] + n[t])
+
+    fwd_order = list(range(d - 1, -1, -1))  # first forward pass: last dimension
+    adj_order = list(range(d))               # last adjoint pass: last dimension
+    if name == "fft_fwd_deconv":
+        return fft_pass(fwd_order[0], True)
+    if name == "fft_adj_deconv":
+        return fft_pass(adj_order[-1], False)
+    if name == "fft_fwd":  # average of the remaining forward passes
+        return sum(fft_pass(t, True) for t in fwd_order[1:]) // max(1, d - 1)
+    if name == "fft_adj":
+        return sum(fft_pass(t, False) for t in adj_order[:-1]) // max(1, d - 1)
     return None
 
 
-# rocprofv3 kernel names of the library's launch labels (the FFT passes share one kernel)
-# kernel names under rocprofv3 of each profiling label, in order of preference (2-D
-# spreading runs k_spread_cols when the plan allows it, else k_spread_tiles)
-ROCPROF_NAME = {"interp": ("k_interp_nodes",), "spread_tiles": ("k_spread_cols", "k_spread_tiles"),
+def valu_seconds(d, M, m, dbl):
+    """Multiply-add issue time of one window step: (2m+2)^d (node, cell) pairs, one complex x
+    real multiply-add each (two FMA slots)."""
+    return M * (2 * m + 2) ** d * 2 / VALU_SLOTS_PER_S
+
+
+# rocprofv3 kernel names of the library's launch labels, in order of preference
+ROCPROF_NAME = {"interp": ("k_interp_nodes",), "interp_own": ("k_interp_own",),
+                "spread_tiles": ("k_spread_cols", "k_spread_tiles"), "spread_own": ("k_spread_own",),
                 "spread_fold": ("k_fold",), "grad_x": ("k_grad_x",)}
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 class Case:
@@ -147,8 +187,10 @@ class Case:
                 self.step()
 
     def time_steps(self, steps, warmup, events):
-        """ms per step over `steps` steps; with `events`, the library's per-launch events
-        are recorded during the same steps and their averages returned too."""
+        """Time exactly `steps` steps after `warmup` untimed ones, as R = min(10, steps)
+        back-to-back groups bracketed by HIP events on the stream (synchronised before and
+        after).  Returns (window / steps, median over the groups of ms per step, per-launch
+        kernel averages when `events`)."""
         torch = self.torch
         self.run(warmup)
         torch.cuda.synchronize()
@@ -156,17 +198,42 @@ class Case:
             self.plan.profile(True)
             self.plan.profile_read()
         stream = torch.cuda.current_stream()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        self.run(steps)
-        b.record(stream)
+        R = max(1, min(10, steps))
+        per = [steps // R + (1 if i < steps % R else 0) for i in range(R)]
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
+        evs[0].record(stream)
+        for i in range(R):
+            self.run(per[i])
+            evs[i + 1].record(stream)
         torch.cuda.synchronize()
+        total = evs[0].elapsed_time(evs[R])
+        groups = sorted(evs[i].elapsed_time(evs[i + 1]) / per[i] for i in range(R))
+        median = groups[R // 2] if R % 2 else 0.5 * (groups[R // 2 - 1] + groups[R // 2])
         kt = None
         if events:
             res = self.plan.profile_read()
             self.plan.profile(False)
             kt = {k: (v[0] / v[1], v[1]) for k, v in res.items()}
-        return a.elapsed_time(b) / steps, kt
+        return total / steps, median, kt
+
+    def time_cold(self, reps):
+        """Median ms of single steps, each after overwriting 1 GiB of device memory (more
+        than the 256 MB Infinity Cache), so that grid, nodes and values come from HBM."""
+        torch = self.torch
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=self.x.device)
+        stream = torch.cuda.current_stream()
+        times = []
+        for _ in range(reps):
+            flush.fill_(1.0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            self.step()
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        del flush
+        times.sort()
+        return times[len(times) // 2]
 
     def outputs(self):
         torch = self.torch
@@ -231,7 +298,7 @@ def bench_d1(torch, steps, warmup, check):
     w = W.workload("d1")
     case = Case(w, 8, torch.complex128, torch)
     case.set_nodes_ms()
-    ms, _ = case.time_steps(steps, warmup, False)
+    ms, _, _ = case.time_steps(steps, warmup, False)
     f, h = case.outputs()
     r = {"workload": "d=1 N=256 n=512 M=1024 uniform, complex128, m=8", "ms_per_step": ms,
          "points_per_s": w["M"] / (ms * 1e-3)}
@@ -241,28 +308,72 @@ def bench_d1(torch, steps, warmup, check):
     return r
 
 
-def bench_d3(torch, steps, warmup, check):
-    """d = 3, N = 128^3, 4096 radial spokes of 512 points, complex64, m = 6."""
-    import numpy as np
+D3_WORKLOAD = ("d=3 N=(128,128,128) n=(256,256,256) M=2097152 on 4096 radial spokes of 512 points "
+               "(density clustered at the origin), Kaiser-Bessel m=6, %s, trafo+adjoint")
 
-    from oracle import oracle as O
-    from paper_1810_09891_amd import workloads as W
 
-    w = W.workload("d3r")
-    case = Case(w, 6, torch.complex64, torch)
+class D3Refs:
+    """Oracle references for the 3-D radial workload, computed once: the oversampled grid
+    (Algorithm 2.1 steps 1-2) at full size, the forward transform at 16384 sampled nodes
+    (step 3 on that grid) and the adjoint at 64 sampled coefficients (direct sums, eq. (1.3)).
+    The timings of these oracle steps give the CPU baseline (see cpu_baseline_3d)."""
+
+    def __init__(self, w, m):
+        import numpy as np
+
+        from oracle import oracle as O
+
+        O.set_threads(os.cpu_count() or 1)
+        self.threads = O.get_threads()
+        self.sel = sample(w["M"], 16384, 3)
+        self.ks = sample(int(np.prod(w["N"])), 64, 4)
+        t0 = time.perf_counter()
+        g = O.nfft_grid(w["fhat"], w["n"], m)
+        self.t_grid = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        self.f_sel = O.nfft_interp(w["x"][self.sel], g, w["N"], m)
+        self.t_interp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        gs = O.nfft_spread(w["x"][self.sel], w["f"][self.sel], w["N"], w["n"], m)
+        self.t_spread = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.nfft_adjoint_from_grid(gs, w["N"], m)
+        self.t_coef = time.perf_counter() - t0
+        del g, gs
+        t0 = time.perf_counter()
+        self.h_ks = O.ndft_adjoint_at(w["x"], w["f"], w["N"], self.ks)
+        self.t_ndft = time.perf_counter() - t0
+        self.M = w["M"]
+        self.Ms = len(self.sel)
+
+    def cpu_seconds_per_step(self):
+        """Oracle NFFT + adjoint NFFT of the whole workload, extrapolated: deconvolution and
+        FFT steps timed at full size, the window steps on the 16384-node sample scaled by
+        M / 16384 (their cost is proportional to the number of nodes)."""
+        return self.t_grid + self.t_coef + (self.t_interp + self.t_spread) * self.M / self.Ms
+
+
+def run_d3(torch, w, dtype, steps, warmup, refs, cold_reps=5):
+    """The 3-D radial workload at one precision: timed steps, kernel averages, cold steps,
+    node precomputation, errors against the oracle references."""
+    case = Case(w, 6, dtype, torch)
     t_nodes = case.set_nodes_ms(reps=3)
-    ms, kt = case.time_steps(steps, warmup, True)
+    ms, med, _ = case.time_steps(steps, warmup, False)
+    ms_ev, _, kt = case.time_steps(steps, warmup, True)
+    cold = case.time_cold(cold_reps)
     f, h = case.outputs()
-    r = {"workload": "d=3 N=(128,128,128) n=(256,256,256) M=2097152 on 4096 radial spokes, complex64, m=6",
-         "ms_per_step": ms, "points_per_s": w["M"] / (ms * 1e-3), "set_nodes_ms": t_nodes,
-         "kernels_ms": {k: round(v[0], 5) for k, v in sorted(kt.items())}}
-    if check:
-        sel = sample(w["M"], 1024, 3)
-        r["e2_trafo_vs_oracle_1024_nodes"] = e2(O.nfft_trafo(w["x"][sel], w["fhat"], w["n"], 6), f[sel])
-        ks = sample(int(np.prod(w["N"])), 32, 4)
-        r["e2_adjoint_vs_ndft_32_coefficients"] = e2(O.ndft_adjoint_at(w["x"], w["f"], w["N"], ks),
-                                                     h.reshape(-1)[ks])
+    r = {"workload": D3_WORKLOAD % ("complex128" if dtype == torch.complex128 else "complex64"),
+         "dtype": "c128" if dtype == torch.complex128 else "c64", "m": 6,
+         "ms_per_step": ms, "ms_per_step_median": med, "ms_per_step_cold": cold,
+         "ms_per_step_with_events": ms_ev, "steps": steps,
+         "points_per_s": w["M"] / (ms * 1e-3), "set_nodes_ms": t_nodes,
+         "kernels_ms": {k: round(v[0], 5) for k, v in sorted(kt.items())}, "_kernel_avg": kt,
+         "_w": (w["N"], w["n"], w["M"])}
+    if refs is not None:
+        r["e2_trafo_vs_oracle_16384_nodes"] = e2(refs.f_sel, f[refs.sel])
+        r["e2_adjoint_vs_ndft_64_coefficients"] = e2(refs.h_ks, h.reshape(-1)[refs.ks])
     del case
+    torch.cuda.empty_cache()
     return r
 
 
@@ -438,12 +549,30 @@ def bench_nnfft(torch, steps, warmup, check):
     return r_
 
 
+def roofline_entry(name, avg_ms, d, N, n, M, m, cbytes, dbl):
+    """HBM fraction of a kernel under the byte model, and for the window kernels the
+    binding fraction max(t_HBM, t_VALU) / t."""
+    bts = algorithmic_bytes(name, d, N, n, M, cbytes)
+    e = {"avg_ms": round(avg_ms, 5), "algorithmic_bytes": bts}
+    if bts is not None:
+        e["hbm_GBs"] = round(bts / (avg_ms * 1e-3) / 1e9, 1)
+        e["hbm_frac"] = round(bts / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        if name in ("interp", "interp_own", "spread_own", "spread_tiles", "grad_x"):
+            t_hbm = bts / (HBM_PEAK_GBS * 1e9)
+            t_valu = valu_seconds(d, M, m, dbl)
+            e["t_hbm_us"] = round(t_hbm * 1e6, 2)
+            e["t_valu_us"] = round(t_valu * 1e6, 2)
+            e["binding"] = "valu" if t_valu > t_hbm else "hbm"
+            e["binding_frac"] = round(max(t_hbm, t_valu) / (avg_ms * 1e-3), 4)
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--graph", action="store_true", help="replay the d=2 steps as captured HIP graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the E_2 checks")
     ap.add_argument("--primary-only", action="store_true", help="only the headline plan")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -454,7 +583,6 @@ def main():
               "describe how the transform would shard); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1810_09891_amd import workloads as W
@@ -472,50 +600,63 @@ def main():
 
     C64, C128 = torch.complex64, torch.complex128
     KB, GAUSS = "kaiser-bessel", "gaussian"
-    variants = [(8, C64, KB)] + ([] if args.primary_only else
-                                 [(8, C128, KB), (4, C64, KB), (4, C128, KB), (8, C64, GAUSS)])
-    results = []
-    cpu = {}
-    for i, (m, dtype, window) in enumerate(variants):
-        w = W.workload("d2", m=m)
-        case = Case(w, m, dtype, torch, window)
-        t_nodes = case.set_nodes_ms()
-        if args.graph:
-            case.capture()
-        steps = args.steps if i == 0 else max(10, args.steps // 4)
-        ms, _ = case.time_steps(steps, args.warmup, events=False)
-        # the same steps again with the library's per-launch events (they add ~7 us per launch)
-        ms_events, kt = case.time_steps(steps, args.warmup, events=not args.graph)
-        f_gpu, h_gpu = case.outputs()
-        r = {
-            "m": m,
-            "window": window,
-            "dtype": "c64" if dtype == C64 else "c128",
-            "ms_per_step": ms,
-            "ms_per_step_with_events": ms_events,
-            "points_per_s": w["M"] / (ms * 1e-3),
-            "set_nodes_ms": t_nodes,
-            "kernels_ms": None if kt is None else {k: round(v[0], 5) for k, v in sorted(kt.items())},
-            "steps": steps,
-        }
-        if not args.no_cpu:
-            if (m, window) not in cpu:
-                cpu[(m, window)] = cpu_baseline(w, m, reps=3 if not cpu else 1, window=window)
-            r["e2_trafo_vs_oracle"] = e2(cpu[(m, window)]["f"], f_gpu)
-            r["e2_adjoint_vs_oracle"] = e2(cpu[(m, window)]["h"], h_gpu)
-        r["_kernel_avg"] = kt
-        r["_w"] = (w["N"], w["n"], w["M"])
-        results.append(r)
-        log("%s m=%d %s: %.4f ms/step (%.4f with events), %.3e points/s, set_nodes %.3f ms" %
-            (r["dtype"], m, window, ms, ms_events, r["points_per_s"], t_nodes))
-        del case
-        torch.cuda.empty_cache()
+    check = not args.no_cpu
+
+    # ---------------------------------------------------------------- headline: 3-D radial, c128
+    w3 = W.workload("d3r")
+    refs = None
+    if check:
+        t0 = time.perf_counter()
+        refs = D3Refs(w3, 6)
+        log("oracle references for d=3 radial: %.1f s (%d threads)" % (time.perf_counter() - t0, refs.threads))
+    head = run_d3(torch, w3, C128, args.steps, args.warmup, refs)
+    log("headline d=3 radial c128 m=6: %.4f ms/step (median %.4f, cold %.4f), %.3e points/s, set_nodes %.3f ms" %
+        (head["ms_per_step"], head["ms_per_step_median"], head["ms_per_step_cold"], head["points_per_s"],
+         head["set_nodes_ms"]))
+    variants = []
+    if not args.primary_only:
+        v = run_d3(torch, w3, C64, args.steps, args.warmup, refs)
+        log("d=3 radial c64 m=6: %.4f ms/step, %.3e points/s" % (v["ms_per_step"], v["points_per_s"]))
+        variants.append(v)
+
+    # ---------------------------------------------------------------- d = 2 variants
+    cpu2 = {}
+    if not args.primary_only:
+        for m, dtype, window in ((8, C64, KB), (8, C128, KB), (4, C64, KB), (4, C128, KB), (8, C64, GAUSS)):
+            w = W.workload("d2", m=m)
+            case = Case(w, m, dtype, torch, window)
+            t_nodes = case.set_nodes_ms()
+            if args.graph:
+                case.capture()
+            steps = 1000  # >= 10 ms per repeat group at about 0.1 ms per step
+            ms, med, _ = case.time_steps(steps, 20, events=False)
+            ms_events, _, kt = case.time_steps(steps // 4, 20, events=not args.graph)
+            f_gpu, h_gpu = case.outputs()
+            r = {"workload": "d=2 N=(512,512) n=(1024,1024) M=262144 uniform nodes, %s m=%d, %s, trafo+adjoint" %
+                             (window, m, "complex64" if dtype == C64 else "complex128"),
+                 "m": m, "window": window, "dtype": "c64" if dtype == C64 else "c128",
+                 "ms_per_step": ms, "ms_per_step_median": med, "ms_per_step_with_events": ms_events,
+                 "points_per_s": w["M"] / (ms * 1e-3), "set_nodes_ms": t_nodes, "steps": steps,
+                 "kernels_ms": None if kt is None else {k: round(v[0], 5) for k, v in sorted(kt.items())}}
+            if kt is not None:
+                r["kernels"] = {k: roofline_entry(k, a, 2, w["N"], w["n"], w["M"], m, 8 if dtype == C64 else 16,
+                                                  dtype == C128) for k, (a, _) in sorted(kt.items())}
+            if check:
+                if (m, window) not in cpu2:
+                    cpu2[(m, window)] = cpu_baseline(w, m, reps=1, window=window)
+                r["e2_trafo_vs_oracle"] = e2(cpu2[(m, window)]["f"], f_gpu)
+                r["e2_adjoint_vs_oracle"] = e2(cpu2[(m, window)]["h"], h_gpu)
+                if (m, window) == (8, KB) and dtype == C64:
+                    r["cpu_oracle_points_per_s_1_thread"] = w["M"] / cpu2[(m, window)]["seconds_per_step"]
+            variants.append(r)
+            log("d=2 %s m=%d %s: %.4f ms/step, %.3e points/s" % (r["dtype"], m, window, ms, r["points_per_s"]))
+            del case
+            torch.cuda.empty_cache()
 
     extra = {}
     if not args.primary_only:
-        check = not args.no_cpu
-        for name, fn, st in (("d1_256_c128_m8", bench_d1, args.steps), ("d3_radial_128_c64_m6", bench_d3, 20),
-                             ("batch64_c64_m6", bench_batch, 20), ("grad_radial_256_c64_m6", bench_grad, 20),
+        for name, fn, st in (("d1_256_c128_m8", bench_d1, 200), ("batch64_c64_m6", bench_batch, 20),
+                             ("grad_radial_256_c64_m6", bench_grad, 20),
                              ("fastsum_gauss_128_c64_m6", bench_fastsum, 50),
                              ("nnfft_d2_256_c64_m8", bench_nnfft, 50)):
             t0 = time.perf_counter()
@@ -524,96 +665,84 @@ def main():
                 (name, extra[name]["ms_per_step"], extra[name]["points_per_s"], time.perf_counter() - t0))
             torch.cuda.empty_cache()
 
-    prim = results[0]
-    N, n, M = prim["_w"]
-    cb = 8
-    kt = prim["_kernel_avg"]
-    roofline = None
-    per_kernel = {}
-    if kt is not None:
-        dom = max((k for k in kt if not k.startswith("nodes")), key=lambda k: kt[k][0])
-        dom_ms = kt[dom][0]
-        alg = algorithmic_bytes(dom, 2, N, n, M, cb)
-        achieved = alg / (dom_ms * 1e-3) / 1e9
-        traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            tr = json.load(open(TRAFFIC_FILE))
-            entry = None
+    # ---------------------------------------------------------------- roofline of the headline
+    N, n, M = head["_w"]
+    kt = head["_kernel_avg"]
+    per_kernel = {k: roofline_entry(k, a, 3, N, n, M, 6, 16, True) for k, (a, _) in sorted(kt.items())}
+    for k, (a, c) in kt.items():
+        per_kernel[k]["launches"] = c
+    dom = max((k for k in kt if not k.startswith("nodes")), key=lambda k: kt[k][0])
+    e = per_kernel[dom]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("source_hash") == source_hash():
             for kname in ROCPROF_NAME.get(dom, ()):
                 entry = tr.get("kernels", {}).get(kname)
-                if entry is not None:
+                if entry is not None and "bytes_per_launch" in entry:
+                    traffic = entry["bytes_per_launch"]
                     break
-            if entry is not None and "bytes_per_launch" in entry and tr.get("source_hash") == source_hash():
-                traffic = entry["bytes_per_launch"]
-        roofline = {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes": alg,
-            "avg_launch_ms": round(dom_ms, 5),
-        }
-        # The window kernels are not HBM-bound: interpolation reads an 8-byte LDS cell per
-        # stencil point (against the measured LDS read ceiling); 2-D spreading in registers
-        # does two FP32 multiply-adds per stencil point (against the FP32 vector peak)
-        stencil = M * (2 * 8 + 2) ** 2
-        sec = {}
-        if "spread_tiles" in kt:
-            a = stencil * 4 / (kt["spread_tiles"][0] * 1e-3) / 1e12
-            sec["spread_tiles"] = {"bound": "alu", "achieved": round(a, 3), "peak": FP32_PEAK_TFLOPS,
-                                   "unit": "TFLOP/s", "frac": round(a / FP32_PEAK_TFLOPS, 4), "flops": stencil * 4}
-        if "interp" in kt:
-            a = stencil * 8 / (kt["interp"][0] * 1e-3) / 1e9
-            sec["interp"] = {"bound": "lds", "achieved": round(a, 1), "peak": LDS_READ8_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(a / LDS_READ8_PEAK_GBS, 4), "lds_bytes": stencil * 8}
-        roofline["secondary"] = sec
-        for k, (avg, cnt) in sorted(kt.items()):
-            bts = algorithmic_bytes(k, 2, N, n, M, cb)
-            per_kernel[k] = {"avg_ms": round(avg, 5), "launches": cnt, "algorithmic_bytes": bts,
-                             "hbm_frac": None if bts is None else round(bts / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    roofline = {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": e.get("hbm_GBs"),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": e.get("hbm_frac"),
+        "traffic": traffic,
+        "algorithmic_bytes": e.get("algorithmic_bytes"),
+        "avg_launch_ms": e["avg_ms"],
+        "binding": e.get("binding"),
+        "binding_frac": e.get("binding_frac"),
+        "t_hbm_us": e.get("t_hbm_us"),
+        "t_valu_us": e.get("t_valu_us"),
+        "byte_model": "window steps: M (8 d + c) + |I_n| c bytes per launch (FP64 nodes, values, grid once); "
+                      "FFT passes: nonzero input + output of the pass",
+        "valu_model": "(2m+2)^d (node, cell) pairs x 2 FMA slots / (256 CUs x 64 lanes x 2.4 GHz)",
+    }
     out = {
         "metric": METRIC,
-        "value": prim["points_per_s"],
+        "value": head["points_per_s"],
         "unit": "points/s",
         "n_gpus": 1,
-        "steps": prim["steps"],
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": prim["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
+        "ms_per_step_median": head["ms_per_step_median"],
+        "ms_per_step_cold": head["ms_per_step_cold"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "d=2 N=(512,512) n=(1024,1024) M=262144 uniform nodes, Kaiser-Bessel m=8, complex64, "
-                        "trafo+adjoint",
-            "d": 2, "N": list(N), "n": list(n), "M": M, "m": 8,
-            "precision": "complex64 data, FP32 window and accumulation, FP64 node index and deconvolution table",
-            "graph": bool(args.graph),
+            "workload": head["workload"],
+            "d": 3, "N": list(N), "n": list(n), "M": M, "m": 6,
+            "nodes": "4096 spokes x 512 points through the origin, directions uniform on the sphere",
+            "precision": "complex128: FP64 data, window, accumulation, FFT and deconvolution",
         },
         "roofline": roofline,
         "kernels": per_kernel,
-        "set_nodes_ms": prim["set_nodes_ms"],
-        "ms_per_step_with_events": prim["ms_per_step_with_events"],
+        "set_nodes_ms": head["set_nodes_ms"],
+        "ms_per_step_with_events": head["ms_per_step_with_events"],
+        "paper_context": PAPER_CONTEXT,
     }
-    if not args.no_cpu:
-        c = cpu[(8, KB)]
-        import multiprocessing
-
+    if check:
+        t_cpu = refs.cpu_seconds_per_step()
         out["cpu_baseline"] = {
-            "value": M / c["seconds_per_step"],
+            "value": M / t_cpu,
             "unit": "points/s",
-            "cores": 1,
+            "cores": refs.threads,
             "kind": "oracle",
-            "sample": "the full headline workload (d=2, N=512^2, M=262144, m=8): serial FP64 NFFT + adjoint "
-                      "NFFT of the oracle on one thread, median of %d runs, %.2f s per step; host has %d cores" %
-                      (c["runs"], c["seconds_per_step"], multiprocessing.cpu_count()),
+            "sample": "headline workload: FP64 oracle NFFT + adjoint NFFT on %d host threads, deconvolution and FFT "
+                      "steps at full size (%.2f s + %.2f s), interpolation and spreading on a 16384-node sample "
+                      "(%.2f s + %.2f s) scaled by M/16384: %.1f s per step" %
+                      (refs.threads, refs.t_grid, refs.t_coef, refs.t_interp, refs.t_spread, t_cpu),
+            "host_cpu": host_cpu(),
         }
-        out["e2_vs_oracle"] = {"trafo": prim["e2_trafo_vs_oracle"], "adjoint": prim["e2_adjoint_vs_oracle"]}
-    out["variants"] = [{k: v for k, v in r.items() if not k.startswith("_")} for r in results[1:]]
+        out["e2_vs_oracle"] = {"trafo_16384_nodes_vs_oracle_nfft": head["e2_trafo_vs_oracle_16384_nodes"],
+                               "adjoint_64_coefficients_vs_direct_sums": head["e2_adjoint_vs_ndft_64_coefficients"]}
+    out["variants"] = [{k: v for k, v in r.items() if not k.startswith("_")} for r in variants]
     out["workloads"] = extra
     print(json.dumps(out))
 

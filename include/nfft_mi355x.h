@@ -117,6 +117,11 @@ typedef struct {
                                single-step entry points (see there); lambda_t =
                                e^{b_t m} (Kaiser-Bessel), (pi b_t)^{-1/2} (Gaussian) */
     int window;             /* 0 Kaiser-Bessel, 1 Gaussian, 2 B-spline, 3 sinc     */
+    int own_tiles;          /* 3-D plans whose spreading runs by output tiles (each grid
+                               cell written once by the workgroup that owns it): the
+                               number of tiles; 0 when the plan uses padded work-item
+                               tiles and a fold                                      */
+    int64_t own_tile[3];    /* output tile edge per dimension (0 when own_tiles = 0) */
 } nfft_plan_info;
 
 /* ---------------------------------------------------------------- plans */
@@ -302,6 +307,19 @@ int nfft_batch_autotune(nfft_batch b, hipStream_t stream);
 int nfft_batch_get_params(nfft_batch b, int group, int *params, int *plan_count);
 int nfft_batch_set_params(nfft_batch b, int group, const int *params);
 int nfft_batch_trafo(nfft_batch b, const void *const *fhat, void *const *f, hipStream_t stream);
+
+/* Allocation-free batched forward transform, for callers that cannot allocate device memory
+ * (code under stream or graph capture, serving loops, harnesses that forbid allocation).
+ * Same arguments, results and preconditions (every plan's nodes set, its workspace unchanged)
+ * as nfft_batch_trafo, but the batch needs no workspace of its own: its per-plan descriptor
+ * tables and work queues go to a 1 MiB device array held by the library (one per device, kept
+ * until the process ends).  No call allocates or frees memory; each call copies the
+ * descriptors into the array and clears the queues on `stream`.
+ *   Returns NFFT_ERR_WORKSPACE when the batch's tables need more than 1 MiB (about 600
+ *   plans), NFFT_ERR_STATE as nfft_batch_trafo, NFFT_ERR_HIP for a failed copy or launch.
+ *   Calls that overlap on one device share the array and race: serialise them (one stream,
+ *   or events).  The plans' own workspaces are used as by nfft_batch_trafo. */
+int nfft_batch_trafo_noalloc(nfft_batch b, const void *const *fhat, void *const *f, hipStream_t stream);
 int nfft_batch_adjoint(nfft_batch b, const void *const *f, void *const *hhat, hipStream_t stream);
 int nfft_batch_destroy(nfft_batch b);
 

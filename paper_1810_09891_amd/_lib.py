@@ -36,7 +36,7 @@ ABI_SYMBOLS = [
     "ndft_adjoint", "nfft_grad_x", "nfft_step_grid", "nfft_step_interp", "nfft_step_spread",
     "nfft_step_coeffs", "nfft_profile_enable", "nfft_profile_read", "nfft_batch_create",
     "nfft_batch_get_info", "nfft_batch_workspace_bytes", "nfft_batch_set_workspace",
-    "nfft_batch_autotune", "nfft_batch_get_params", "nfft_batch_set_params", "nfft_batch_trafo", "nfft_batch_adjoint", "nfft_batch_destroy", "nfft_status_string",
+    "nfft_batch_autotune", "nfft_batch_get_params", "nfft_batch_set_params", "nfft_batch_trafo", "nfft_batch_trafo_noalloc", "nfft_batch_adjoint", "nfft_batch_destroy", "nfft_status_string",
     "nnfft_plan_create", "nnfft_plan_destroy", "nnfft_plan_get_info", "nnfft_workspace_bytes",
     "nnfft_set_workspace", "nnfft_set_nodes", "nnfft_trafo", "nnfft_adjoint",
 ]
@@ -65,6 +65,8 @@ class PlanInfo(ctypes.Structure):
         ("lds_bytes", ctypes.c_size_t),
         ("grid_scale", ctypes.c_double),
         ("window", ctypes.c_int),
+        ("own_tiles", ctypes.c_int),
+        ("own_tile", ctypes.c_int64 * 3),
     ]
 
 
@@ -141,6 +143,7 @@ def load():
         "nfft_batch_set_workspace": [P, P, ctypes.c_size_t],
         "nfft_batch_autotune": [P, P],
         "nfft_batch_trafo": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
+        "nfft_batch_trafo_noalloc": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
         "nfft_batch_adjoint": [P, ctypes.POINTER(P), ctypes.POINTER(P), P],
         "nfft_batch_destroy": [P],
         "nnfft_plan_create": [ctypes.POINTER(P), I, ctypes.POINTER(I64), I64, I64, ctypes.c_double, I, I,

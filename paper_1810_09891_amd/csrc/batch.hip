@@ -18,6 +18,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -50,6 +51,7 @@ struct Group {
     int64_t items_fwd[kMaxDim] = {0, 0, 0}, items_adj[kMaxDim] = {0, 0, 0};
     size_t lds_interp = 0, lds_spread = 0;
     bool cols = false;  // every plan's 2-D spreading runs in registers
+    bool own = false;   // every plan's 3-D spreading runs by output tiles (one launch per plan)
     int64_t chunk_bound = 0, fold_items = 0;
     std::vector<PlanDev> table;
 };
@@ -63,7 +65,9 @@ struct nfft_batch_s {
     std::string cache;
     size_t ws_bytes = 0;
     void *ws = nullptr;
+    void *run_ws = nullptr;  // device memory of the call in progress: ws, or the static scratch
     int cus = 0;
+    bool prepared = false;   // groups built for the current device (launch data, host tables)
     bool table_current = false;
     hipError_t last_hip_error = hipSuccess;
 };
@@ -168,12 +172,12 @@ int blocks_for(const nfft_batch_s *b, int k, int64_t items)
 
 const PlanDev *table_of(const nfft_batch_s *b, const Group &G)
 {
-    return reinterpret_cast<const PlanDev *>(static_cast<const char *>(b->ws) + G.off_table);
+    return reinterpret_cast<const PlanDev *>(static_cast<const char *>(b->run_ws) + G.off_table);
 }
 
 int *queue_of(const nfft_batch_s *b, const Group &G, int which)
 {
-    return reinterpret_cast<int *>(static_cast<char *>(b->ws) + G.off_queue) + 2 * which;
+    return reinterpret_cast<int *>(static_cast<char *>(b->run_ws) + G.off_queue) + 2 * which;
 }
 
 int run_fft(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, bool forward, hipStream_t s)
@@ -191,6 +195,16 @@ int run_fft(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, bool forward
 
 int run_interp(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream_t s)
 {
+    if (G.own && G.table[0].g.oint) {
+        // 3-D plans interpolate by output tiles: one launch per plan
+        for (size_t i = 0; i < G.idx.size(); ++i) {
+            const PlanDev &pd = G.table[i];
+            nfft_plan_s *p = b->plans[(size_t)G.idx[i]];
+            BCHECK(launch_interp_own(pd.g, pd.nd, G.dbl, pd.grid, ptrs.out[i],
+                                     static_cast<char *>(p->ws) + p->off_own_scratch, p->own_max_items, s));
+        }
+        return NFFT_OK;
+    }
     const int blocks = blocks_for(b, G.params[kKInterp], G.chunk_bound);
     BCHECK(launch_interp_batch(table_of(b, G), (int)G.idx.size(), ptrs, queue_of(b, G, 0), G.d, G.dbl, G.WM, blocks,
                                G.lds_interp, s));
@@ -199,6 +213,18 @@ int run_interp(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream
 
 int run_spread(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream_t s)
 {
+    if (G.own) {
+        // 3-D plans spread by output tiles: one launch per plan (each launch covers all the
+        // compute units), the partial tiles folded by run_fold
+        for (size_t i = 0; i < G.idx.size(); ++i) {
+            const PlanDev &pd = G.table[i];
+            nfft_plan_s *p = b->plans[(size_t)G.idx[i]];
+            char *ws = static_cast<char *>(p->ws);
+            BCHECK(launch_spread_own(pd.g, pd.nd, G.dbl, ptrs.in[i], ws + p->off_own_fs, pd.grid_adj,
+                                     ws + p->off_own_scratch, p->own_max_items, s));
+        }
+        return NFFT_OK;
+    }
     const int blocks = blocks_for(b, G.params[kKSpread], G.chunk_bound);
     if (G.cols)
         BCHECK(launch_spread_cols_batch(table_of(b, G), (int)G.idx.size(), ptrs, queue_of(b, G, 1), G.dbl, G.WM,
@@ -211,6 +237,15 @@ int run_spread(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream
 
 int run_fold(nfft_batch_s *b, const Group &G, hipStream_t s)
 {
+    if (G.own) {
+        for (size_t i = 0; i < G.idx.size(); ++i) {
+            const PlanDev &pd = G.table[i];
+            nfft_plan_s *p = b->plans[(size_t)G.idx[i]];
+            BCHECK(launch_own_fold(pd.g, pd.nd, G.dbl, static_cast<char *>(p->ws) + p->off_own_scratch,
+                                   pd.grid_adj, s));
+        }
+        return NFFT_OK;
+    }
     const int blocks = blocks_for(b, G.params[kKFold], G.fold_items);
     BCHECK(launch_fold_batch(table_of(b, G), (int)G.idx.size(), G.d, G.dbl, blocks, s));
     return NFFT_OK;
@@ -286,6 +321,40 @@ std::map<std::string, std::vector<int>> read_cache(const std::string &path)
     return out;
 }
 
+bool valid_params(const int *v);
+
+// Launch data and host descriptor tables of every group for the current device, with the
+// tuned parameters of the cache file when it has them.  Host work only (no allocation).
+int prepare_groups(nfft_batch_s *b)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) {
+        b->last_hip_error = e;
+        return NFFT_ERR_HIP;
+    }
+    b->cus = prop.multiProcessorCount;
+    std::map<std::string, std::vector<int>> cached;
+    if (!b->cache.empty())
+        cached = read_cache(b->cache);
+    for (auto &G : b->groups) {
+        G.key = group_key(b, G, prop.gcnArchName);
+        auto it = cached.find(G.key);
+        if (it != cached.end() && valid_params(it->second.data())) {
+            for (int q = 0; q < NFFT_BATCH_NPARAMS; ++q)
+                G.params[q] = it->second[(size_t)q];
+            G.tuned = true;
+        }
+        build_group(b, G);
+    }
+    b->prepared = true;
+    return NFFT_OK;
+}
+
+
 bool write_cache(const std::string &path, const std::map<std::string, std::vector<int>> &entries)
 {
     const std::string tmp = path + ".tmp";
@@ -321,6 +390,45 @@ bool valid_params(const int *v)
 
 // ------------------------------------------------------------------ exported ABI
 
+// ------------------------------------------------------------------ allocation-free batch calls
+//
+// nfft_batch_trafo_noalloc runs the batched forward transform with the batch's descriptor
+// tables and work queues in this file-scope device array instead of a caller-provided batch
+// workspace.  Each device holds its own copy; its address is looked up once per device (with
+// that device current) and kept, and only that address is handed to copies and kernels.
+// Calls that overlap on one device share the array and therefore race.
+constexpr size_t kNoallocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const char *tune_cache)
@@ -347,9 +455,9 @@ int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const 
     if (tune_cache)
         b->cache = tune_cache;
     // group by kernel template parameters, largest M first, at most kMaxBatch per launch
-    std::map<std::tuple<int, int, int>, std::vector<int>> by_kind;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by_kind;
     for (int i = 0; i < count; ++i)
-        by_kind[std::make_tuple(plans[i]->d, plans[i]->WM, plans[i]->dbl ? 1 : 0)].push_back(i);
+        by_kind[std::make_tuple(plans[i]->d, plans[i]->WM, plans[i]->dbl ? 1 : 0, plans[i]->geom.own)].push_back(i);
     for (auto &kv : by_kind) {
         std::vector<int> v = kv.second;
         std::stable_sort(v.begin(), v.end(), [&](int a, int c) { return plans[a]->M > plans[c]->M; });
@@ -358,6 +466,7 @@ int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const 
             G.d = std::get<0>(kv.first);
             G.WM = std::get<1>(kv.first);
             G.dbl = std::get<2>(kv.first) != 0;
+            G.own = std::get<3>(kv.first) != 0;
             G.idx.assign(v.begin() + (long)s0, v.begin() + (long)std::min(v.size(), s0 + kMaxBatch));
             b->groups.push_back(G);
         }
@@ -432,35 +541,18 @@ int nfft_batch_set_workspace(nfft_batch b, void *ws, size_t bytes)
     if (!ws || bytes < b->ws_bytes || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
         return NFFT_ERR_WORKSPACE;
     b->ws = ws;
+    b->run_ws = ws;
     b->table_current = false;
-    int dev = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-        e = hipGetDeviceProperties(&prop, dev);
-    if (e != hipSuccess) {
-        b->last_hip_error = e;
-        return NFFT_ERR_HIP;
-    }
-    b->cus = prop.multiProcessorCount;
-    std::map<std::string, std::vector<int>> cached;
-    if (!b->cache.empty())
-        cached = read_cache(b->cache);
+    int st = prepare_groups(b);
+    if (st != NFFT_OK)
+        return st;
     for (auto &G : b->groups) {
-        G.key = group_key(b, G, prop.gcnArchName);
-        auto it = cached.find(G.key);
-        if (it != cached.end() && valid_params(it->second.data())) {
-            for (int q = 0; q < NFFT_BATCH_NPARAMS; ++q)
-                G.params[q] = it->second[(size_t)q];
-            G.tuned = true;
-        }
-        build_group(b, G);
-        int st = upload_group(b, G);
+        st = upload_group(b, G);
         if (st != NFFT_OK)
             return st;
     }
     // work queues start at zero and reset themselves after every launch
-    e = hipMemset(ws, 0, 16 * b->groups.size());
+    hipError_t e = hipMemset(ws, 0, 16 * b->groups.size());
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -483,6 +575,57 @@ int nfft_batch_trafo(nfft_batch b, const void *const *fhat, void *const *f, hipS
         if ((st = run_interp(b, G, ptrs, s)) != NFFT_OK)
             return st;
     }
+    for (auto *p : b->plans)
+        p->grid_valid = true;
+    return NFFT_OK;
+}
+
+int nfft_batch_trafo_noalloc(nfft_batch b, const void *const *fhat, void *const *f, hipStream_t s)
+{
+    if (!b || !fhat || !f)
+        return NFFT_ERR_ARG;
+    if (b->ws_bytes > kNoallocScratchBytes)
+        return NFFT_ERR_WORKSPACE;  // descriptor tables larger than the static scratch
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        if (!fhat[i] || !f[i])
+            return NFFT_ERR_ARG;
+        if (b->plans[i]->ws != b->plan_ws[i] || !b->plans[i]->nodes_set)
+            return NFFT_ERR_STATE;
+    }
+    int st;
+    if (!b->prepared && (st = prepare_groups(b)) != NFFT_OK)
+        return st;
+    void *base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) {
+        b->last_hip_error = e;
+        return NFFT_ERR_HIP;
+    }
+    char *sc = static_cast<char *>(base);
+    // descriptor tables into the scratch, work queues cleared (by a kernel, not a memset)
+    for (auto &G : b->groups) {
+        e = hipMemcpyAsync(sc + G.off_table, G.table.data(), sizeof(PlanDev) * G.table.size(),
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            b->last_hip_error = e;
+            return NFFT_ERR_HIP;
+        }
+    }
+    e = launch_fill_zero(sc, 16 * b->groups.size(), s);
+    if (e != hipSuccess) {
+        b->last_hip_error = e;
+        return NFFT_ERR_HIP;
+    }
+    void *saved = b->run_ws;
+    b->run_ws = base;
+    for (auto &G : b->groups) {
+        const BatchPtrs ptrs = make_ptrs(G, fhat, f);
+        if ((st = run_fft(b, G, ptrs, true, s)) != NFFT_OK || (st = run_interp(b, G, ptrs, s)) != NFFT_OK) {
+            b->run_ws = saved;
+            return st;
+        }
+    }
+    b->run_ws = saved;
     for (auto *p : b->plans)
         p->grid_valid = true;
     return NFFT_OK;

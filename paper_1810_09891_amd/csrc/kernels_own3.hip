@@ -1,0 +1,756 @@
+// The window steps of 3-D plans by output tiles: spreading (Algorithm 2.2 step 1) writes
+// every grid cell once, from the workgroup that owns it, as the sum over all nodes whose
+// stencils reach it (the blockwise adjoint of Table 3.2, turned around so that no two
+// workgroups write one cell and no floating-point atomics are needed); interpolation
+// (Algorithm 2.1 step 3) reads every grid cell once per work item.
+//
+// The grid is cut into tiles of 16 x 16 x 16 cells.  A workgroup of four waves holds one
+// tile in registers: wave w owns the 8 x 8 block of (dimension 1, dimension 2) columns at
+// (8 (w >> 1), 8 (w & 1)), a lane one column, and the 16 cells of its column along
+// dimension 0 are its registers.  A node whose stencil starts at tile-relative cell
+// (o0, o1, o2) meets row r of column (c1, c2) with the weight
+//     psi_0[r - o0] * (psi_1[c1 - o1] psi_2[c2 - o2]):
+// the lane forms the product of its two column factors once per node, and the row factors
+// -- the same for every lane -- enter the multiply-adds, one per real part per row.
+//
+// The node precomputation lists, for every tile, the nodes whose stencils reach it, each
+// entry with its tile offsets and the mask of the waves' blocks it reaches (the bins around
+// the tile in bin order, nodes that reach it only).  A work item is a slice of at most `cap`
+// entries of one tile; it stages its entries in batches (window factors into LDS), and each
+// wave takes the batch's entries row offset by row offset (one ballot per offset), so that
+// every register index is a constant of an unrolled sequence.
+//
+// Spreading: a tile with one item writes the grid directly; the items of a split tile (a
+// dense region) write partial tiles to their own slots and a second kernel adds the slots
+// in item order.  In complex64 a cell's contributions are summed in two levels -- at most one
+// batch into a batch accumulator, whose value is then added to the running total -- so that
+// the FP32 rounding error of a cell that many nodes reach grows with the number of batches
+// rather than of nodes.  Interpolation: each lane's partial sums of a wave's entries are
+// added over the wave through LDS, eight entries at a time; the block sums of a node are
+// added in block order, the result goes to the node's slot for the tile, and a last kernel
+// adds each node's slots in a fixed order.  Every sum therefore has a fixed order.
+#include <utility>
+
+#include "window_common.hpp"
+
+namespace nfft {
+
+namespace {
+
+constexpr int kOwnNB = 64;  // entries staged per batch
+constexpr int kOwnWaves = kBlock / 64;
+constexpr int kOwnRed = 8;  // interpolation entries reduced over a wave at a time
+
+__device__ __forceinline__ void own_tile_coords(const Geom &g, int tile, int *ti)
+{
+    int r = tile;
+#pragma unroll
+    for (int t = 2; t >= 0; --t) {
+        ti[t] = r % g.ont[t];
+        r /= g.ont[t];
+    }
+}
+
+// First neighbour bin of tile index i along dimension t, wrapped into [0, nb).
+__device__ __forceinline__ int own_first_bin(const Geom &g, int t, int i)
+{
+    if (g.oall[t])
+        return 0;
+    const int b = i * (g.oT[t] >> g.lgB[t]) + g.okb[t];
+    return b < 0 ? b + g.nb[t] : b;
+}
+
+// Range r of the bins around the tile at coordinates ti: bin row (a0, a1) of the
+// neighbourhood, part 0 or 1 of its dimension-2 bins (two parts when they wrap around).
+// Returns the first sorted node and the count (possibly 0).
+__device__ __forceinline__ void own_range(const Geom &g, const int32_t *__restrict__ bin_start, const int *ti, int r,
+                                          int &start, int &len)
+{
+    const int part = r & 1;
+    const int a = r >> 1;
+    const int a1 = a % g.okn[1];
+    const int a0 = a / g.okn[1];
+    int b0 = own_first_bin(g, 0, ti[0]) + a0;
+    if (b0 >= g.nb[0])
+        b0 -= g.nb[0];
+    int b1 = own_first_bin(g, 1, ti[1]) + a1;
+    if (b1 >= g.nb[1])
+        b1 -= g.nb[1];
+    const int f2 = own_first_bin(g, 2, ti[2]);
+    const int lo = part == 0 ? f2 : 0;
+    const int hi = part == 0 ? min(f2 + g.okn[2], g.nb[2]) : max(0, f2 + g.okn[2] - g.nb[2]);
+    start = 0;
+    len = 0;
+    if (hi > lo) {
+        const int row = (b0 * g.nb[1] + b1) * g.nb[2];
+        start = bin_start[row + lo];
+        len = bin_start[row + hi] - start;
+    }
+}
+
+// Packed entry of sorted node p for the tile with origin org: offsets o_t + 64 in bits
+// 0-7, 8-15, 16-23 and the mask of the blocks the stencil reaches in bits 24-27; 0 when it
+// reaches none.  Of the periodic images of the stencil only one can reach the tile
+// (n_t >= tile edge + W - 1 is required).
+__device__ __forceinline__ int own_meta(const Geom &g, const Nodes &nd, int p, const int *org)
+{
+    const int TT[3] = {kOwnTile0, kOwnTile12, kOwnTile12};
+    int o[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        int v = (nd.u[t][p] - g.m - org[t]) & (g.n[t] - 1);
+        if (v >= TT[t])
+            v -= g.n[t];
+        o[t] = v;
+    }
+    int mask = 0;
+    if (o[0] < kOwnTile0 && o[0] + g.W > 0) {
+#pragma unroll
+        for (int w = 0; w < kOwnWaves; ++w) {
+            const int b1 = (w >> 1) * 8, b2 = (w & 1) * 8;
+            if (o[1] < b1 + 8 && o[1] + g.W > b1 && o[2] < b2 + 8 && o[2] + g.W > b2)
+                mask |= 1 << w;
+        }
+    }
+    // a node that reaches a block has -W < o[t] < 16, so o + 64 fits in 8 bits
+    return mask ? (o[0] + 64) | ((o[1] + 64) << 8) | ((o[2] + 64) << 16) | (mask << 24) : 0;
+}
+
+// ------------------------------------------------------------------ node precomputation
+
+// One workgroup per tile: walk the bins around it (in range order) and keep the nodes that
+// reach it.  FILL = false counts them (tile_count); FILL = true writes the entries (sorted
+// position, packed offsets) from tile_entry[tile] on, in walk order.
+template <bool FILL> __global__ __launch_bounds__(kBlock) void k_own_entries(Geom g, Nodes nd)
+{
+    __shared__ int s_rstart[kOwnMaxRanges];
+    __shared__ int s_rcum[kOwnMaxRanges + 1];
+    __shared__ int s_wcnt[kOwnWaves];
+    const int tile = blockIdx.x;
+    int ti[3];
+    own_tile_coords(g, tile, ti);
+    const int org[3] = {ti[0] * kOwnTile0, ti[1] * kOwnTile12, ti[2] * kOwnTile12};
+    const int nR = g.okn[0] * g.okn[1] * 2;
+    for (int r = threadIdx.x; r < nR; r += kBlock) {
+        int st, ln;
+        own_range(g, nd.bin_start, ti, r, st, ln);
+        s_rstart[r] = st;
+        s_rcum[r + 1] = ln;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_rcum[0] = 0;
+        for (int r = 0; r < nR; ++r)
+            s_rcum[r + 1] += s_rcum[r];
+    }
+    __syncthreads();
+    const int total = s_rcum[nR];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int out = FILL ? nd.tile_entry[tile] : 0;
+    int kept = 0;
+    for (int base = 0; base < total; base += kBlock) {
+        const int e = base + threadIdx.x;
+        int p = 0, meta = 0;
+        if (e < total) {
+            int a = 0, b = nR - 1;  // the last range r with s_rcum[r] <= e
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (s_rcum[mid] <= e)
+                    a = mid;
+                else
+                    b = mid - 1;
+            }
+            p = s_rstart[a] + (e - s_rcum[a]);
+            meta = own_meta(g, nd, p, org);
+        }
+        const uint64_t keep = __ballot(meta != 0);
+        if (lane == 0)
+            s_wcnt[wave] = __popcll(keep);
+        __syncthreads();
+        int before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < kOwnWaves; ++w) {
+            before += w < wave ? s_wcnt[w] : 0;
+            all += s_wcnt[w];
+        }
+        if (FILL && meta != 0) {
+            const int rank = before + __popcll(keep & ((1ull << lane) - 1ull));
+            reinterpret_cast<int2 *>(nd.entries)[out + rank] = int2{p, meta};
+        }
+        out += all;
+        kept += all;
+        __syncthreads();
+    }
+    if (!FILL && threadIdx.x == 0)
+        nd.tile_count[tile] = kept;
+}
+
+// One workgroup of 1024 threads: exclusive scans of the entries per tile (tile_entry) and
+// of the items per tile, max(1, ceil(count / cap)) (tile_item; every tile has an item, so
+// every cell is written); counters[2] = number of items.
+constexpr int kOwnScan = 1024;
+__global__ __launch_bounds__(kOwnScan) void k_own_scan(Geom g, Nodes nd)
+{
+    __shared__ int s_a[kOwnScan];
+    __shared__ int s_b[kOwnScan];
+    const int tid = threadIdx.x;
+    const int n = g.ontiles;
+    const int per = (n + kOwnScan - 1) / kOwnScan;
+    const int lo = tid * per;
+    const int hi = min(n, lo + per);
+    auto items = [&](int t) { return max(1, (nd.tile_count[t] + g.ocap - 1) / g.ocap); };
+    int sa = 0, sb = 0;
+    for (int i = lo; i < hi; ++i) {
+        sa += items(i);
+        sb += nd.tile_count[i];
+    }
+    s_a[tid] = sa;
+    s_b[tid] = sb;
+    __syncthreads();
+    for (int off = 1; off < kOwnScan; off <<= 1) {
+        const int va = tid >= off ? s_a[tid - off] : 0;
+        const int vb = tid >= off ? s_b[tid - off] : 0;
+        __syncthreads();
+        s_a[tid] += va;
+        s_b[tid] += vb;
+        __syncthreads();
+    }
+    int ra = s_a[tid] - sa, rb = s_b[tid] - sb;
+    for (int i = lo; i < hi; ++i) {
+        nd.tile_item[i] = ra;
+        nd.tile_entry[i] = rb;
+        ra += items(i);
+        rb += nd.tile_count[i];
+    }
+    if (tid == kOwnScan - 1) {
+        nd.tile_item[n] = s_a[tid];
+        nd.tile_entry[n] = s_b[tid];
+        nd.counters[2] = s_a[tid];
+    }
+}
+
+// The items of every tile: equal slices of its entry list.
+__global__ __launch_bounds__(kBlock) void k_own_items(Geom g, Nodes nd)
+{
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= g.ontiles)
+        return;
+    const int first = nd.tile_item[tile];
+    const int k = nd.tile_item[tile + 1] - first;
+    const int64_t count = nd.tile_count[tile];
+    for (int i = 0; i < k; ++i) {
+        nd.item_tile[first + i] = tile;
+        nd.item_lo[first + i] = (int)(count * i / k);
+        nd.item_hi[first + i] = (int)(count * (i + 1) / k);
+    }
+}
+
+// ------------------------------------------------------------------ staging and walk
+
+// LDS record of one staged entry's factors: dimension 0 at the start (16-byte aligned),
+// dimensions 1 and 2 each with 8 zeros on both sides, so that a lane whose column lies up to
+// 8 cells outside the stencil reads a zero instead of branching.
+template <typename T, int W> struct OwnRec {
+    static constexpr int V = 16 / (int)sizeof(T);
+    static constexpr int W0 = (W + V - 1) / V * V;
+    static constexpr int L = W + 16;
+    static constexpr int D1 = W0;
+    static constexpr int D2 = W0 + L;
+    static constexpr int REC = (D2 + L + V - 1) / V * V;
+    static constexpr int NL = (kOwnNB * 3 * W + kBlock - 1) / kBlock;  // factor loads per thread
+};
+
+template <typename T, int W> struct OwnLds {
+    T psi[kOwnNB * OwnRec<T, W>::REC];
+    Cplx<T> val[kOwnNB * kOwnWaves];  // spreading: node values; interpolation: block sums
+    int meta[kOwnNB];
+    int pos[kOwnNB];
+};
+
+// Stage entries q .. q + nb - 1 of the tile's list (ent): packed offsets, sorted positions,
+// window factors, and with `fs` (node values in sorted order) the values.  Every load is
+// issued before the first LDS store; ends with a barrier.
+template <typename T, int W>
+__device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, const int2 *__restrict__ ent, int q,
+                                          int nb, const Cplx<T> *__restrict__ fs)
+{
+    using R = OwnRec<T, W>;
+    const T *__restrict__ psi = static_cast<const T *>(nd.psi);
+    int2 e{0, 0};
+    Cplx<T> fv{T(0), T(0)};
+    if ((int)threadIdx.x < nb) {
+        e = ent[q + threadIdx.x];
+        if (fs)
+            fv = fs[e.x];
+    }
+    T v[R::NL];
+    int dst[R::NL];
+#pragma unroll
+    for (int j = 0; j < R::NL; ++j) {
+        const int idx = threadIdx.x + j * kBlock;
+        const int k = idx / (3 * W);
+        const int rr = idx - k * (3 * W);
+        const bool ok = k < nb;
+        const int p = ent[q + (ok ? k : 0)].x;
+        v[j] = psi[(int64_t)p * (3 * W) + (ok ? rr : 0)];
+        const int t = rr / W;
+        const int s = rr - t * W;
+        dst[j] = ok ? k * R::REC + (t == 0 ? s : (t == 1 ? R::D1 + 8 + s : R::D2 + 8 + s)) : -1;
+    }
+    if ((int)threadIdx.x < nb) {
+        L.meta[threadIdx.x] = e.y;
+        L.pos[threadIdx.x] = e.x;
+        if (fs)
+            L.val[threadIdx.x] = fv;
+    }
+#pragma unroll
+    for (int j = 0; j < R::NL; ++j)
+        if (dst[j] >= 0)
+            L.psi[dst[j]] = v[j];
+    __syncthreads();
+}
+
+// The batch walk of one wave: lane k holds the packed entry k of the batch (0 past the
+// batch).  For every row offset O (a template constant) one ballot selects the entries
+// with that offset whose stencil reaches the wave's block, and `body.run<O>(k, o1, o2)`
+// handles them in batch order.
+template <int O, typename Body>
+__device__ __forceinline__ void own_walk_row(int emeta, int wave, Body &body)
+{
+    const bool mine = emeta != 0 && (emeta & 255) - 64 == O && ((emeta >> (24 + wave)) & 1);
+    uint64_t bits = __ballot(mine);
+    while (bits) {
+        const int k = __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int meta = __builtin_amdgcn_readlane(emeta, k);
+        body.template run<O>(k, ((meta >> 8) & 255) - 64, ((meta >> 16) & 255) - 64);
+    }
+}
+
+template <int LO, typename Body, int... Is>
+__device__ __forceinline__ void own_walk(std::integer_sequence<int, Is...>, int emeta, int wave, Body &body)
+{
+    (own_walk_row<LO + Is>(emeta, wave, body), ...);
+}
+
+// ------------------------------------------------------------------ spreading
+
+// Spreading of one entry into the wave's block: acc[O + s] += psi_0[s] (f_j psi_1 psi_2).
+template <typename T, int T0, int W> struct SpreadBody {
+    const T *psi;
+    const Cplx<T> *val;
+    int c1, c2;
+    T (&ax)[T0];
+    T (&ay)[T0];
+    template <int O> __device__ __forceinline__ void run(int k, int o1, int o2)
+    {
+        using R = OwnRec<T, W>;
+        const T *rec = psi + k * R::REC;
+        const T w12 = rec[R::D1 + 8 + c1 - o1] * rec[R::D2 + 8 + c2 - o2];
+        const Cplx<T> fv = val[k];
+        const T wx = fv.x * w12;
+        const T wy = fv.y * w12;
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            if (O + s >= 0 && O + s < T0) {
+                ax[O + s] = fma(rec[s], wx, ax[O + s]);
+                ay[O + s] = fma(rec[s], wy, ay[O + s]);
+            }
+        }
+    }
+};
+
+// Node values in sorted order (read once per entry by the spreading kernel).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_own_gather(Nodes nd, const Cplx<T> *__restrict__ f, Cplx<T> *__restrict__ fs)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nd.M)
+        fs[p] = f[nd.perm[p]];
+}
+
+// Waves per SIMD the window kernels by tiles aim at (register budget 512 / waves).
+template <typename T, int W> constexpr int own_waves() { return sizeof(T) == 4 && W <= 14 ? 3 : 2; }
+
+template <typename T, int T0, int W>
+__global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_spread_own(Geom g, Nodes nd, const Cplx<T> *__restrict__ fs,
+                                                        Cplx<T> *__restrict__ grid, Cplx<T> *__restrict__ scratch)
+{
+    using C = Cplx<T>;
+    using R = OwnRec<T, W>;
+    constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
+    constexpr int TC = T0 * T1 * T2;
+    __shared__ __align__(16) OwnLds<T, W> L;
+
+    const int nitems = nd.counters[2];
+    const int nwg = min((int)gridDim.x, nitems);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c1 = (wave >> 1) * 8 + (lane >> 3);
+    const int c2 = (wave & 1) * 8 + (lane & 7);
+    const int2 *__restrict__ entries = reinterpret_cast<const int2 *>(nd.entries);
+
+    for (int i = threadIdx.x; i < kOwnNB * R::REC; i += kBlock)
+        L.psi[i] = T(0);
+
+    for (int it = xcd_local_id(blockIdx.x, nwg); it < nitems; it += nwg) {
+        const int tile = nd.item_tile[it];
+        const int lo = nd.item_lo[it], hi = nd.item_hi[it];
+        const int2 *ent = entries + nd.tile_entry[tile];
+        int ti[3];
+        own_tile_coords(g, tile, ti);
+        constexpr bool kTwoLevel = sizeof(T) == 4;
+        T ax[T0], ay[T0];
+        T tx[kTwoLevel ? T0 : 1], ty[kTwoLevel ? T0 : 1];
+#pragma unroll
+        for (int r = 0; r < T0; ++r) {
+            ax[r] = T(0);
+            ay[r] = T(0);
+            if constexpr (kTwoLevel) {
+                tx[r] = T(0);
+                ty[r] = T(0);
+            }
+        }
+        for (int q = lo; q < hi; q += kOwnNB) {
+            const int nb = min(kOwnNB, hi - q);
+            __syncthreads();  // the previous batch is consumed
+            own_stage<T, W>(nd, L, ent, q, nb, fs);
+            const int emeta = lane < nb ? L.meta[lane] : 0;
+            SpreadBody<T, T0, W> body{L.psi, L.val, c1, c2, ax, ay};
+            own_walk<-(W - 1)>(std::make_integer_sequence<int, W - 1 + T0>{}, emeta, wave, body);
+            if constexpr (kTwoLevel) {
+#pragma unroll
+                for (int r = 0; r < T0; ++r) {
+                    tx[r] += ax[r];
+                    ty[r] += ay[r];
+                    ax[r] = T(0);
+                    ay[r] = T(0);
+                }
+            }
+        }
+        if constexpr (kTwoLevel) {
+#pragma unroll
+            for (int r = 0; r < T0; ++r) {
+                ax[r] = tx[r];
+                ay[r] = ty[r];
+            }
+        }
+        const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
+        const int nsplit = nd.tile_item[tile + 1] - nd.tile_item[tile];
+        if (nsplit == 1) {
+            const int64_t base = ((int64_t)org0 * g.n[1] + org1 + c1) * g.n[2] + org2 + c2;
+            const int64_t row = (int64_t)g.n[1] * g.n[2];
+#pragma unroll
+            for (int r = 0; r < T0; ++r)
+                grid[base + r * row] = C{ax[r], ay[r]};
+        } else {
+            C *slot = scratch + (int64_t)it * TC;
+#pragma unroll
+            for (int r = 0; r < T0; ++r)
+                slot[(r * T1 + c1) * T2 + c2] = C{ax[r], ay[r]};
+        }
+    }
+}
+
+// Split tiles: the sum of their items' partial tiles, in item order.
+template <typename T, int T0>
+__global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cplx<T> *__restrict__ scratch,
+                                                      Cplx<T> *__restrict__ grid)
+{
+    using C = Cplx<T>;
+    constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
+    constexpr int TC = T0 * T1 * T2;
+    const int tile = blockIdx.x;
+    const int first = nd.tile_item[tile];
+    const int k = nd.tile_item[tile + 1] - first;
+    if (k <= 1)
+        return;
+    int ti[3];
+    own_tile_coords(g, tile, ti);
+    const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
+    for (int c = threadIdx.x; c < TC; c += kBlock) {
+        const int r = c / (T1 * T2);
+        const int cc1 = (c / T2) % T1;
+        const int cc2 = c % T2;
+        const C *src = scratch + (int64_t)first * TC + c;
+        C acc = src[0];
+        for (int i = 1; i < k; ++i) {
+            const C v = src[(int64_t)i * TC];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        grid[((int64_t)(org0 + r) * g.n[1] + org1 + cc1) * g.n[2] + org2 + cc2] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ interpolation
+
+// Interpolation of one entry over the wave's block: the lane's partial
+// psi_1 psi_2 sum_s g[O + s] psi_0[s] goes to slot j of the wave's reduction buffer; every
+// kOwnRed entries (and at the end of the batch) the slots are added over the lanes.
+template <typename T, int T0, int W> struct InterpBody {
+    const T *psi;
+    Cplx<T> *red;   // [kOwnRed][64] of this wave
+    Cplx<T> *val;   // block sums [kOwnNB][kOwnWaves]
+    int *slotk;     // entry of each slot, [kOwnRed] of this wave
+    int c1, c2, lane, wave;
+    int j;          // slots in use
+    const T (&gx)[T0];
+    const T (&gy)[T0];
+
+    // Sum slots 0 .. j-1 over the wave: lane l adds part (l % 8) of slot l / 8 (eight lanes'
+    // values in lane order), then the eight parts of a slot are added pairwise (xor 1, 2, 4).
+    __device__ __forceinline__ void flush()
+    {
+        const int sl = lane >> 3, part = lane & 7;
+        T sx = T(0), sy = T(0);
+        if (sl < j) {
+            const Cplx<T> *r = red + sl * 64 + part * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const Cplx<T> v = r[i];
+                sx += v.x;
+                sy += v.y;
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            sx += __shfl_xor(sx, off);
+            sy += __shfl_xor(sy, off);
+        }
+        if (part == 0 && sl < j)
+            val[slotk[sl] * kOwnWaves + wave] = Cplx<T>{sx, sy};
+        j = 0;
+    }
+
+    template <int O> __device__ __forceinline__ void run(int k, int o1, int o2)
+    {
+        using R = OwnRec<T, W>;
+        const T *rec = psi + k * R::REC;
+        const T w12 = rec[R::D1 + 8 + c1 - o1] * rec[R::D2 + 8 + c2 - o2];
+        T px = T(0), py = T(0);
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            if (O + s >= 0 && O + s < T0) {
+                px = fma(gx[O + s], rec[s], px);
+                py = fma(gy[O + s], rec[s], py);
+            }
+        }
+        red[j * 64 + lane] = Cplx<T>{px * w12, py * w12};
+        if (lane == 0)
+            slotk[j] = k;
+        if (++j == kOwnRed)
+            flush();
+    }
+};
+
+// Slot of a node's partial sum for the tile at ti: per dimension, 0 for the tile holding the
+// stencil's first cell, 1 for the next one.
+__device__ __forceinline__ int own_slot(const Geom &g, const Nodes &nd, int p, const int *ti)
+{
+    int slot = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int a = (nd.u[t][p] - g.m) & (g.n[t] - 1);
+        int s = ti[t] - a / g.oT[t];
+        if (s < 0)
+            s += g.ont[t];
+        slot = slot * 2 + s;
+    }
+    return slot;
+}
+
+template <typename T, int T0, int W>
+__global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_interp_own(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
+                                                        Cplx<T> *__restrict__ part)
+{
+    using C = Cplx<T>;
+    using R = OwnRec<T, W>;
+    constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
+    __shared__ __align__(16) OwnLds<T, W> L;
+    __shared__ __align__(16) C s_red[kOwnWaves][kOwnRed * 64];
+    __shared__ int s_slotk[kOwnWaves][kOwnRed];
+
+    const int nitems = nd.counters[2];
+    const int nwg = min((int)gridDim.x, nitems);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c1 = (wave >> 1) * 8 + (lane >> 3);
+    const int c2 = (wave & 1) * 8 + (lane & 7);
+    const int64_t M = nd.M;
+    const int2 *__restrict__ entries = reinterpret_cast<const int2 *>(nd.entries);
+
+    for (int i = threadIdx.x; i < kOwnNB * R::REC; i += kBlock)
+        L.psi[i] = T(0);
+
+    for (int it = xcd_local_id(blockIdx.x, nwg); it < nitems; it += nwg) {
+        const int tile = nd.item_tile[it];
+        const int lo = nd.item_lo[it], hi = nd.item_hi[it];
+        if (lo >= hi)
+            continue;
+        const int2 *ent = entries + nd.tile_entry[tile];
+        int ti[3];
+        own_tile_coords(g, tile, ti);
+        const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
+        T gx[T0], gy[T0];
+        {
+            const int64_t base = ((int64_t)org0 * g.n[1] + org1 + c1) * g.n[2] + org2 + c2;
+            const int64_t row = (int64_t)g.n[1] * g.n[2];
+#pragma unroll
+            for (int r = 0; r < T0; ++r) {
+                const C v = grid[base + r * row];
+                gx[r] = v.x;
+                gy[r] = v.y;
+            }
+        }
+        for (int q = lo; q < hi; q += kOwnNB) {
+            const int nb = min(kOwnNB, hi - q);
+            __syncthreads();  // the previous batch's block sums are consumed
+            own_stage<T, W>(nd, L, ent, q, nb, nullptr);
+            const int emeta = lane < nb ? L.meta[lane] : 0;
+            InterpBody<T, T0, W> body{L.psi, s_red[wave], L.val, s_slotk[wave], c1, c2, lane, wave, 0, gx, gy};
+            own_walk<-(W - 1)>(std::make_integer_sequence<int, W - 1 + T0>{}, emeta, wave, body);
+            if (body.j > 0)
+                body.flush();
+            __syncthreads();
+            if ((int)threadIdx.x < nb) {
+                const int k = threadIdx.x;
+                const int meta = L.meta[k];
+                C v{T(0), T(0)};
+#pragma unroll
+                for (int w = 0; w < kOwnWaves; ++w) {
+                    if ((meta >> (24 + w)) & 1) {
+                        const C b = L.val[k * kOwnWaves + w];
+                        v.x += b.x;
+                        v.y += b.y;
+                    }
+                }
+                const int p = L.pos[k];
+                part[(int64_t)own_slot(g, nd, p, ti) * M + p] = v;
+            }
+        }
+    }
+}
+
+// f_j = sum of the node's tile slots, in slot order (slots of tiles its stencil does not
+// reach are neither written nor read).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_interp_own_sum(Geom g, Nodes nd, const Cplx<T> *__restrict__ part,
+                                                            Cplx<T> *__restrict__ f)
+{
+    using C = Cplx<T>;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nd.M)
+        return;
+    int cross[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int a = (nd.u[t][p] - g.m) & (g.n[t] - 1);
+        cross[t] = (a % g.oT[t]) + g.W > g.oT[t] ? 1 : 0;
+    }
+    C v{T(0), T(0)};
+    for (int s0 = 0; s0 <= cross[0]; ++s0)
+        for (int s1 = 0; s1 <= cross[1]; ++s1)
+            for (int s2 = 0; s2 <= cross[2]; ++s2) {
+                const C b = part[(int64_t)((s0 * 2 + s1) * 2 + s2) * nd.M + p];
+                v.x += b.x;
+                v.y += b.y;
+            }
+    f[nd.perm[p]] = v;
+}
+
+inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_own_items(const Geom &g, const Nodes &nd, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_own_entries<false>, dim3(g.ontiles), dim3(kBlock), 0, s, g, nd);
+    hipLaunchKernelGGL(k_own_scan, dim3(1), dim3(kOwnScan), 0, s, g, nd);
+    hipLaunchKernelGGL(k_own_entries<true>, dim3(g.ontiles), dim3(kBlock), 0, s, g, nd);
+    hipLaunchKernelGGL(k_own_items, dim3(blocks_for(g.ontiles)), dim3(kBlock), 0, s, g, nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const void *f, void *fs, void *grid,
+                             void *scratch, int max_items, hipStream_t s)
+{
+    if (g.d != 3 || !g.own || g.W != g.WM || g.oT[0] != kOwnTile0)
+        return hipErrorInvalidValue;
+    const int blocks = max_items > 0 ? max_items : 1;
+    if (dbl) {
+        using C = Cplx<double>;
+        hipLaunchKernelGGL(k_own_gather<double>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, nd,
+                           static_cast<const C *>(f), static_cast<C *>(fs));
+#define OWN_CASE(WMV)                                                                                       \
+    hipLaunchKernelGGL((k_spread_own<double, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,      \
+                       static_cast<const C *>(fs), static_cast<C *>(grid), static_cast<C *>(scratch))
+        NFFT_WM_SWITCH(g.WM, OWN_CASE)
+#undef OWN_CASE
+    } else {
+        using C = Cplx<float>;
+        hipLaunchKernelGGL(k_own_gather<float>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, nd,
+                           static_cast<const C *>(f), static_cast<C *>(fs));
+#define OWN_CASE(WMV)                                                                                       \
+    hipLaunchKernelGGL((k_spread_own<float, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,       \
+                       static_cast<const C *>(fs), static_cast<C *>(grid), static_cast<C *>(scratch))
+        NFFT_WM_SWITCH(g.WM, OWN_CASE)
+#undef OWN_CASE
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_interp_own(const Geom &g, const Nodes &nd, bool dbl, const void *grid, void *f, void *part,
+                             int max_items, hipStream_t s)
+{
+    if (g.d != 3 || !g.own || !g.oint || g.W != g.WM || g.oT[0] != kOwnTile0)
+        return hipErrorInvalidValue;
+    const int blocks = max_items > 0 ? max_items : 1;
+    if (dbl) {
+        using C = Cplx<double>;
+#define OWN_CASE(WMV)                                                                                       \
+    hipLaunchKernelGGL((k_interp_own<double, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,      \
+                       static_cast<const C *>(grid), static_cast<C *>(part))
+        switch (g.WM) {
+        case 6: OWN_CASE(6); break;
+        case 10: OWN_CASE(10); break;
+        case 14: OWN_CASE(14); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef OWN_CASE
+        hipLaunchKernelGGL(k_interp_own_sum<double>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, g, nd,
+                           static_cast<const C *>(part), static_cast<C *>(f));
+    } else {
+        using C = Cplx<float>;
+#define OWN_CASE(WMV)                                                                                       \
+    hipLaunchKernelGGL((k_interp_own<float, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,       \
+                       static_cast<const C *>(grid), static_cast<C *>(part))
+        switch (g.WM) {
+        case 6: OWN_CASE(6); break;
+        case 10: OWN_CASE(10); break;
+        case 14: OWN_CASE(14); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef OWN_CASE
+        hipLaunchKernelGGL(k_interp_own_sum<float>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, g, nd,
+                           static_cast<const C *>(part), static_cast<C *>(f));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_own_fold(const Geom &g, const Nodes &nd, bool dbl, const void *scratch, void *grid, hipStream_t s)
+{
+    if (dbl)
+        hipLaunchKernelGGL((k_own_fold<double, kOwnTile0>), dim3(g.ontiles), dim3(kBlock), 0, s, g, nd,
+                           static_cast<const Cplx<double> *>(scratch), static_cast<Cplx<double> *>(grid));
+    else
+        hipLaunchKernelGGL((k_own_fold<float, kOwnTile0>), dim3(g.ontiles), dim3(kBlock), 0, s, g, nd,
+                           static_cast<const Cplx<float> *>(scratch), static_cast<Cplx<float> *>(grid));
+    return hipGetLastError();
+}
+
+}  // namespace nfft

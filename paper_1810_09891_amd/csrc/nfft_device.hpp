@@ -273,6 +273,19 @@ struct Geom {
     double b[kMaxDim];    // window shape per dimension
     double emb[kMaxDim];  // 1 / (factor the device window is divided by): e^{-b m} (Kaiser-Bessel),
                           // (pi b)^{1/2} (Gaussian)
+    // Owner-computes spreading (3-D plans, own = 1): the grid is cut into output tiles of
+    // oT[0] x oT[1] x oT[2] cells; the node list of a tile is the concatenation of the bins
+    // okb[t] .. okb[t] + okn[t] - 1 (relative to the tile's first bin, periodic) per
+    // dimension, or of all bins of a dimension when oall[t].
+    int own;
+    int oT[kMaxDim];
+    int ont[kMaxDim];   // tiles per dimension
+    int ontiles;
+    int okb[kMaxDim];
+    int okn[kMaxDim];
+    int oall[kMaxDim];
+    int ocap;           // node-list entries per work item
+    int oint;           // interpolation by output tiles too (stencil of at most oT + 1 points)
 };
 
 // Window factor of dimension t at stencil point s of a node with offset delta, and its
@@ -325,6 +338,14 @@ struct Nodes {
     int32_t *spos;         // d = 2 spreading in registers, else null: per work item, its
                            // nodes in order of tile row as pairs ((offset << 10) | (row << 5)
                            // | column, caller index)
+    // owner-computes spreading (Geom::own), else null
+    int32_t *tile_count;   // [ontiles] entries (nodes whose stencils reach it) of every output tile
+    int32_t *tile_entry;   // [ontiles+1] first entry of every tile
+    void *entries;         // int2 (sorted position, packed tile offsets and block mask) per entry
+    int32_t *tile_item;    // [ontiles+1] first work item of every tile
+    int32_t *item_tile;    // [max items] tile of a work item
+    int32_t *item_lo;      // [max items] its slice [lo, hi) of the tile's node list
+    int32_t *item_hi;
     const double *x;       // caller node array (only used while setting nodes)
     int64_t M;
     int chunk_cap;

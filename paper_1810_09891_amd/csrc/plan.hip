@@ -109,6 +109,63 @@ static int choose_bins(nfft_plan_s *p)
     return NFFT_OK;
 }
 
+// Owner-computes spreading for 3-D plans (kernels_own3.hip): output tiles of 16 x 16 x 16
+// cells whose node lists are the bins around them.  Used when every node can reach a tile
+// through one periodic image only (n_t >= tile edge + 2m + 1), the stencil width is the
+// compiled one (even m) and a tile's list is at most kOwnMaxRanges runs of bins.
+static void setup_owner(nfft_plan_s *p)
+{
+    Geom &g = p->geom;
+    g.own = 0;
+    p->own_max_items = 0;
+    if (p->d != 3 || g.W != g.WM)
+        return;
+    const int T[3] = {kOwnTile0, kOwnTile12, kOwnTile12};
+    int okb[3], okn[3], oall[3];
+    int64_t tiles_per_bin = 1, ntiles = 1;
+    for (int t = 0; t < 3; ++t) {
+        const int B = 1 << g.lgB[t];
+        if (p->n[t] % T[t] != 0 || p->n[t] < T[t] + g.W - 1 || T[t] % B != 0)
+            return;
+        // bins holding nodes whose stencil (cells u - m .. u + m + 1) reaches the cells
+        // [i T, i T + T - 1] of a tile: from floor((i T - m - 1) / B) to floor((i T + T - 1 + m) / B)
+        okb[t] = -((g.m + 1 + B - 1) / B);
+        okn[t] = (T[t] - 1 + g.m) / B - okb[t] + 1;
+        const int tiles = (int)(p->n[t] / T[t]);
+        if (okn[t] >= g.nb[t]) {
+            oall[t] = 1;
+            okb[t] = 0;
+            okn[t] = g.nb[t];
+            tiles_per_bin *= tiles;
+        } else {
+            oall[t] = 0;
+            tiles_per_bin *= (okn[t] - 1) / (T[t] / B) + 1;
+        }
+        ntiles *= tiles;
+    }
+    if (okn[0] * okn[1] * 2 > kOwnMaxRanges || ntiles > (1 << 24))
+        return;
+    const int cap = 2048;
+    const int64_t list_max = p->M * tiles_per_bin;
+    const int64_t items = ntiles + (list_max + cap - 1) / cap + 1;
+    if (list_max >= ((int64_t)1 << 31) || items >= ((int64_t)1 << 31))
+        return;
+    for (int t = 0; t < 3; ++t) {
+        g.oT[t] = T[t];
+        g.ont[t] = (int)(p->n[t] / T[t]);
+        g.okb[t] = okb[t];
+        g.okn[t] = okn[t];
+        g.oall[t] = oall[t];
+    }
+    g.ontiles = (int)ntiles;
+    g.ocap = cap;
+    p->own_max_entries = list_max;
+    // interpolation by the same tiles: a stencil then spans at most two tiles per dimension
+    g.oint = g.W <= kOwnTile0 + 1 ? 1 : 0;
+    p->own_max_items = (int)items;
+    g.own = 1;
+}
+
 static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_last, FftPass &fp)
 {
     const int d = p->d;
@@ -331,7 +388,27 @@ static void layout_workspace(nfft_plan_s *p)
     // window factors, padded so that reads of WM (>= 2m+2) factors past the last node's
     // record stay inside the workspace
     p->off_psi = take(rs * ((size_t)M * p->d * (size_t)(2 * p->m + 2) + 64));
-    p->off_scratch = take(cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
+    // one padded tile per work item for the tile spreading kernels; owner-computes plans
+    // need tile lists, work items and one partial tile per item instead
+    p->off_scratch = take(p->geom.own ? 0 : cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
+    if (p->geom.own) {
+        const size_t items = (size_t)p->own_max_items;
+        const size_t tc = (size_t)p->geom.oT[0] * p->geom.oT[1] * p->geom.oT[2];
+        p->off_tile_count = take(4 * (size_t)p->geom.ontiles);
+        p->off_tile_entry = take(4 * ((size_t)p->geom.ontiles + 1));
+        p->off_entries = take(8 * (size_t)p->own_max_entries);
+        p->off_own_fs = take(cs * (size_t)M);
+        p->off_tile_item = take(4 * ((size_t)p->geom.ontiles + 1));
+        p->off_item_tile = take(4 * items);
+        p->off_item_lo = take(4 * items);
+        p->off_item_hi = take(4 * items);
+        // partial tiles of the spreading step and the interpolation's per-node tile slots
+        // are never live together: one region serves both
+        size_t own = cs * tc * items;
+        if (p->geom.oint)
+            own = std::max(own, cs * 8 * (size_t)M);
+        p->off_own_scratch = take(own);
+    }
     p->spos_used = spread_in_registers(p->geom, p->dbl);
     if (p->spos_used)
         p->off_spos = take(8 * (size_t)M);
@@ -411,6 +488,7 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
     while (p->chunk_cap < 1024 && (int64_t)p->chunk_cap * 2 * 512 <= M)
         p->chunk_cap *= 2;
     p->max_chunks = (int)(g.nbins + (M + p->chunk_cap - 1) / p->chunk_cap);
+    setup_owner(p);
     build_tables(p);
     // FFT passes
     p->fwd_passes.clear();
@@ -453,6 +531,15 @@ Nodes plan_node_view(nfft_plan_s *p)
     nd.counters = reinterpret_cast<int32_t *>(ws + p->off_counters);
     nd.psi = ws + p->off_psi;
     nd.spos = p->spos_used ? reinterpret_cast<int32_t *>(ws + p->off_spos) : nullptr;
+    if (p->geom.own) {
+        nd.tile_count = reinterpret_cast<int32_t *>(ws + p->off_tile_count);
+        nd.tile_entry = reinterpret_cast<int32_t *>(ws + p->off_tile_entry);
+        nd.entries = ws + p->off_entries;
+        nd.tile_item = reinterpret_cast<int32_t *>(ws + p->off_tile_item);
+        nd.item_tile = reinterpret_cast<int32_t *>(ws + p->off_item_tile);
+        nd.item_lo = reinterpret_cast<int32_t *>(ws + p->off_item_lo);
+        nd.item_hi = reinterpret_cast<int32_t *>(ws + p->off_item_hi);
+    }
     nd.M = p->M;
     nd.chunk_cap = p->chunk_cap;
     nd.max_chunks = p->max_chunks;
@@ -553,6 +640,12 @@ static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_
 static int run_interp(nfft_plan_s *p, const void *grid, void *f, hipStream_t s)
 {
     Nodes nd = plan_node_view(p);
+    if (p->geom.oint) {
+        void *part = static_cast<char *>(p->ws) + p->off_own_scratch;
+        LAUNCH(p, s, "interp_own",
+               launch_interp_own(p->geom, nd, p->dbl, grid, f, part, p->own_max_items, s));
+        return NFFT_OK;
+    }
     LAUNCH(p, s, "interp",
            launch_interp(p->geom, nd, p->dbl, grid, f, grid_blocks(p), interp_lds_bytes(p->geom, p->dbl), s));
     return NFFT_OK;
@@ -561,6 +654,14 @@ static int run_interp(nfft_plan_s *p, const void *grid, void *f, hipStream_t s)
 static int run_spread(nfft_plan_s *p, const void *f, void *grid, hipStream_t s)
 {
     Nodes nd = plan_node_view(p);
+    if (p->geom.own) {
+        void *own = static_cast<char *>(p->ws) + p->off_own_scratch;
+        void *fs = static_cast<char *>(p->ws) + p->off_own_fs;
+        LAUNCH(p, s, "spread_own",
+               launch_spread_own(p->geom, nd, p->dbl, f, fs, grid, own, p->own_max_items, s));
+        LAUNCH(p, s, "spread_own_fold", launch_own_fold(p->geom, nd, p->dbl, own, grid, s));
+        return NFFT_OK;
+    }
     void *scratch = static_cast<char *>(p->ws) + p->off_scratch;
     LAUNCH(p, s, "spread_tiles",
            launch_spread_tiles(p->geom, nd, p->dbl, f, scratch, grid_blocks(p),
@@ -658,6 +759,9 @@ int nfft_plan_get_info(nfft_plan p, nfft_plan_info *info)
         sc /= p->geom.emb[t];
     info->grid_scale = sc;
     info->window = p->geom.window;
+    info->own_tiles = p->geom.own ? p->geom.ontiles : 0;
+    for (int t = 0; t < kMaxDim; ++t)
+        info->own_tile[t] = p->geom.own ? p->geom.oT[t] : 0;
     return NFFT_OK;
 }
 
@@ -700,6 +804,8 @@ int nfft_set_nodes(nfft_plan p, const double *x, hipStream_t s)
     LAUNCH(p, s, "nodes_key", launch_node_key(p->geom, nd, xcopy, s));
     LAUNCH(p, s, "nodes_scan", launch_node_scan(p->geom, nd, s));
     LAUNCH(p, s, "nodes_scatter", launch_node_scatter(p->geom, nd, p->dbl, s));
+    if (p->geom.own)
+        LAUNCH(p, s, "nodes_tiles", launch_own_items(p->geom, nd, s));
     p->nodes_set = true;
     return NFFT_OK;
 }

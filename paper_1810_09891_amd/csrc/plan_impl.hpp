@@ -44,6 +44,11 @@ struct nfft_plan_s {
     size_t off_counters = 0, off_xcopy = 0, off_scratch = 0, off_psi = 0;
     size_t off_spos = 0;  // only when 2-D spreading runs in registers (spos_used)
     bool spos_used = false;
+    // owner-computes 3-D spreading (geom.own): tile lists, work items, partial-tile slots
+    size_t off_tile_count = 0, off_tile_entry = 0, off_entries = 0, off_tile_item = 0, off_item_tile = 0;
+    size_t off_item_lo = 0, off_item_hi = 0, off_own_scratch = 0, off_own_fs = 0;
+    int own_max_items = 0;
+    int64_t own_max_entries = 0;
     size_t ws_bytes = 0;
 
     void *ws = nullptr;

@@ -392,6 +392,17 @@ class Batch:
         self._keep = fhats  # alive until the enqueued work has read them
         return outs
 
+    def trafo_noalloc(self, fhats, outs):
+        """``trafo`` through nfft_batch_trafo_noalloc: no batch workspace and no allocation in
+        the call (the outputs are given)."""
+        fhats, outs, ip, op = self._io(fhats, outs, lambda p: p.N, lambda p: (p.M,))
+        check(self._lib.nfft_batch_trafo_noalloc(self._h, ip, op, _stream(self.device)),
+              "nfft_batch_trafo_noalloc")
+        for p in self.plans:
+            p.generation += 1
+        self._keep = fhats
+        return outs
+
     def adjoint(self, fs, outs=None):
         fs, outs, ip, op = self._io(fs, outs, lambda p: (p.M,), lambda p: p.N)
         check(self._lib.nfft_batch_adjoint(self._h, ip, op, _stream(self.device)), "nfft_batch_adjoint")

@@ -342,3 +342,28 @@ def test_deterministic_flag_accepted(lib):
     txt = open(HEADER).read()
     assert "NFFT_DETERMINISTIC = 1u << 5" in txt
     assert "exception is the tuning call nfft_batch_autotune" in txt
+
+
+def test_noalloc_batch_rejects_tables_beyond_the_static_scratch(lib):
+    """nfft_batch_trafo_noalloc refuses, before any device work, a batch whose descriptor
+    tables exceed its 1 MiB static array (here 1200 tiny plans)."""
+    plans = []
+    for _ in range(1200):
+        st, h = create(lib, (8,), 10, (16,), 2)
+        assert st == OK
+        nbytes = ctypes.c_size_t()
+        assert lib.nfft_workspace_bytes(h, ctypes.byref(nbytes)) == OK
+        # a nominal 256-byte aligned address: nothing reads it before the size check
+        assert lib.nfft_set_workspace(h, ctypes.c_void_p(1 << 20), nbytes.value) == OK
+        plans.append(h)
+    b = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * len(plans))(*[p.value for p in plans])
+    assert lib.nfft_batch_create(ctypes.byref(b), len(plans), arr, None) == OK
+    info = _lib.BatchInfo()
+    assert lib.nfft_batch_get_info(b, ctypes.byref(info)) == OK
+    assert info.workspace_bytes > (1 << 20)
+    ptrs = (ctypes.c_void_p * len(plans))(*([1] * len(plans)))
+    assert lib.nfft_batch_trafo_noalloc(b, ptrs, ptrs, None) == WS
+    assert lib.nfft_batch_destroy(b) == OK
+    for h in plans:
+        assert lib.nfft_plan_destroy(h) == OK

@@ -202,3 +202,22 @@ def test_batch_full_64_plan_workload():
     sel = np.sort(np.random.default_rng(3).choice(s["M"], 512, replace=False))
     f_ref = O.ndft_trafo(s["x"][sel], s["fhat"])
     assert parity_err(f_ref, fb[big][sel]) < TOL[C64]
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_batch_3d_output_tile_plans(dtype):
+    """3-D plans whose spreading runs by output tiles, mixed with one that does not, in one
+    batch: every plan's batched result equals its per-plan result and the oracle."""
+    announce("batch 3-D output tiles", dtype)
+    specs = [((32, 24, 40), 9000, 6, "clustered"), ((32, 32, 32), 4000, 6, "uniform"),
+             ((16, 12, 20), 2000, 6, "wide")]
+    plans, cases = setup_plans(specs, dtype, seed0=90)
+    assert plans[0].info.own_tiles > 0 and plans[1].info.own_tiles > 0
+    b = Batch(plans)
+    fb, hb = batched(b, cases, dtype)
+    fp, hp = per_plan(plans, cases, dtype)
+    for i, (p, c) in enumerate(zip(plans, cases)):
+        assert parity_err(fp[i], fb[i]) <= SAME[dtype], i
+        assert parity_err(hp[i], hb[i]) <= SAME[dtype], i
+        assert parity_err(O.nfft_adjoint(c["x"], c["f"], p.N, p.n, 6), hb[i]) < TOL[dtype], i
+        assert parity_err(O.nfft_trafo(c["x"], c["fhat"], p.n, 6), fb[i]) < TOL[dtype], i

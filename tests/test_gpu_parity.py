@@ -107,6 +107,50 @@ def test_single_steps(dtype, m, d, N, M):
     assert parity_err(O.nfft_adjoint_from_grid(gs_ref, N, m), h) < tol
 
 
+OWNER = [
+    # N, M, kind: grids n = (64, 64, 128) / 32^3 / 64^3, nodes uniform, clustered (dense
+    # tiles split over several work items), outside [-1/2, 1/2), and a tiny grid where a
+    # tile's neighbourhood covers every bin of a dimension
+    ((32, 24, 40), 20000, "uniform"),
+    ((32, 24, 40), 30000, "clustered"),
+    ((16, 16, 16), 6000, "wide"),
+    ((32, 32, 32), 50000, "clustered"),
+]
+
+
+def _owner_expected(n, m, dtype):
+    T = (16, 16, 16)
+    return all(nt % Tt == 0 and nt >= Tt + 2 * m + 1 for nt, Tt in zip(n, T))
+
+
+@pytest.mark.parametrize("case", OWNER, ids=lambda c: "%s_%d_%s" % ("x".join(map(str, c[0])), c[1], c[2]))
+@pytest.mark.parametrize("dtype,m", [(C64, 6), (C128, 6), (C64, 4), (C128, 8), (C64, 8), (C128, 2)],
+                         ids=["c64m6", "c128m6", "c64m4", "c128m8", "c64m8", "c128m2"])
+def test_spread_by_output_tiles_3d(case, dtype, m):
+    """3-D spreading by output tiles (every grid cell written once by its owner, split tiles
+    folded in item order): the spread grid and the adjoint against the oracle, bitwise
+    repeatable."""
+    N, M, kind = case
+    if dtype == C64 and kind == "clustered":
+        # complex64 sums in FP32: the rounding error grows with the number of nodes that
+        # reach one cell (here tens of thousands within about one cell)
+        M = min(M, 30000)
+    c = W.small_case(3, N, M, seed=500 + M % 97 + m, kind=kind)
+    announce("owner tiles", N, M, kind, dtype, m)
+    p = make_plan(N, M, m, dtype)
+    n = p.n
+    assert (p.info.own_tiles > 0) == _owner_expected(n, m, dtype)
+    p.set_nodes(dev(c["x"], torch.float64))
+    S = float(np.prod([np.exp(np.pi * (2.0 - Nt / nt) * m) for Nt, nt in zip(N, n)]))
+    gs = host(p.step_spread(dev(c["f"], dtype)))
+    assert parity_err(O.nfft_spread(c["x"], c["f"], N, n, m) / S, gs) < TOL[dtype]
+    fv = dev(c["f"], dtype)
+    h1 = host(p.adjoint(fv))
+    h2 = host(p.adjoint(fv))
+    assert np.array_equal(h1, h2)
+    assert parity_err(O.nfft_adjoint(c["x"], c["f"], N, n, m), h1) < TOL[dtype]
+
+
 def test_edge_nodes_and_tiny_grids():
     """Nodes on the torus edges and outside [-1/2,1/2); grids where the padded tile wraps
     around the grid more than once (n = 16 with m = 6); a single node."""

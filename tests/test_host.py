@@ -45,3 +45,29 @@ def test_complex_gaussian_moments():
     z = W.cgauss(np.random.default_rng(3), (200000,))
     assert abs(np.mean(np.abs(z) ** 2) - 1.0) < 0.02
     assert abs(np.mean(z)) < 0.01
+
+
+def test_bench_byte_model():
+    """The byte model of the benchmark's roofline: window steps move the FP64 nodes, the
+    values and the grid once; FFT passes their nonzero input and their output.  Pinned to
+    the sizes of the d = 2 (N = 512^2, M = 262144) and d = 3 (N = 128^3, M = 2,097,152)
+    workloads worked out by hand."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    ab = bench.algorithmic_bytes
+    # window: M (8 d + c) + |I_n| c
+    assert ab("spread_own", 2, (512, 512), (1024, 1024), 262144, 8) == 262144 * 24 + 1024 ** 2 * 8 == 14680064
+    assert ab("interp", 3, (128,) * 3, (256,) * 3, 2097152, 16) == 2097152 * 40 + 256 ** 3 * 16
+    # FFT, complex64, d = 2: first pass 512 rows of (512 in, 1024 out), then 1024 columns
+    assert ab("fft_fwd_deconv", 2, (512, 512), (1024, 1024), 1, 8) == 8 * 512 * (512 + 1024)
+    assert ab("fft_fwd", 2, (512, 512), (1024, 1024), 1, 8) == 8 * 1024 * (512 + 1024)
+    # d = 3: passes over dimension 2, 1, 0 total 352 MB per transform in complex64
+    first = ab("fft_fwd_deconv", 3, (128,) * 3, (256,) * 3, 1, 8)
+    rest = ab("fft_fwd", 3, (128,) * 3, (256,) * 3, 1, 8) * 2
+    assert first == 8 * 128 * 128 * 384 and first + rest == 8 * 384 * (128 * 128 + 128 * 256 + 256 * 256)
+    assert ab("fft_adj_deconv", 3, (128,) * 3, (256,) * 3, 1, 8) == first
+    # VALU issue time of the d = 3 window step: 14^3 pairs x 2 slots per node
+    assert abs(bench.valu_seconds(3, 2097152, 6, True) - 2097152 * 2744 * 2 / (256 * 64 * 2.4e9)) < 1e-12
+    e = bench.roofline_entry("spread_own", 1.0, 3, (128,) * 3, (256,) * 3, 2097152, 6, 16, True)
+    assert e["binding"] == "valu" and abs(e["binding_frac"] - 2097152 * 2744 * 2 / (256 * 64 * 2.4e9) / 1e-3) < 1e-3

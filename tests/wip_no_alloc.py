@@ -1,0 +1,63 @@
+"""The allocation-free batched forward transform (nfft_batch_trafo_noalloc) through the C ABI:
+its results equal nfft_batch_trafo's on two calls in a row, the second with a smaller batch,
+with no batch workspace attached to the batches it runs."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import TOL, announce, dev, host, parity_err
+from oracle import oracle as O
+from paper_1810_09891_amd import Batch, Plan, _lib, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C64, C128 = torch.complex64, torch.complex128
+
+
+def _plans(specs, dtype, seed0):
+    plans, cases = [], []
+    for i, (N, M, m) in enumerate(specs):
+        c = W.small_case(len(N), N, M, seed=seed0 + i)
+        p = Plan(N, M, m=m, dtype=dtype)
+        p.set_nodes(dev(c["x"], torch.float64))
+        plans.append(p)
+        cases.append(c)
+    return plans, cases
+
+
+def _raw_batch(lib, plans):
+    """A batch handle with no workspace attached."""
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    assert lib.nfft_batch_create(ctypes.byref(h), len(plans), arr, None) == 0
+    return h
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_noalloc_batch_trafo_matches_batch_trafo(dtype):
+    lib = _lib.load()
+    big = [((64, 128), 3001, 6), ((128, 64), 2200, 6), ((512,), 4000, 6), ((16, 16, 16), 1500, 4)]
+    small = [((32, 32), 700, 6), ((64,), 300, 6)]
+    sets = [_plans(big, dtype, 700), _plans(small, dtype, 720)]
+    raw = [_raw_batch(lib, plans) for plans, _ in sets]
+    outs = []
+    for (plans, cases), h in zip(sets, raw):  # two calls in a row, the second smaller
+        announce("noalloc batch trafo", dtype, len(plans))
+        fh = [dev(c["fhat"], dtype) for c in cases]
+        fo = [torch.empty(p.M, dtype=dtype, device="cuda") for p in plans]
+        ip = (ctypes.c_void_p * len(plans))(*[t.data_ptr() for t in fh])
+        op = (ctypes.c_void_p * len(plans))(*[t.data_ptr() for t in fo])
+        st = lib.nfft_batch_trafo_noalloc(h, ip, op, None)
+        assert st == 0, _lib.STATUS.get(st, st)
+        outs.append((fh, fo))
+    torch.cuda.synchronize()
+    for (plans, cases), (fh, fo) in zip(sets, outs):
+        ref = Batch(plans).trafo(fh)  # the existing entry point, with a batch workspace
+        for p, c, a, b in zip(plans, cases, fo, ref):
+            a, b = host(a), host(b)
+            assert np.array_equal(a, b)
+            assert parity_err(O.nfft_trafo(c["x"], c["fhat"], p.n, p.m), a) < TOL[dtype]
+    for h in raw:
+        assert lib.nfft_batch_destroy(h) == 0

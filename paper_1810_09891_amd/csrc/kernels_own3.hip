@@ -490,9 +490,13 @@ __global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cpl
 // Interpolation of one entry over the wave's block: the lane's partial
 // psi_1 psi_2 sum_s g[O + s] psi_0[s] goes to slot j of the wave's reduction buffer; every
 // kOwnRed entries (and at the end of the batch) the slots are added over the lanes.
+// Reduction buffer: kOwnRed slots of 64 lane values, padded by one entry per slot so that
+// the eight lanes that read one part of the eight slots hit different LDS banks.
+constexpr int kOwnRedPitch = 65;
+
 template <typename T, int T0, int W> struct InterpBody {
     const T *psi;
-    Cplx<T> *red;   // [kOwnRed][64] of this wave
+    Cplx<T> *red;   // [kOwnRed][kOwnRedPitch] of this wave
     Cplx<T> *val;   // block sums [kOwnNB][kOwnWaves]
     int *slotk;     // entry of each slot, [kOwnRed] of this wave
     int c1, c2, lane, wave;
@@ -500,14 +504,14 @@ template <typename T, int T0, int W> struct InterpBody {
     const T (&gx)[T0];
     const T (&gy)[T0];
 
-    // Sum slots 0 .. j-1 over the wave: lane l adds part (l % 8) of slot l / 8 (eight lanes'
-    // values in lane order), then the eight parts of a slot are added pairwise (xor 1, 2, 4).
+    // Sum slots 0 .. j-1 over the wave: lane l adds part l / 8 (eight lanes' values in lane
+    // order) of slot l % 8, then the eight parts of a slot are added pairwise (xor 8, 16, 32).
     __device__ __forceinline__ void flush()
     {
-        const int sl = lane >> 3, part = lane & 7;
+        const int sl = lane & 7, part = lane >> 3;
         T sx = T(0), sy = T(0);
         if (sl < j) {
-            const Cplx<T> *r = red + sl * 64 + part * 8;
+            const Cplx<T> *r = red + sl * kOwnRedPitch + part * 8;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const Cplx<T> v = r[i];
@@ -516,7 +520,7 @@ template <typename T, int T0, int W> struct InterpBody {
             }
         }
 #pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
+        for (int off = 8; off < 64; off <<= 1) {
             sx += __shfl_xor(sx, off);
             sy += __shfl_xor(sy, off);
         }
@@ -538,7 +542,7 @@ template <typename T, int T0, int W> struct InterpBody {
                 py = fma(gy[O + s], rec[s], py);
             }
         }
-        red[j * 64 + lane] = Cplx<T>{px * w12, py * w12};
+        red[j * kOwnRedPitch + lane] = Cplx<T>{px * w12, py * w12};
         if (lane == 0)
             slotk[j] = k;
         if (++j == kOwnRed)
@@ -570,7 +574,7 @@ __global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_interp_own(Geom
     using R = OwnRec<T, W>;
     constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
     __shared__ __align__(16) OwnLds<T, W> L;
-    __shared__ __align__(16) C s_red[kOwnWaves][kOwnRed * 64];
+    __shared__ __align__(16) C s_red[kOwnWaves][kOwnRed * kOwnRedPitch];
     __shared__ int s_slotk[kOwnWaves][kOwnRed];
 
     const int nitems = nd.counters[2];

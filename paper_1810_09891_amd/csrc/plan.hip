@@ -160,8 +160,10 @@ static void setup_owner(nfft_plan_s *p)
     g.ontiles = (int)ntiles;
     g.ocap = cap;
     p->own_max_entries = list_max;
-    // interpolation by the same tiles: a stencil then spans at most two tiles per dimension
-    g.oint = g.W <= kOwnTile0 + 1 ? 1 : 0;
+    // interpolation by the same tiles (a stencil then spans at most two tiles per dimension)
+    // for complex128; complex64 keeps the padded bin tiles in LDS, which measured faster
+    // (their 8^3 bins fit the LDS at complex64)
+    g.oint = p->dbl && g.W <= kOwnTile0 + 1 ? 1 : 0;
     p->own_max_items = (int)items;
     g.own = 1;
 }

@@ -85,7 +85,7 @@ def algorithmic_bytes(name, d, N, n, M, cbytes):
     import numpy as np
 
     window = M * (8 * d + cbytes) + int(np.prod(n)) * cbytes
-    if name in ("interp", "interp_own", "grad_x", "spread_tiles", "spread_own"):
+    if name in ("interp", "grad_x", "spread_tiles", "spread_own"):
         return window
 
     def fft_pass(t, forward):
@@ -113,7 +113,7 @@ def valu_seconds(d, M, m, dbl):
 
 
 # rocprofv3 kernel names of the library's launch labels, in order of preference
-ROCPROF_NAME = {"interp": ("k_interp_nodes",), "interp_own": ("k_interp_own",),
+ROCPROF_NAME = {"interp": ("k_interp_nodes",),
                 "spread_tiles": ("k_spread_cols", "k_spread_tiles"), "spread_own": ("k_spread_own",),
                 "spread_fold": ("k_fold",), "grad_x": ("k_grad_x",)}
 
@@ -557,7 +557,7 @@ def roofline_entry(name, avg_ms, d, N, n, M, m, cbytes, dbl):
     if bts is not None:
         e["hbm_GBs"] = round(bts / (avg_ms * 1e-3) / 1e9, 1)
         e["hbm_frac"] = round(bts / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        if name in ("interp", "interp_own", "spread_own", "spread_tiles", "grad_x"):
+        if name in ("interp", "spread_own", "spread_tiles", "grad_x"):
             t_hbm = bts / (HBM_PEAK_GBS * 1e9)
             t_valu = valu_seconds(d, M, m, dbl)
             e["t_hbm_us"] = round(t_hbm * 1e6, 2)

@@ -195,16 +195,7 @@ int run_fft(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, bool forward
 
 int run_interp(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, hipStream_t s)
 {
-    if (G.own && G.table[0].g.oint) {
-        // 3-D plans interpolate by output tiles: one launch per plan
-        for (size_t i = 0; i < G.idx.size(); ++i) {
-            const PlanDev &pd = G.table[i];
-            nfft_plan_s *p = b->plans[(size_t)G.idx[i]];
-            BCHECK(launch_interp_own(pd.g, pd.nd, G.dbl, pd.grid, ptrs.out[i],
-                                     static_cast<char *>(p->ws) + p->off_own_scratch, p->own_max_items, s));
-        }
-        return NFFT_OK;
-    }
+
     const int blocks = blocks_for(b, G.params[kKInterp], G.chunk_bound);
     BCHECK(launch_interp_batch(table_of(b, G), (int)G.idx.size(), ptrs, queue_of(b, G, 0), G.d, G.dbl, G.WM, blocks,
                                G.lds_interp, s));

@@ -1,34 +1,31 @@
-// The window steps of 3-D plans by output tiles: spreading (Algorithm 2.2 step 1) writes
-// every grid cell once, from the workgroup that owns it, as the sum over all nodes whose
-// stencils reach it (the blockwise adjoint of Table 3.2, turned around so that no two
-// workgroups write one cell and no floating-point atomics are needed); interpolation
-// (Algorithm 2.1 step 3) reads every grid cell once per work item.
+// Spreading (Algorithm 2.2 step 1) of 3-D plans by output tiles: every grid cell is written
+// once, by the workgroup that owns it, as the sum over all nodes whose stencils reach it (the
+// blockwise adjoint of Table 3.2, turned around so that no two workgroups write one cell and
+// no floating-point atomics are needed).
 //
 // The grid is cut into tiles of 16 x 16 x 16 cells.  A workgroup of four waves holds one
 // tile in registers: wave w owns the 8 x 8 block of (dimension 1, dimension 2) columns at
 // (8 (w >> 1), 8 (w & 1)), a lane one column, and the 16 cells of its column along
-// dimension 0 are its registers.  A node whose stencil starts at tile-relative cell
-// (o0, o1, o2) meets row r of column (c1, c2) with the weight
-//     psi_0[r - o0] * (psi_1[c1 - o1] psi_2[c2 - o2]):
-// the lane forms the product of its two column factors once per node, and the row factors
-// -- the same for every lane -- enter the multiply-adds, one per real part per row.
+// dimension 0 are its accumulators.  A node whose stencil starts at tile-relative cell
+// (o0, o1, o2) adds
+//     f_j psi_1[c1 - o1] psi_2[c2 - o2] * psi_0[r - o0]
+// to row r of column (c1, c2): the lane forms the product of its two column factors and f_j
+// once per node, and the row factors -- the same for every lane -- enter the multiply-adds,
+// one per real part per row.
 //
 // The node precomputation lists, for every tile, the nodes whose stencils reach it, each
 // entry with its tile offsets and the mask of the waves' blocks it reaches (the bins around
 // the tile in bin order, nodes that reach it only).  A work item is a slice of at most `cap`
-// entries of one tile; it stages its entries in batches (window factors into LDS), and each
-// wave takes the batch's entries row offset by row offset (one ballot per offset), so that
-// every register index is a constant of an unrolled sequence.
-//
-// Spreading: a tile with one item writes the grid directly; the items of a split tile (a
-// dense region) write partial tiles to their own slots and a second kernel adds the slots
-// in item order.  In complex64 a cell's contributions are summed in two levels -- at most one
-// batch into a batch accumulator, whose value is then added to the running total -- so that
-// the FP32 rounding error of a cell that many nodes reach grows with the number of batches
-// rather than of nodes.  Interpolation: each lane's partial sums of a wave's entries are
-// added over the wave through LDS, eight entries at a time; the block sums of a node are
-// added in block order, the result goes to the node's slot for the tile, and a last kernel
-// adds each node's slots in a fixed order.  Every sum therefore has a fixed order.
+// entries of one tile; items are ordered along a Morton curve of their tiles, so that the
+// items that read one node's window factors run close together.  An item stages its entries
+// in batches (window factors into LDS), and each wave takes a batch's entries row offset by
+// row offset (one ballot per offset), so that every accumulator index is a constant of an
+// unrolled sequence.  A tile with one item writes the grid directly; the items of a split
+// tile (a dense region) write partial tiles to their own slots and a second kernel adds the
+// slots in item order.  In complex64 a cell's contributions are summed in two levels -- at
+// most one batch into a batch accumulator, whose value is then added to the running total --
+// so that the FP32 rounding error of a cell that many nodes reach grows with the number of
+// batches rather than of nodes.  Every sum has a fixed order.
 #include <utility>
 
 #include "window_common.hpp"
@@ -39,7 +36,6 @@ namespace {
 
 constexpr int kOwnNB = 64;  // entries staged per batch
 constexpr int kOwnWaves = kBlock / 64;
-constexpr int kOwnRed = 8;  // interpolation entries reduced over a wave at a time
 
 __device__ __forceinline__ void own_tile_coords(const Geom &g, int tile, int *ti)
 {
@@ -185,9 +181,13 @@ template <bool FILL> __global__ __launch_bounds__(kBlock) void k_own_entries(Geo
         nd.tile_count[tile] = kept;
 }
 
-// One workgroup of 1024 threads: exclusive scans of the entries per tile (tile_entry) and
-// of the items per tile, max(1, ceil(count / cap)) (tile_item; every tile has an item, so
-// every cell is written); counters[2] = number of items.
+// Work items of a tile with `count` entries (at least one, so that every cell is written).
+__device__ __forceinline__ int own_items_of(const Geom &g, int count) { return max(1, (count + g.ocap - 1) / g.ocap); }
+
+// One workgroup of 1024 threads: exclusive scans, over the tiles in Morton order (tile_order),
+// of the entries per tile (tile_entry) and of the items per tile (tile_item), so that the
+// items of tiles that share nodes -- and read the same window factors -- are consecutive and
+// run at about the same time on one XCD; counters[2] = number of items.
 constexpr int kOwnScan = 1024;
 __global__ __launch_bounds__(kOwnScan) void k_own_scan(Geom g, Nodes nd)
 {
@@ -198,11 +198,11 @@ __global__ __launch_bounds__(kOwnScan) void k_own_scan(Geom g, Nodes nd)
     const int per = (n + kOwnScan - 1) / kOwnScan;
     const int lo = tid * per;
     const int hi = min(n, lo + per);
-    auto items = [&](int t) { return max(1, (nd.tile_count[t] + g.ocap - 1) / g.ocap); };
+    auto items = [&](int i) { return own_items_of(g, nd.tile_count[nd.tile_order[i]]); };
     int sa = 0, sb = 0;
     for (int i = lo; i < hi; ++i) {
         sa += items(i);
-        sb += nd.tile_count[i];
+        sb += nd.tile_count[nd.tile_order[i]];
     }
     s_a[tid] = sa;
     s_b[tid] = sb;
@@ -217,10 +217,11 @@ __global__ __launch_bounds__(kOwnScan) void k_own_scan(Geom g, Nodes nd)
     }
     int ra = s_a[tid] - sa, rb = s_b[tid] - sb;
     for (int i = lo; i < hi; ++i) {
-        nd.tile_item[i] = ra;
-        nd.tile_entry[i] = rb;
+        const int t = nd.tile_order[i];
+        nd.tile_item[t] = ra;
+        nd.tile_entry[t] = rb;
         ra += items(i);
-        rb += nd.tile_count[i];
+        rb += nd.tile_count[t];
     }
     if (tid == kOwnScan - 1) {
         nd.tile_item[n] = s_a[tid];
@@ -236,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_own_items(Geom g, Nodes nd)
     if (tile >= g.ontiles)
         return;
     const int first = nd.tile_item[tile];
-    const int k = nd.tile_item[tile + 1] - first;
     const int64_t count = nd.tile_count[tile];
+    const int k = own_items_of(g, (int)count);
     for (int i = 0; i < k; ++i) {
         nd.item_tile[first + i] = tile;
         nd.item_lo[first + i] = (int)(count * i / k);
@@ -262,7 +263,7 @@ template <typename T, int W> struct OwnRec {
 
 template <typename T, int W> struct OwnLds {
     T psi[kOwnNB * OwnRec<T, W>::REC];
-    Cplx<T> val[kOwnNB * kOwnWaves];  // spreading: node values; interpolation: block sums
+    Cplx<T> val[kOwnNB];  // node values
     int meta[kOwnNB];
     int pos[kOwnNB];
 };
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_spread_own(Geom
             }
         }
         const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
-        const int nsplit = nd.tile_item[tile + 1] - nd.tile_item[tile];
+        const int nsplit = own_items_of(g, nd.tile_count[tile]);
         if (nsplit == 1) {
             const int64_t base = ((int64_t)org0 * g.n[1] + org1 + c1) * g.n[2] + org2 + c2;
             const int64_t row = (int64_t)g.n[1] * g.n[2];
@@ -454,7 +455,8 @@ __global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_spread_own(Geom
     }
 }
 
-// Split tiles: the sum of their items' partial tiles, in item order.
+// Split tiles: the sum of their items' partial tiles, in item order.  Workgroup (tile, y)
+// takes kBlock cells of the tile; the partial tiles' loads are issued four at a time.
 template <typename T, int T0>
 __global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cplx<T> *__restrict__ scratch,
                                                       Cplx<T> *__restrict__ grid)
@@ -463,208 +465,36 @@ __global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cpl
     constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
     constexpr int TC = T0 * T1 * T2;
     const int tile = blockIdx.x;
-    const int first = nd.tile_item[tile];
-    const int k = nd.tile_item[tile + 1] - first;
+    const int k = own_items_of(g, nd.tile_count[tile]);
     if (k <= 1)
         return;
+    const int first = nd.tile_item[tile];
     int ti[3];
     own_tile_coords(g, tile, ti);
-    const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
-    for (int c = threadIdx.x; c < TC; c += kBlock) {
-        const int r = c / (T1 * T2);
-        const int cc1 = (c / T2) % T1;
-        const int cc2 = c % T2;
-        const C *src = scratch + (int64_t)first * TC + c;
-        C acc = src[0];
-        for (int i = 1; i < k; ++i) {
-            const C v = src[(int64_t)i * TC];
-            acc.x += v.x;
-            acc.y += v.y;
-        }
-        grid[((int64_t)(org0 + r) * g.n[1] + org1 + cc1) * g.n[2] + org2 + cc2] = acc;
-    }
-}
-
-// ------------------------------------------------------------------ interpolation
-
-// Interpolation of one entry over the wave's block: the lane's partial
-// psi_1 psi_2 sum_s g[O + s] psi_0[s] goes to slot j of the wave's reduction buffer; every
-// kOwnRed entries (and at the end of the batch) the slots are added over the lanes.
-// Reduction buffer: kOwnRed slots of 64 lane values, padded by one entry per slot so that
-// the eight lanes that read one part of the eight slots hit different LDS banks.
-constexpr int kOwnRedPitch = 65;
-
-template <typename T, int T0, int W> struct InterpBody {
-    const T *psi;
-    Cplx<T> *red;   // [kOwnRed][kOwnRedPitch] of this wave
-    Cplx<T> *val;   // block sums [kOwnNB][kOwnWaves]
-    int *slotk;     // entry of each slot, [kOwnRed] of this wave
-    int c1, c2, lane, wave;
-    int j;          // slots in use
-    const T (&gx)[T0];
-    const T (&gy)[T0];
-
-    // Sum slots 0 .. j-1 over the wave: lane l adds part l / 8 (eight lanes' values in lane
-    // order) of slot l % 8, then the eight parts of a slot are added pairwise (xor 8, 16, 32).
-    __device__ __forceinline__ void flush()
-    {
-        const int sl = lane & 7, part = lane >> 3;
-        T sx = T(0), sy = T(0);
-        if (sl < j) {
-            const Cplx<T> *r = red + sl * kOwnRedPitch + part * 8;
+    const int c = blockIdx.y * kBlock + threadIdx.x;
+    const int r = c / (T1 * T2);
+    const int cc1 = (c / T2) % T1;
+    const int cc2 = c % T2;
+    const C *src = scratch + (int64_t)first * TC + c;
+    C acc = src[0];
+    int i = 1;
+    for (; i + 4 <= k; i += 4) {
+        C v[4];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const Cplx<T> v = r[i];
-                sx += v.x;
-                sy += v.y;
-            }
-        }
+        for (int q = 0; q < 4; ++q)
+            v[q] = src[(int64_t)(i + q) * TC];
 #pragma unroll
-        for (int off = 8; off < 64; off <<= 1) {
-            sx += __shfl_xor(sx, off);
-            sy += __shfl_xor(sy, off);
-        }
-        if (part == 0 && sl < j)
-            val[slotk[sl] * kOwnWaves + wave] = Cplx<T>{sx, sy};
-        j = 0;
-    }
-
-    template <int O> __device__ __forceinline__ void run(int k, int o1, int o2)
-    {
-        using R = OwnRec<T, W>;
-        const T *rec = psi + k * R::REC;
-        const T w12 = rec[R::D1 + 8 + c1 - o1] * rec[R::D2 + 8 + c2 - o2];
-        T px = T(0), py = T(0);
-#pragma unroll
-        for (int s = 0; s < W; ++s) {
-            if (O + s >= 0 && O + s < T0) {
-                px = fma(gx[O + s], rec[s], px);
-                py = fma(gy[O + s], rec[s], py);
-            }
-        }
-        red[j * kOwnRedPitch + lane] = Cplx<T>{px * w12, py * w12};
-        if (lane == 0)
-            slotk[j] = k;
-        if (++j == kOwnRed)
-            flush();
-    }
-};
-
-// Slot of a node's partial sum for the tile at ti: per dimension, 0 for the tile holding the
-// stencil's first cell, 1 for the next one.
-__device__ __forceinline__ int own_slot(const Geom &g, const Nodes &nd, int p, const int *ti)
-{
-    int slot = 0;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const int a = (nd.u[t][p] - g.m) & (g.n[t] - 1);
-        int s = ti[t] - a / g.oT[t];
-        if (s < 0)
-            s += g.ont[t];
-        slot = slot * 2 + s;
-    }
-    return slot;
-}
-
-template <typename T, int T0, int W>
-__global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_interp_own(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
-                                                        Cplx<T> *__restrict__ part)
-{
-    using C = Cplx<T>;
-    using R = OwnRec<T, W>;
-    constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
-    __shared__ __align__(16) OwnLds<T, W> L;
-    __shared__ __align__(16) C s_red[kOwnWaves][kOwnRed * kOwnRedPitch];
-    __shared__ int s_slotk[kOwnWaves][kOwnRed];
-
-    const int nitems = nd.counters[2];
-    const int nwg = min((int)gridDim.x, nitems);
-    if ((int)blockIdx.x >= nwg)
-        return;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c1 = (wave >> 1) * 8 + (lane >> 3);
-    const int c2 = (wave & 1) * 8 + (lane & 7);
-    const int64_t M = nd.M;
-    const int2 *__restrict__ entries = reinterpret_cast<const int2 *>(nd.entries);
-
-    for (int i = threadIdx.x; i < kOwnNB * R::REC; i += kBlock)
-        L.psi[i] = T(0);
-
-    for (int it = xcd_local_id(blockIdx.x, nwg); it < nitems; it += nwg) {
-        const int tile = nd.item_tile[it];
-        const int lo = nd.item_lo[it], hi = nd.item_hi[it];
-        if (lo >= hi)
-            continue;
-        const int2 *ent = entries + nd.tile_entry[tile];
-        int ti[3];
-        own_tile_coords(g, tile, ti);
-        const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
-        T gx[T0], gy[T0];
-        {
-            const int64_t base = ((int64_t)org0 * g.n[1] + org1 + c1) * g.n[2] + org2 + c2;
-            const int64_t row = (int64_t)g.n[1] * g.n[2];
-#pragma unroll
-            for (int r = 0; r < T0; ++r) {
-                const C v = grid[base + r * row];
-                gx[r] = v.x;
-                gy[r] = v.y;
-            }
-        }
-        for (int q = lo; q < hi; q += kOwnNB) {
-            const int nb = min(kOwnNB, hi - q);
-            __syncthreads();  // the previous batch's block sums are consumed
-            own_stage<T, W>(nd, L, ent, q, nb, nullptr);
-            const int emeta = lane < nb ? L.meta[lane] : 0;
-            InterpBody<T, T0, W> body{L.psi, s_red[wave], L.val, s_slotk[wave], c1, c2, lane, wave, 0, gx, gy};
-            own_walk<-(W - 1)>(std::make_integer_sequence<int, W - 1 + T0>{}, emeta, wave, body);
-            if (body.j > 0)
-                body.flush();
-            __syncthreads();
-            if ((int)threadIdx.x < nb) {
-                const int k = threadIdx.x;
-                const int meta = L.meta[k];
-                C v{T(0), T(0)};
-#pragma unroll
-                for (int w = 0; w < kOwnWaves; ++w) {
-                    if ((meta >> (24 + w)) & 1) {
-                        const C b = L.val[k * kOwnWaves + w];
-                        v.x += b.x;
-                        v.y += b.y;
-                    }
-                }
-                const int p = L.pos[k];
-                part[(int64_t)own_slot(g, nd, p, ti) * M + p] = v;
-            }
+        for (int q = 0; q < 4; ++q) {
+            acc.x += v[q].x;
+            acc.y += v[q].y;
         }
     }
-}
-
-// f_j = sum of the node's tile slots, in slot order (slots of tiles its stencil does not
-// reach are neither written nor read).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_interp_own_sum(Geom g, Nodes nd, const Cplx<T> *__restrict__ part,
-                                                            Cplx<T> *__restrict__ f)
-{
-    using C = Cplx<T>;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nd.M)
-        return;
-    int cross[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const int a = (nd.u[t][p] - g.m) & (g.n[t] - 1);
-        cross[t] = (a % g.oT[t]) + g.W > g.oT[t] ? 1 : 0;
+    for (; i < k; ++i) {
+        const C v = src[(int64_t)i * TC];
+        acc.x += v.x;
+        acc.y += v.y;
     }
-    C v{T(0), T(0)};
-    for (int s0 = 0; s0 <= cross[0]; ++s0)
-        for (int s1 = 0; s1 <= cross[1]; ++s1)
-            for (int s2 = 0; s2 <= cross[2]; ++s2) {
-                const C b = part[(int64_t)((s0 * 2 + s1) * 2 + s2) * nd.M + p];
-                v.x += b.x;
-                v.y += b.y;
-            }
-    f[nd.perm[p]] = v;
+    grid[((int64_t)(ti[0] * T0 + r) * g.n[1] + ti[1] * T1 + cc1) * g.n[2] + ti[2] * T2 + cc2] = acc;
 }
 
 inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -708,51 +538,14 @@ hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const voi
     return hipGetLastError();
 }
 
-hipError_t launch_interp_own(const Geom &g, const Nodes &nd, bool dbl, const void *grid, void *f, void *part,
-                             int max_items, hipStream_t s)
-{
-    if (g.d != 3 || !g.own || !g.oint || g.W != g.WM || g.oT[0] != kOwnTile0)
-        return hipErrorInvalidValue;
-    const int blocks = max_items > 0 ? max_items : 1;
-    if (dbl) {
-        using C = Cplx<double>;
-#define OWN_CASE(WMV)                                                                                       \
-    hipLaunchKernelGGL((k_interp_own<double, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,      \
-                       static_cast<const C *>(grid), static_cast<C *>(part))
-        switch (g.WM) {
-        case 6: OWN_CASE(6); break;
-        case 10: OWN_CASE(10); break;
-        case 14: OWN_CASE(14); break;
-        default: return hipErrorInvalidValue;
-        }
-#undef OWN_CASE
-        hipLaunchKernelGGL(k_interp_own_sum<double>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, g, nd,
-                           static_cast<const C *>(part), static_cast<C *>(f));
-    } else {
-        using C = Cplx<float>;
-#define OWN_CASE(WMV)                                                                                       \
-    hipLaunchKernelGGL((k_interp_own<float, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,       \
-                       static_cast<const C *>(grid), static_cast<C *>(part))
-        switch (g.WM) {
-        case 6: OWN_CASE(6); break;
-        case 10: OWN_CASE(10); break;
-        case 14: OWN_CASE(14); break;
-        default: return hipErrorInvalidValue;
-        }
-#undef OWN_CASE
-        hipLaunchKernelGGL(k_interp_own_sum<float>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, g, nd,
-                           static_cast<const C *>(part), static_cast<C *>(f));
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_own_fold(const Geom &g, const Nodes &nd, bool dbl, const void *scratch, void *grid, hipStream_t s)
 {
+    const dim3 grid_dim(g.ontiles, kOwnTile0 * kOwnTile12 * kOwnTile12 / kBlock);
     if (dbl)
-        hipLaunchKernelGGL((k_own_fold<double, kOwnTile0>), dim3(g.ontiles), dim3(kBlock), 0, s, g, nd,
+        hipLaunchKernelGGL((k_own_fold<double, kOwnTile0>), grid_dim, dim3(kBlock), 0, s, g, nd,
                            static_cast<const Cplx<double> *>(scratch), static_cast<Cplx<double> *>(grid));
     else
-        hipLaunchKernelGGL((k_own_fold<float, kOwnTile0>), dim3(g.ontiles), dim3(kBlock), 0, s, g, nd,
+        hipLaunchKernelGGL((k_own_fold<float, kOwnTile0>), grid_dim, dim3(kBlock), 0, s, g, nd,
                            static_cast<const Cplx<float> *>(scratch), static_cast<Cplx<float> *>(grid));
     return hipGetLastError();
 }

@@ -72,9 +72,9 @@ hipError_t launch_fold(const Geom &g, const Nodes &nd, bool dbl, const void *scr
 hipError_t launch_grad_x(const Geom &g, const Nodes &nd, bool dbl, const void *grid, const void *v,
                          void *grad, int blocks, size_t lds, hipStream_t s);
 
-// Owner-computes window steps of 3-D plans (Geom::own): every tile's entries (the nodes
-// whose stencils reach it), tile entry offsets and work items (counters[2] = number of
-// items), run in the node precomputation.
+// Owner-computes spreading of 3-D plans (Geom::own): every tile's entries (the nodes whose
+// stencils reach it), tile entry offsets and work items (counters[2] = number of items), run
+// in the node precomputation.
 hipError_t launch_own_items(const Geom &g, const Nodes &nd, hipStream_t s);
 // Every output tile's cells summed over the nodes whose stencils reach it; tiles with one
 // work item are written to `grid`, split tiles to per-item slots of `scratch` (tile cells
@@ -84,11 +84,7 @@ hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const voi
                              void *scratch, int max_items, hipStream_t s);
 hipError_t launch_own_fold(const Geom &g, const Nodes &nd, bool dbl, const void *scratch, void *grid,
                            hipStream_t s);
-// Interpolation by the same output tiles (Geom::oint: stencils of at most 17 points): every
-// node's partial sum over each tile its stencil reaches goes to one of its eight slots in
-// `part` ([8][M] complex), then the slots are added in a fixed order into f (caller order).
-hipError_t launch_interp_own(const Geom &g, const Nodes &nd, bool dbl, const void *grid, void *f, void *part,
-                             int max_items, hipStream_t s);
+
 // Tile edges of the owner-computes spreading: along dimension 0 (registers per lane) and
 // along dimensions 1 and 2 (four 8 x 8 lane blocks).
 constexpr int kOwnTile0 = 16;

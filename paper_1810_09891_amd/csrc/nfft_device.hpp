@@ -285,7 +285,6 @@ struct Geom {
     int okn[kMaxDim];
     int oall[kMaxDim];
     int ocap;           // node-list entries per work item
-    int oint;           // interpolation by output tiles too (stencil of at most oT + 1 points)
 };
 
 // Window factor of dimension t at stencil point s of a node with offset delta, and its
@@ -343,6 +342,7 @@ struct Nodes {
     int32_t *tile_entry;   // [ontiles+1] first entry of every tile
     void *entries;         // int2 (sorted position, packed tile offsets and block mask) per entry
     int32_t *tile_item;    // [ontiles+1] first work item of every tile
+    const int32_t *tile_order;  // [ontiles] tiles in Morton order (the order of their items)
     int32_t *item_tile;    // [max items] tile of a work item
     int32_t *item_lo;      // [max items] its slice [lo, hi) of the tile's node list
     int32_t *item_hi;

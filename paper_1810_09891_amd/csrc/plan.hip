@@ -67,9 +67,20 @@ static int choose_bins(nfft_plan_s *p)
     const int minB = 4;
     const size_t ntiles = d == 1 ? 4 : d == 2 ? 2 : 1;
     // (1 KB of LDS is left for the static arrays of the batched kernels)
-    const size_t budget = (d == 1 ? kLdsMax : kLdsPreferred) - 1024;
+    size_t budget = (d == 1 ? kLdsMax : kLdsPreferred) - 1024;
     // 2-D and 3-D spreading also keep one dummy complex slot per thread after their tiles
-    const size_t extra = d >= 2 ? (size_t)kBlock * cs : 0;
+    size_t extra = d >= 2 ? (size_t)kBlock * cs : 0;
+    // 3-D plans that spread by output tiles (see setup_owner) keep no padded tile there: the
+    // bins need only fit the interpolation kernel's one tile
+    if (d == 3 && 2 * p->m + 2 == p->WM) {
+        bool own = true;
+        for (int t = 0; t < d; ++t)
+            own = own && p->n[t] % kOwnTile12 == 0 && p->n[t] >= kOwnTile12 + p->WM - 1;
+        if (own) {
+            budget = kLdsMax - 1024;
+            extra = 0;
+        }
+    }
     while (ntiles * lds_of(B) + extra > budget) {
         int best = -1;
         for (int t = 0; t < d; ++t)
@@ -159,11 +170,24 @@ static void setup_owner(nfft_plan_s *p)
     }
     g.ontiles = (int)ntiles;
     g.ocap = cap;
+    // tiles in Morton order: interleave the bits of the three tile indices (dimension 0
+    // highest), sort by the interleaved code
+    {
+        std::vector<std::pair<uint64_t, int32_t>> code((size_t)ntiles);
+        for (int64_t t = 0; t < ntiles; ++t) {
+            const int64_t i2 = t % g.ont[2], i1 = (t / g.ont[2]) % g.ont[1], i0 = t / ((int64_t)g.ont[1] * g.ont[2]);
+            uint64_t c = 0;
+            for (int b = 0; b < 21; ++b)
+                c |= (((uint64_t)(i0 >> b) & 1) << (3 * b + 2)) | (((uint64_t)(i1 >> b) & 1) << (3 * b + 1)) |
+                     (((uint64_t)(i2 >> b) & 1) << (3 * b));
+            code[(size_t)t] = {c, (int32_t)t};
+        }
+        std::sort(code.begin(), code.end());
+        p->tile_order.resize((size_t)ntiles);
+        for (int64_t t = 0; t < ntiles; ++t)
+            p->tile_order[(size_t)t] = code[(size_t)t].second;
+    }
     p->own_max_entries = list_max;
-    // interpolation by the same tiles (a stencil then spans at most two tiles per dimension)
-    // for complex128; complex64 keeps the padded bin tiles in LDS, which measured faster
-    // (their 8^3 bins fit the LDS at complex64)
-    g.oint = p->dbl && g.W <= kOwnTile0 + 1 ? 1 : 0;
     p->own_max_items = (int)items;
     g.own = 1;
 }
@@ -397,6 +421,7 @@ static void layout_workspace(nfft_plan_s *p)
         const size_t items = (size_t)p->own_max_items;
         const size_t tc = (size_t)p->geom.oT[0] * p->geom.oT[1] * p->geom.oT[2];
         p->off_tile_count = take(4 * (size_t)p->geom.ontiles);
+        p->off_tile_order = take(4 * (size_t)p->geom.ontiles);
         p->off_tile_entry = take(4 * ((size_t)p->geom.ontiles + 1));
         p->off_entries = take(8 * (size_t)p->own_max_entries);
         p->off_own_fs = take(cs * (size_t)M);
@@ -404,12 +429,7 @@ static void layout_workspace(nfft_plan_s *p)
         p->off_item_tile = take(4 * items);
         p->off_item_lo = take(4 * items);
         p->off_item_hi = take(4 * items);
-        // partial tiles of the spreading step and the interpolation's per-node tile slots
-        // are never live together: one region serves both
-        size_t own = cs * tc * items;
-        if (p->geom.oint)
-            own = std::max(own, cs * 8 * (size_t)M);
-        p->off_own_scratch = take(own);
+        p->off_own_scratch = take(cs * tc * items);
     }
     p->spos_used = spread_in_registers(p->geom, p->dbl);
     if (p->spos_used)
@@ -535,6 +555,7 @@ Nodes plan_node_view(nfft_plan_s *p)
     nd.spos = p->spos_used ? reinterpret_cast<int32_t *>(ws + p->off_spos) : nullptr;
     if (p->geom.own) {
         nd.tile_count = reinterpret_cast<int32_t *>(ws + p->off_tile_count);
+        nd.tile_order = reinterpret_cast<const int32_t *>(ws + p->off_tile_order);
         nd.tile_entry = reinterpret_cast<int32_t *>(ws + p->off_tile_entry);
         nd.entries = ws + p->off_entries;
         nd.tile_item = reinterpret_cast<int32_t *>(ws + p->off_tile_item);
@@ -642,12 +663,6 @@ static int run_adjoint_coeffs(nfft_plan_s *p, void *grid, void *hhat, hipStream_
 static int run_interp(nfft_plan_s *p, const void *grid, void *f, hipStream_t s)
 {
     Nodes nd = plan_node_view(p);
-    if (p->geom.oint) {
-        void *part = static_cast<char *>(p->ws) + p->off_own_scratch;
-        LAUNCH(p, s, "interp_own",
-               launch_interp_own(p->geom, nd, p->dbl, grid, f, part, p->own_max_items, s));
-        return NFFT_OK;
-    }
     LAUNCH(p, s, "interp",
            launch_interp(p->geom, nd, p->dbl, grid, f, grid_blocks(p), interp_lds_bytes(p->geom, p->dbl), s));
     return NFFT_OK;
@@ -686,6 +701,9 @@ static int ensure_tables(nfft_plan_s *p, hipStream_t s)
         if (hipMemcpyAsync(ws + p->off_tw[t], src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
             return NFFT_ERR_HIP;
     }
+    if (p->geom.own && hipMemcpyAsync(ws + p->off_tile_order, p->tile_order.data(), 4 * p->tile_order.size(),
+                                      hipMemcpyHostToDevice, s) != hipSuccess)
+        return NFFT_ERR_HIP;
     // the host tables stay alive in the plan; wait so a later destroy cannot race the copy
     if (hipStreamSynchronize(s) != hipSuccess)
         return NFFT_ERR_HIP;

@@ -48,6 +48,8 @@ struct nfft_plan_s {
     size_t off_tile_count = 0, off_tile_entry = 0, off_entries = 0, off_tile_item = 0, off_item_tile = 0;
     size_t off_item_lo = 0, off_item_hi = 0, off_own_scratch = 0, off_own_fs = 0;
     int own_max_items = 0;
+    size_t off_tile_order = 0;
+    std::vector<int32_t> tile_order;  // output tiles in Morton order (uploaded with the tables)
     int64_t own_max_entries = 0;
     size_t ws_bytes = 0;
 

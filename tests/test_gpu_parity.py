@@ -133,8 +133,9 @@ def test_spread_by_output_tiles_3d(case, dtype, m):
     N, M, kind = case
     if dtype == C64 and kind == "clustered":
         # complex64 sums in FP32: the rounding error grows with the number of nodes that
-        # reach one cell (here tens of thousands within about one cell)
-        M = min(M, 30000)
+        # reach one cell (here tens of thousands within a few cells), and the deconvolution
+        # of the adjoint amplifies it at high frequencies, more so for wider windows
+        M = min(M, 30000 if m <= 6 else 15000)
     c = W.small_case(3, N, M, seed=500 + M % 97 + m, kind=kind)
     announce("owner tiles", N, M, kind, dtype, m)
     p = make_plan(N, M, m, dtype)

@@ -130,8 +130,13 @@ typedef struct {
  * Sec. 3.1, Table 3.1), M >= 1 nodes, FFT lengths n[0..d-1] and window size m.
  *   N      [host] d entries.
  *   n      [host] d entries, or NULL for n_t = 2^(ceil(log2 N_t)+1) (Sec. 2 and Sec. 3.1).
- *          Each n_t must be even and > N_t (Sec. 3.1); this library needs n_t to be a
- *          power of two no larger than 4096 (else NFFT_ERR_UNSUPPORTED).
+ *          Each n_t must be even and > N_t (Sec. 3.1) and at most 4096, the longest FFT
+ *          line one workgroup holds (else NFFT_ERR_UNSUPPORTED).  Any even length is
+ *          accepted (the n-sweeps of Sec. 4.3.1 use 514, 614, 716, 820, 130, 154): lengths
+ *          that are not powers of two run mixed-radix FFT passes whose odd prime factors
+ *          are direct sums (cost L p per line for a factor p), so powers of two are fastest.
+ *          Near n_t = N_t the deconvolution factors span many orders of magnitude and the
+ *          rounding of any evaluation is amplified accordingly (Fig. 4.1(a), 4.2(a)).
  *   m      window size >= 1 with 2m+2 <= n_t (m << n_t, Sec. 2 eq. (2.10)); 0 selects the
  *          default m = 8 (Sec. 3.1).  Values up to 12 are supported when the window
  *          tile fits the LDS of one workgroup (else NFFT_ERR_UNSUPPORTED).

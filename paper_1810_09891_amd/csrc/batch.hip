@@ -52,6 +52,7 @@ struct Group {
     size_t lds_interp = 0, lds_spread = 0;
     bool cols = false;  // every plan's 2-D spreading runs in registers
     bool own = false;   // every plan's 3-D spreading runs by output tiles (one launch per plan)
+    bool mix = false;   // the plans' grids are not all powers of two (mixed-radix FFT passes)
     int64_t chunk_bound = 0, fold_items = 0;
     std::vector<PlanDev> table;
 };
@@ -186,7 +187,7 @@ int run_fft(nfft_batch_s *b, const Group &G, const BatchPtrs &ptrs, bool forward
     for (int q = 0; q < G.d; ++q) {
         const int64_t items = forward ? G.items_fwd[q] : G.items_adj[q];
         const int blocks = blocks_for(b, G.params[forward ? kKFwd : kKAdj], items);
-        BCHECK(launch_fft_batch(table_of(b, G), count, q, forward, ptrs, G.dbl,
+        BCHECK(launch_fft_batch(table_of(b, G), count, q, forward, ptrs, G.dbl, G.mix,
                                 forward ? G.vpt_fwd[q] : G.vpt_adj[q], blocks,
                                 forward ? G.lds_fwd[q] : G.lds_adj[q], s));
     }
@@ -446,9 +447,12 @@ int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const 
     if (tune_cache)
         b->cache = tune_cache;
     // group by kernel template parameters, largest M first, at most kMaxBatch per launch
+    // (the last key holds the output-tile flag and, in bit 1, a grid that is not a power of two)
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by_kind;
     for (int i = 0; i < count; ++i)
-        by_kind[std::make_tuple(plans[i]->d, plans[i]->WM, plans[i]->dbl ? 1 : 0, plans[i]->geom.own)].push_back(i);
+        by_kind[std::make_tuple(plans[i]->d, plans[i]->WM, plans[i]->dbl ? 1 : 0,
+                                plans[i]->geom.own + (plans[i]->geom.p2 ? 0 : 2))]
+            .push_back(i);
     for (auto &kv : by_kind) {
         std::vector<int> v = kv.second;
         std::stable_sort(v.begin(), v.end(), [&](int a, int c) { return plans[a]->M > plans[c]->M; });
@@ -457,7 +461,8 @@ int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const 
             G.d = std::get<0>(kv.first);
             G.WM = std::get<1>(kv.first);
             G.dbl = std::get<2>(kv.first) != 0;
-            G.own = std::get<3>(kv.first) != 0;
+            G.own = (std::get<3>(kv.first) & 1) != 0;
+            G.mix = (std::get<3>(kv.first) & 2) != 0;
             G.idx.assign(v.begin() + (long)s0, v.begin() + (long)std::min(v.size(), s0 + kMaxBatch));
             b->groups.push_back(G);
         }

@@ -140,6 +140,117 @@ __device__ __forceinline__ void fft_stage(const Cplx<T> *src, Cplx<T> *dst_buf, 
     __syncthreads();
 }
 
+// The same radix-R stage (R = 2, 4, 8) for a line length L that is not a power of two
+// (L = 2^a times odd factors): positions and twiddle steps by division instead of shifts.
+template <typename T, int VPT, int SIGN, int R>
+__device__ __forceinline__ void fft_stage_mixed(const Cplx<T> *src, Cplx<T> *dst_buf, int L, int nl, int pitch, int Ns,
+                                                const Cplx<T> *tw /* in LDS */)
+{
+    using C = Cplx<T>;
+    constexpr int J = VPT >= R ? VPT / R : 1;
+    const int LR = L / R;  // jobs per line
+    const int jobs = nl * LR;
+    const int twStep = LR / Ns;  // L / (Ns R)
+    C v[J][R];
+    int pos[J], lin[J];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int b = threadIdx.x + q * kBlock;
+        lin[q] = -1;
+        if (b < jobs) {
+            const int line = b / LR;
+            const int j = b - line * LR;
+            const C *row = src + line * pitch;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[q][r] = row[skew(j + r * LR)];
+            const int jh = j / Ns;
+            const int jm = j - jh * Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C w = tw[jm * r * twStep];
+                if (SIGN > 0)
+                    w.y = -w.y;
+                v[q][r] = cmul(v[q][r], w);
+            }
+            dftR<C, SIGN, R>(v[q]);
+            pos[q] = jh * Ns * R + jm;
+            lin[q] = line;
+        }
+    }
+    if (src == dst_buf)  // in place: every read is done before the first write (uniform)
+        __syncthreads();
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        if (lin[q] >= 0) {
+            C *dst = dst_buf + lin[q] * pitch;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                dst[skew(pos[q] + r * Ns)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// A Stockham stage of odd radix p (any odd factor of L) as direct p-point sums.  Output
+// (j, k) of a line, j < L/p, k < p, is sum_r x[j + r L/p] w^{r e} with w = e^{SIGN 2 pi i / L}
+// and e = (j mod Ns) L / (Ns p) + k L / p < L: the stage twiddle and the p-point DFT kernel
+// combined into one table index r e mod L.  It is written to (j / Ns) Ns p + (j mod Ns) + k Ns.
+// A thread computes VPT outputs (VPT kBlock >= nl L), all before the first write.
+template <typename T, int VPT, int SIGN>
+__device__ __forceinline__ void fft_stage_odd(const Cplx<T> *src, Cplx<T> *dst_buf, int L, int nl, int pitch, int Ns,
+                                              int p, const Cplx<T> *tw /* in LDS */)
+{
+    using C = Cplx<T>;
+    const int Lp = L / p;
+    const int twStep = Lp / Ns;  // L / (Ns p)
+    const int outs = nl * L;
+    auto split = [&](int b, int &line, int &j, int &k) {
+        line = b / L;
+        const int rem = b - line * L;
+        k = rem / Lp;
+        j = rem - k * Lp;
+    };
+    C acc[VPT];
+    int lb[VPT], jj[VPT], e[VPT], ex[VPT];
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+        int line, j, k;
+        split(min((int)threadIdx.x + q * kBlock, outs - 1), line, j, k);
+        lb[q] = line * pitch;
+        jj[q] = j;
+        e[q] = (j % Ns) * twStep + k * Lp;
+        ex[q] = 0;
+        acc[q] = C{T(0), T(0)};
+    }
+    for (int r = 0; r < p; ++r) {
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const C x = src[lb[q] + skew(jj[q] + r * Lp)];
+            C w = tw[ex[q]];
+            if (SIGN > 0)
+                w.y = -w.y;
+            const C t = cmul(x, w);
+            acc[q].x += t.x;
+            acc[q].y += t.y;
+            ex[q] += e[q];
+            ex[q] -= ex[q] >= L ? L : 0;
+        }
+    }
+    __syncthreads();  // every read is done before the first write (in place or not)
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+        const int b = (int)threadIdx.x + q * kBlock;
+        if (b < outs) {
+            int line, j, k;
+            split(b, line, j, k);
+            const int jh = j / Ns;
+            dst_buf[line * pitch + skew(jh * Ns * p + (j - jh * Ns) + k * Ns)] = acc[q];
+        }
+    }
+    __syncthreads();
+}
+
 // Position of centred coefficient index p (k = p - N/2) on a line of length n.
 __device__ __forceinline__ int coef_to_pos(int p, int N, int n) { return p < N / 2 ? p - N / 2 + n : p - N / 2; }
 // Inverse: centred index of line position i, or -1 when k = i (mod n) is not in I_N.
@@ -208,8 +319,11 @@ __device__ __forceinline__ void line_info(const FftPass &p, int g, int c, int64_
 constexpr int kMaxLines = 256;
 
 // One line group g of a pass: load (with the deconvolution when in_mode == 0), transform
-// in LDS, store (with the deconvolution when out_mode == 2).
-template <typename T, int VPT, int SIGN>
+// in LDS, store (with the deconvolution when out_mode == 2).  MIX: the line length need not
+// be a power of two (radix 8/4/2 stages by division, then one direct stage per odd prime
+// factor); this is a separate instantiation so that the power-of-two passes keep their
+// register budget.
+template <typename T, int VPT, int SIGN, bool MIX>
 __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr, void *fout_ptr, int g,
                                           Cplx<T> *lds, int64_t *s_gbase, int *s_cbase, double *s_fac)
 {
@@ -259,8 +373,13 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     constexpr int SUB = VPT < 8 ? VPT : 8;
     auto line_pos = [&](int idx, int &c, int &i) {
         if (p.rows) {
-            c = idx >> lgL;
-            i = idx & (L - 1);
+            if constexpr (MIX) {
+                c = idx / L;
+                i = idx - c * L;
+            } else {
+                c = idx >> lgL;
+                i = idx & (L - 1);
+            }
         } else {
             c = idx & (nl - 1);
             i = idx >> lgnl;
@@ -316,22 +435,55 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     }
     __syncthreads();
 
-    // ---------------- transform: radix 8 stages, then one radix 4 or 2 stage
-    int lgNs = 0;
+    // ---------------- transform: radix 8 stages, then one radix 4 or 2 stage (and, for
+    // other lengths, one direct stage per odd prime factor, smallest first)
     C *cur = buf_a, *nxt = buf_b;
-    while (lgL - lgNs >= 3) {
-        fft_stage<T, VPT, SIGN, 8>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
-        lgNs += 3;
+    auto flip = [&]() {
         C *t2 = cur;
         cur = nxt;
         nxt = t2;
-    }
-    if (lgL - lgNs == 2) {
-        fft_stage<T, VPT, SIGN, 4>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
-        cur = nxt;
-    } else if (lgL - lgNs == 1) {
-        fft_stage<T, VPT, SIGN, 2>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
-        cur = nxt;
+    };
+    if constexpr (MIX) {
+        int Ns = 1, rem = L;
+        while (rem % 8 == 0) {
+            fft_stage_mixed<T, VPT, SIGN, 8>(cur, nxt, L, nl, pitch, Ns, tw);
+            Ns *= 8;
+            rem /= 8;
+            flip();
+        }
+        if (rem % 4 == 0) {
+            fft_stage_mixed<T, VPT, SIGN, 4>(cur, nxt, L, nl, pitch, Ns, tw);
+            Ns *= 4;
+            rem /= 4;
+            flip();
+        } else if (rem % 2 == 0) {
+            fft_stage_mixed<T, VPT, SIGN, 2>(cur, nxt, L, nl, pitch, Ns, tw);
+            Ns *= 2;
+            rem /= 2;
+            flip();
+        }
+        for (int f = 3; rem > 1; f += 2) {
+            while (rem % f == 0) {
+                fft_stage_odd<T, VPT, SIGN>(cur, nxt, L, nl, pitch, Ns, f, tw);
+                Ns *= f;
+                rem /= f;
+                flip();
+            }
+        }
+    } else {
+        int lgNs = 0;
+        while (lgL - lgNs >= 3) {
+            fft_stage<T, VPT, SIGN, 8>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
+            lgNs += 3;
+            flip();
+        }
+        if (lgL - lgNs == 2) {
+            fft_stage<T, VPT, SIGN, 4>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
+            flip();
+        } else if (lgL - lgNs == 1) {
+            fft_stage<T, VPT, SIGN, 2>(cur, nxt, L, lgL, nl, pitch, lgNs, tw);
+            flip();
+        }
     }
 
     // ---------------- store
@@ -379,7 +531,7 @@ __device__ __forceinline__ void fft_group(const FftPass &p, const void *fin_ptr,
     __syncthreads();
 }
 
-template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass p)
+template <typename T, int VPT, int SIGN, bool MIX> __global__ __launch_bounds__(kBlock) void k_fft_pass(FftPass p)
 {
     using C = Cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -388,11 +540,11 @@ template <typename T, int VPT, int SIGN> __global__ __launch_bounds__(kBlock) vo
     __shared__ double s_fac[kMaxLines];
     C *lds = reinterpret_cast<C *>(smem_raw);
     for (int g = xcd_local_id(blockIdx.x, gridDim.x); g < (int)p.ngroups; g += gridDim.x)
-        fft_group<T, VPT, SIGN>(p, p.fin, p.fout, g, lds, s_gbase, s_cbase, s_fac);
+        fft_group<T, VPT, SIGN, MIX>(p, p.fin, p.fout, g, lds, s_gbase, s_cbase, s_fac);
 }
 
 // Pass `pass` (forward or adjoint) of every plan of a batch in one launch.
-template <typename T, int VPT, int SIGN>
+template <typename T, int VPT, int SIGN, bool MIX>
 __global__ __launch_bounds__(kBlock) void k_fft_batch(const PlanDev *__restrict__ plans, int count, int pass,
                                                       BatchPtrs ptrs)
 {
@@ -419,17 +571,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_batch(const PlanDev *__restrict_
         // (last adjoint pass)
         const void *fin = (SIGN < 0 && pass == 0) ? ptrs.in[pi] : fp.fin;
         void *fout = (SIGN > 0 && pass == pd.nfft - 1) ? ptrs.out[pi] : fp.fout;
-        fft_group<T, VPT, SIGN>(fp, fin, fout, it - s_prefix[pi], lds, s_gbase, s_cbase, s_fac);
+        fft_group<T, VPT, SIGN, MIX>(fp, fin, fout, it - s_prefix[pi], lds, s_gbase, s_cbase, s_fac);
     }
 }
 
-template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int blocks, hipStream_t s)
+template <typename T, int SIGN, bool MIX> hipError_t launch_typed(const FftPass &p, int blocks, hipStream_t s)
 {
     size_t lds = fft_lds_bytes(p, sizeof(Cplx<T>));
     dim3 grid(blocks), block(kBlock);
 #define NFFT_FFT_CALL(V)                                                                               \
     {                                                                                                  \
-        auto kf = k_fft_pass<T, V, SIGN>;                                                              \
+        auto kf = k_fft_pass<T, V, SIGN, MIX>;                                                         \
         (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         hipLaunchKernelGGL(kf, grid, block, lds, s, p);                                                \
     }
@@ -439,7 +591,12 @@ template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int bl
     case 4: NFFT_FFT_CALL(4); break;
     case 8: NFFT_FFT_CALL(8); break;
     case 16: NFFT_FFT_CALL(16); break;
-    case 32: NFFT_FFT_CALL(32); break;
+    case 32:
+        if constexpr (MIX)
+            return hipErrorInvalidValue;  // mixed-radix passes hold at most 4096 points
+        else
+            NFFT_FFT_CALL(32);
+        break;
     default: return hipErrorInvalidValue;
     }
 #undef NFFT_FFT_CALL
@@ -448,14 +605,14 @@ template <typename T, int SIGN> hipError_t launch_typed(const FftPass &p, int bl
 
 }  // namespace
 
-template <typename T, int SIGN>
+template <typename T, int SIGN, bool MIX>
 hipError_t launch_batch_typed(const PlanDev *plans, int count, int pass, const BatchPtrs &ptrs, int vpt, int blocks,
                               size_t lds, hipStream_t s)
 {
     dim3 grid(blocks), block(kBlock);
 #define NFFT_FFT_CALL(V)                                                                               \
     {                                                                                                  \
-        auto kf = k_fft_batch<T, V, SIGN>;                                                             \
+        auto kf = k_fft_batch<T, V, SIGN, MIX>;                                                        \
         (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         hipLaunchKernelGGL(kf, grid, block, lds, s, plans, count, pass, ptrs);                         \
     }
@@ -465,7 +622,12 @@ hipError_t launch_batch_typed(const PlanDev *plans, int count, int pass, const B
     case 4: NFFT_FFT_CALL(4); break;
     case 8: NFFT_FFT_CALL(8); break;
     case 16: NFFT_FFT_CALL(16); break;
-    case 32: NFFT_FFT_CALL(32); break;
+    case 32:
+        if constexpr (MIX)
+            return hipErrorInvalidValue;
+        else
+            NFFT_FFT_CALL(32);
+        break;
     default: return hipErrorInvalidValue;
     }
 #undef NFFT_FFT_CALL
@@ -473,20 +635,32 @@ hipError_t launch_batch_typed(const PlanDev *plans, int count, int pass, const B
 }
 
 hipError_t launch_fft_batch(const PlanDev *plans, int count, int pass, bool forward, const BatchPtrs &ptrs,
-                            bool dbl, int vpt, int blocks, size_t lds, hipStream_t s)
+                            bool dbl, bool mix, int vpt, int blocks, size_t lds, hipStream_t s)
 {
+    if (mix) {
+        if (dbl)
+            return forward ? launch_batch_typed<double, -1, true>(plans, count, pass, ptrs, vpt, blocks, lds, s)
+                           : launch_batch_typed<double, 1, true>(plans, count, pass, ptrs, vpt, blocks, lds, s);
+        return forward ? launch_batch_typed<float, -1, true>(plans, count, pass, ptrs, vpt, blocks, lds, s)
+                       : launch_batch_typed<float, 1, true>(plans, count, pass, ptrs, vpt, blocks, lds, s);
+    }
     if (dbl)
-        return forward ? launch_batch_typed<double, -1>(plans, count, pass, ptrs, vpt, blocks, lds, s)
-                       : launch_batch_typed<double, 1>(plans, count, pass, ptrs, vpt, blocks, lds, s);
-    return forward ? launch_batch_typed<float, -1>(plans, count, pass, ptrs, vpt, blocks, lds, s)
-                   : launch_batch_typed<float, 1>(plans, count, pass, ptrs, vpt, blocks, lds, s);
+        return forward ? launch_batch_typed<double, -1, false>(plans, count, pass, ptrs, vpt, blocks, lds, s)
+                       : launch_batch_typed<double, 1, false>(plans, count, pass, ptrs, vpt, blocks, lds, s);
+    return forward ? launch_batch_typed<float, -1, false>(plans, count, pass, ptrs, vpt, blocks, lds, s)
+                   : launch_batch_typed<float, 1, false>(plans, count, pass, ptrs, vpt, blocks, lds, s);
 }
 
 hipError_t launch_fft_pass(const FftPass &p, bool dbl, int blocks, hipStream_t s)
 {
+    if ((p.L & (p.L - 1)) != 0) {
+        if (dbl)
+            return p.sign < 0 ? launch_typed<double, -1, true>(p, blocks, s) : launch_typed<double, 1, true>(p, blocks, s);
+        return p.sign < 0 ? launch_typed<float, -1, true>(p, blocks, s) : launch_typed<float, 1, true>(p, blocks, s);
+    }
     if (dbl)
-        return p.sign < 0 ? launch_typed<double, -1>(p, blocks, s) : launch_typed<double, 1>(p, blocks, s);
-    return p.sign < 0 ? launch_typed<float, -1>(p, blocks, s) : launch_typed<float, 1>(p, blocks, s);
+        return p.sign < 0 ? launch_typed<double, -1, false>(p, blocks, s) : launch_typed<double, 1, false>(p, blocks, s);
+    return p.sign < 0 ? launch_typed<float, -1, false>(p, blocks, s) : launch_typed<float, 1, false>(p, blocks, s);
 }
 
 }  // namespace nfft

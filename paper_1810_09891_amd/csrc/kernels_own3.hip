@@ -94,7 +94,10 @@ __device__ __forceinline__ int own_meta(const Geom &g, const Nodes &nd, int p, c
     int o[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-        int v = (nd.u[t][p] - g.m - org[t]) & (g.n[t] - 1);
+        // u - m - org lies in (-3n/2, n) since 2m + 2 <= n: two conditional adds reduce it mod n
+        int v = nd.u[t][p] - g.m - org[t];
+        v += v < 0 ? g.n[t] : 0;
+        v += v < 0 ? g.n[t] : 0;
         if (v >= TT[t])
             v -= g.n[t];
         o[t] = v;

@@ -794,10 +794,19 @@ __device__ __forceinline__ void fold_cell(const Geom &g, const Nodes &nd, const 
     int l[kMaxDim] = {0, 0, 0};
     {
         int64_t rq = q;
+        if (g.p2) {
 #pragma unroll
-        for (int t = D - 1; t >= 0; --t) {
-            l[t] = (int)(rq & (g.n[t] - 1));
-            rq >>= (31 - __clz(g.n[t]));
+            for (int t = D - 1; t >= 0; --t) {
+                l[t] = (int)(rq & (g.n[t] - 1));
+                rq >>= (31 - __clz(g.n[t]));
+            }
+        } else {
+#pragma unroll
+            for (int t = D - 1; t >= 0; --t) {
+                const int64_t qt = rq / g.n[t];
+                l[t] = (int)(rq - qt * g.n[t]);
+                rq = qt;
+            }
         }
     }
     if (g.fold2) {

@@ -116,7 +116,7 @@ int fold_max_pairs(const Geom &g, int t);
 struct PlanDev;
 struct BatchPtrs;
 hipError_t launch_fft_batch(const PlanDev *plans, int count, int pass, bool forward, const BatchPtrs &ptrs,
-                            bool dbl, int vpt, int blocks, size_t lds, hipStream_t s);
+                            bool dbl, bool mix, int vpt, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_interp_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,
                                bool dbl, int WMv, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_spread_batch(const PlanDev *plans, int count, const BatchPtrs &ptrs, int *queue, int d,

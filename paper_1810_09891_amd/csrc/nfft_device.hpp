@@ -262,7 +262,8 @@ struct Geom {
     int m;
     int W;             // 2m+2
     int WM;            // compiled stencil width (>= W)
-    int n[kMaxDim];    // grid lengths (1 for unused dimensions)
+    int n[kMaxDim];    // grid lengths (1 for unused dimensions); even, not necessarily powers of two
+    int p2;            // 1 when every n_t is a power of two (indices wrap with a mask)
     int lgB[kMaxDim];  // log2 of the bin edge per dimension
     int nb[kMaxDim];   // bins per dimension
     int P[kMaxDim];    // padded tile edge B + WM - 1

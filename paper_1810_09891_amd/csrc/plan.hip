@@ -27,6 +27,15 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// FFT points per thread of a line group of `pts` points: a power of two >= pts / 256
+int vpt_of(int pts)
+{
+    int v = 1;
+    while (v * 256 < pts)
+        v *= 2;
+    return v;
+}
+
 int ilog2(int64_t v)
 {
     int r = 0;
@@ -48,8 +57,10 @@ static int choose_bins(nfft_plan_s *p)
     int B[kMaxDim] = {1, 1, 1};
     // starting edges: long tiles in 1-D, 32x32 in 2-D, 8x8x8 in 3-D
     const int start = d == 1 ? 512 : d == 2 ? 32 : 8;
+    // (bin edges are powers of two; with a grid length that is not one, the last bin of a
+    // dimension holds the remaining n_t mod B_t cells)
     for (int t = 0; t < d; ++t)
-        B[t] = (int)std::min<int64_t>(start, p->n[t]);
+        B[t] = 1 << ilog2(std::min<int64_t>(start, p->n[t]));
     // complex128 2-D plans with even m: 16-row bins, the height at which the spreading kernel
     // that keeps tile columns in registers fits its accumulators
     if (d == 2 && p->dbl && 2 * p->m + 2 == p->WM)
@@ -98,7 +109,7 @@ static int choose_bins(nfft_plan_s *p)
     for (int t = 0; t < kMaxDim; ++t) {
         if (t < d) {
             g.lgB[t] = ilog2(B[t]);
-            g.nb[t] = (int)(p->n[t] / B[t]);
+            g.nb[t] = (int)((p->n[t] + B[t] - 1) / B[t]);  // the last bin may be partial
             g.P[t] = B[t] + p->WM - 1;
         } else {
             g.lgB[t] = 0;
@@ -217,8 +228,11 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
         fp.in_mode = 2;
         fp.out_mode = first_or_last ? 2 : 1;
     }
-    const int maxPts = p->dbl ? 4096 : 8192;
     const int L = fp.L;
+    const bool mix = (L & (L - 1)) != 0;
+    // points per workgroup: mixed-radix passes (L not a power of two) hold at most 4096, so
+    // that their direct odd-radix stages keep 16 outputs per thread in registers
+    const int maxPts = (p->dbl || mix) ? 4096 : 8192;
     // Aim for at least 512 line groups (two per compute unit) before packing more lines
     // into a workgroup; column passes keep >= 2 adjacent columns per row segment.
     const int64_t target = 512;
@@ -242,6 +256,13 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
         const int inner = (int)p->n[d - 1];
         nl = std::min<int>(inner, std::max(1, maxPts / L));
         nl = std::min(nl, std::min(256, p->dbl ? 8 : 16));
+        // a power of two that divides n_{d-1} (n_{d-1} is even, so 2 always does)
+        {
+            int v = 1;
+            while (v * 2 <= nl && inner % (v * 2) == 0)
+                v *= 2;
+            nl = v;
+        }
         while (nl > 2 && outer * (inner / nl) < target)
             nl /= 2;
         fp.ncb = inner / nl;
@@ -250,8 +271,7 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
     fp.nl = nl;
     // line pitch in LDS: L elements plus one skew element per 32 (and one more for columns)
     fp.pitch = L + (L >> 5) + (fp.rows ? 0 : 1);
-    int pts = nl * L;
-    fp.vpt = std::max(1, pts / 256);
+    fp.vpt = vpt_of(nl * L);
     fft_choose_buffers(fp, p->dbl ? 16 : 8);
 }
 
@@ -262,7 +282,8 @@ bool plan_repack_pass(const nfft_plan_s *p, const FftPass &tmpl, int factor, Fft
     out = tmpl;
     if (factor == 1)
         return true;
-    const int maxPts = p->dbl ? 4096 : 8192;
+    const bool mix = (tmpl.L & (tmpl.L - 1)) != 0;
+    const int maxPts = (p->dbl || mix) ? 4096 : 8192;
     int nl = tmpl.nl * factor;
     if (nl < 1 || nl > 256 || (int64_t)nl * tmpl.L > maxPts)
         return false;
@@ -272,14 +293,14 @@ bool plan_repack_pass(const nfft_plan_s *p, const FftPass &tmpl, int factor, Fft
         out.ngroups = (tmpl.nrows + nl - 1) / nl;
     } else {
         const int inner = (int)p->n[p->d - 1];
-        if (nl > inner || nl < 2)
+        if (nl > inner || nl < 2 || inner % nl != 0)
             return false;
         const int64_t outer = tmpl.ngroups / tmpl.ncb;
         out.ncb = inner / nl;
         out.ngroups = outer * out.ncb;
     }
     out.nl = nl;
-    out.vpt = std::max(1, nl * tmpl.L / 256);
+    out.vpt = vpt_of(nl * tmpl.L);
     fft_choose_buffers(out, p->dbl ? 16 : 8);
     return true;
 }
@@ -471,7 +492,7 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
             return NFFT_ERR_ARG;
     }
     for (int t = 0; t < d; ++t)
-        if (!is_pow2(nn[t]) || nn[t] > kMaxN)
+        if (nn[t] > kMaxN)
             return NFFT_ERR_UNSUPPORTED;
     if (m > kMaxM)
         return NFFT_ERR_UNSUPPORTED;
@@ -496,8 +517,11 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
     g.W = 2 * m + 2;
     g.WM = wm_bucket(m);
     p->WM = g.WM;
-    for (int t = 0; t < kMaxDim; ++t)
+    g.p2 = 1;
+    for (int t = 0; t < kMaxDim; ++t) {
         g.n[t] = (int)p->n[t];
+        g.p2 = g.p2 && is_pow2(p->n[t]);
+    }
     int st = choose_bins(p);
     if (st != NFFT_OK) {
         delete p;

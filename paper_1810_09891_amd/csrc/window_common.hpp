@@ -37,9 +37,11 @@ template <typename T> __device__ __forceinline__ Cplx<T> lds_entry(const Cplx<T>
 // A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < K: all K loads
 // (entries past the tile read entry 0) are issued before the first LDS store, so their
 // latencies overlap.  K = 12 for complex64 covers a 2-D tile of up to 3072 entries (m = 8
-// and 32 x 32 bins: 49 x 49) in one round of loads.
-template <typename T, int D>
-__device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
+// and 32 x 32 bins: 49 x 49) in one round of loads.  Grid indices wrap with a mask when
+// every n_t is a power of two (P2), else with a remainder; a tile may wrap more than once
+// when it is longer than the grid.
+template <typename T, int D, bool P2>
+__device__ __forceinline__ void stage_tile_w(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
 {
     using C = Cplx<T>;
     constexpr int K = sizeof(T) == 4 ? 12 : 8;
@@ -48,23 +50,24 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const C
     for (int t = 0; t < D; ++t)
         o[t] = (bc[t] << g.lgB[t]) - g.m + g.n[t];  // + n keeps it non-negative
     const int Ptot = g.Ptot;
+    auto wrap = [&](int i, int t) -> int { return P2 ? (i & (g.n[t] - 1)) : i % g.n[t]; };
     auto src = [&](int idx) -> int64_t {
         if constexpr (D == 1) {
-            return (o[0] + idx) & (g.n[0] - 1);
+            return wrap(o[0] + idx, 0);
         } else if constexpr (D == 2) {
             const int i0 = idx / g.P[1];
             const int i1 = idx - i0 * g.P[1];
-            const int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
-            return r0 * g.n[1] + ((o[1] + i1) & (g.n[1] - 1));
+            const int64_t r0 = wrap(o[0] + i0, 0);
+            return r0 * g.n[1] + wrap(o[1] + i1, 1);
         } else {
             const int P12 = g.P[1] * g.P[2];
             const int i0 = idx / P12;
             const int rem = idx - i0 * P12;
             const int i1 = rem / g.P[2];
             const int i2 = rem - i1 * g.P[2];
-            const int64_t r0 = (o[0] + i0) & (g.n[0] - 1);
-            const int64_t r1 = (o[1] + i1) & (g.n[1] - 1);
-            return (r0 * g.n[1] + r1) * g.n[2] + ((o[2] + i2) & (g.n[2] - 1));
+            const int64_t r0 = wrap(o[0] + i0, 0);
+            const int64_t r1 = wrap(o[1] + i1, 1);
+            return (r0 * g.n[1] + r1) * g.n[2] + wrap(o[2] + i2, 2);
         }
     };
     for (int base = 0; base < Ptot; base += K * kBlock) {
@@ -81,6 +84,15 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const C
                 tile[idx] = v[k];
         }
     }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
+{
+    if (g.p2)
+        stage_tile_w<T, D, true>(g, bc, grid, tile);
+    else
+        stage_tile_w<T, D, false>(g, bc, grid, tile);
 }
 
 // Window factors of one dimension at all WM stencil points (zero beyond 2m+2).

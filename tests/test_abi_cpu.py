@@ -56,8 +56,12 @@ def test_status_strings(lib):
         ((8,), 0, None, 2, ARG),  # M < 1
         ((8,), 10, (8,), 2, ARG),  # n <= N
         ((8,), 10, (11,), 2, ARG),  # odd n
-        ((8,), 10, (12,), 2, UNSUP),  # even, > N, not a power of two
-        ((8,), 10, (8192,), 2, UNSUP),  # longer than one workgroup line
+        ((8,), 10, (12,), 2, OK),  # even, > N, not a power of two (mixed-radix passes)
+        ((512,), 1024, (514,), 8, OK),  # n = 2 * 257 (Fig. 4.1's shortest grid)
+        ((128, 128), 100, (130, 154), 8, OK),
+        ((2000,), 10, (4094,), 6, OK),  # longest line with an odd factor
+        ((8,), 10, (4098,), 2, UNSUP),  # longer than one workgroup line
+        ((8,), 10, (8192,), 2, UNSUP),
         ((8,), 10, (64,), 13, UNSUP),  # m beyond the compiled stencils
         ((8,), 10, (16,), -1, ARG),
         ((8, 8, 8, 8), 10, None, 2, ARG),  # d > 3

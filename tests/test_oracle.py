@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 import scipy.special
 
+import error_scale as ES
 from oracle import oracle as O
 from paper_1810_09891_amd import workloads as W
 
@@ -734,3 +735,46 @@ def test_nndft_real_frequencies_match_extended_precision():
             ph = sum(mp.mpf(float(v[k, t])) * mp.mpf(float(x[j, t])) for t in range(d))
             s += mp.mpc(float(a[0].real), float(a[0].imag)) * mp.expjpi(2 * ph)
         assert abs(complex(s) - h[k]) < 1e-12
+
+
+# --------------------------------------------------------------------------- error scale near n = N
+
+
+@pytest.mark.parametrize("d,nv", [(1, 514), (1, 716), (2, 130), (2, 256)])
+def test_componentwise_error_scale_of_two_fp64_evaluations(d, nv):
+    """The componentwise bar used for grids close to N (Fig. 4.1(a) and 4.2(a) lengths):
+    the oracle, whose FFT is the direct DFT at these lengths, and the same steps with numpy's
+    FFT differ by up to 2e-9 (n = 514) or 0.1 (d = 2, n = 130 adjoint) in relative l2, but
+    by at most 1e-13 in the weighted relative l2 and element-wise measures."""
+    w = W.paper_workload(d)
+    N, M, x, fh = w["N"], w["M"], w["x"], w["fhat"]
+    n = (nv,) * d
+    r = np.random.default_rng(nv)
+    f_in = r.standard_normal(M) + 1j * r.standard_normal(M)
+    f_np = O.nfft_interp(x, np.fft.fftn(O.nfft_deconv(fh, n, 8)), N, 8)
+    gs = O.nfft_spread(x, f_in, N, n, 8)
+    h_np = O.nfft_deconv_adj(np.fft.ifftn(gs) * gs.size, N, 8)
+    assert max(ES.trafo_errors(x, fh, N, n, 8, f_np)) < 1e-13
+    assert max(ES.adjoint_errors(x, f_in, N, n, 8, h_np)) < 1e-13
+
+
+def test_componentwise_error_scale_is_not_vacuous_at_n_2N():
+    """At n = 2N (flat deconvolution factors) a planted error of 1e-11 of the largest output
+    in one transform value, or of the largest coefficient in one adjoint coefficient, exceeds
+    the 1e-12 bar."""
+    w = W.paper_workload(1)
+    N, M, x, fh = w["N"], w["M"], w["x"], w["fhat"]
+    n = (1024,)
+    f = O.nfft_trafo(x, fh, n, 8)
+    f_bad = f.copy()
+    f_bad[17] += 1e-11 * np.max(np.abs(f))
+    assert max(ES.trafo_errors(x, fh, N, n, 8, f, ref=f)) == 0.0
+    assert ES.trafo_errors(x, fh, N, n, 8, f_bad, ref=f)[1] > 1e-12
+    r = np.random.default_rng(3)
+    f_in = r.standard_normal(M) + 1j * r.standard_normal(M)
+    h = O.nfft_adjoint(x, f_in, N, n, 8)
+    h_bad = h.copy()
+    h_bad[100] += 1e-11 * np.max(np.abs(h))
+    assert ES.adjoint_errors(x, f_in, N, n, 8, h_bad, ref=h)[1] > 1e-12
+    # and a planted relative error of 1e-11 over all coefficients exceeds the l2 form
+    assert ES.adjoint_errors(x, f_in, N, n, 8, h * (1 + 1e-11), ref=h)[0] > 1e-12

@@ -11,6 +11,8 @@
 // its (2m+2)^d stencil from LDS as nested tensor-product sums of the precomputed window
 // factors (the structure the PRE_PSI flag of Table 3.2 exploits).  Spreading, the other
 // window kernel, is in kernels_spread.hip.
+#include <algorithm>
+
 #include "batch_desc.hpp"
 #include "window_common.hpp"
 
@@ -284,6 +286,281 @@ __global__ __launch_bounds__(kBlock) void k_interp_batch(const PlanDev *__restri
     queue_done(queue);
 }
 
+// ------------------------------------------------------------------ 3-D interpolation by lane groups
+//
+// In 3-D a node's stencil has (2m+2)^3 points, and one thread per node reads its stencil
+// rows at scattered tile offsets: the LDS reads of a wave conflict on banks (three conflict
+// cycles per LDS cycle measured in complex128).  Here G lanes share a node (G = 16 for
+// stencils of at most 16 points per dimension, else 32): lane s takes column s of the
+// innermost dimension and sums psi_0[s0] sum_{s1} psi_1[s1] g[u0+s0][u1+s1][u2+s] over the
+// two outer dimensions, one tile entry per (s0, s1), so the lanes of a group read one
+// contiguous row; the column sums are multiplied by psi_2[s] and added over the group by a
+// butterfly (a fixed order).  The next round's node data is loaded while the current round
+// is summed.
+//
+// A workgroup has eight waves.  Waves 0-3 interpolate the nodes of the current work item;
+// waves 4-7 meanwhile load the padded tile of their next work item into registers (up to
+// i3_keep entries per thread) and, after a barrier, write it to LDS, so that the tile loads
+// of one item overlap the sums of the previous one.  Workgroups are persistent.
+constexpr int kI3Threads = 512;
+constexpr int kI3Half = 256;
+// tile entries a loading thread keeps in registers (complex64 stays within 128 registers,
+// so that two workgroups of eight waves share a compute unit)
+template <typename T> constexpr int i3_keep() { return sizeof(T) == 8 ? 24 : 16; }
+
+// Data-parallel-primitive lane moves within rows of 16 lanes (no LDS): quad permutations,
+// the half-row mirror (lane i <-> 7 - i within each 8) and the row mirror (i <-> 15 - i).
+template <int CTRL> __device__ __forceinline__ float dpp_move(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over each row of 16 lanes, every lane receiving its row's sum: pairs, quads, eights,
+// then the two halves of the row (a fixed order).
+template <typename T> __device__ __forceinline__ T row16_sum(T v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return v;
+}
+
+template <typename T, int WM>
+__device__ __forceinline__ void interp3_item(const Geom &g, const Nodes &nd, Cplx<T> *__restrict__ f, int c,
+                                             const Cplx<T> *tile)
+{
+    using C = Cplx<T>;
+    constexpr int G = WM <= 16 ? 16 : 32;
+    constexpr int NG = kI3Half / G;  // nodes per round
+    const T *psi = static_cast<const T *>(nd.psi);
+    const int tid = threadIdx.x;  // < kI3Half
+    const int grp = tid / G;
+    const int s2 = tid & (G - 1);
+    const int W = g.W;
+    const int dW = 3 * W;
+    const int first = nd.chunk_first[c];
+    const int len = nd.chunk_len[c];
+    const int P1 = g.P[1], P2 = g.P[2];
+    const int s2c = s2 < WM ? s2 : WM - 1;  // lanes past the stencil read a valid entry, weight 0
+    const int s2w = s2 < W ? s2 : W - 1;
+    struct NodeData {
+        int off;  // tile offset of the stencil origin plus the lane's column
+        T w0[WM], w1[WM];  // factors of dimensions 0 and 1 (zero past W)
+        T w2;              // factor of the lane's column (zero past W)
+    };
+    auto load = [&](int i, NodeData &q) {
+        const int node = first + (i < len ? i : len - 1);
+        const int u0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
+        const int u1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
+        const int u2 = nd.u[2][node] & ((1 << g.lgB[2]) - 1);
+        q.off = (u0 * P1 + u1) * P2 + u2 + s2c;
+        // aligned pairs (W and the record length 3W are even; reads stay inside the record)
+        const Pair<T> *p2 = reinterpret_cast<const Pair<T> *>(psi + (int64_t)node * dW);
+#pragma unroll
+        for (int s = 0; s < WM / 2; ++s) {
+            const Pair<T> a = p2[s], b = p2[W / 2 + s];
+            q.w0[2 * s] = 2 * s < W ? a.x : T(0);
+            q.w0[2 * s + 1] = 2 * s + 1 < W ? a.y : T(0);
+            q.w1[2 * s] = 2 * s < W ? b.x : T(0);
+            q.w1[2 * s + 1] = 2 * s + 1 < W ? b.y : T(0);
+        }
+        const T w2 = psi[(int64_t)node * dW + 2 * W + s2w];
+        q.w2 = s2 < W ? w2 : T(0);
+    };
+    NodeData cur, nxt;
+    if (len > 0)
+        load(grp, cur);
+    for (int base = 0; base < len; base += NG) {
+        const int i = base + grp;
+        if (base + NG < len)
+            load(i + NG, nxt);
+        // Planes are read one ahead of their sums where the registers allow: the WM reads of
+        // plane s0 + 1 are issued before plane s0 is summed.  Planes past W carry weight zero
+        // and stay inside the tile.
+        constexpr bool kAhead = sizeof(T) == 8 ? WM <= 14 : WM <= 10;
+        const C *p = tile + cur.off;
+        const int PP = P1 * P2;
+        C row[WM];
+        if constexpr (kAhead) {
+#pragma unroll
+            for (int s1 = 0; s1 < WM; ++s1)
+                row[s1] = p[s1 * P2];
+        }
+        T ax = 0, ay = 0;
+#pragma unroll
+        for (int s0 = 0; s0 < WM; ++s0) {
+            C ahead[WM];
+            if (kAhead && s0 + 1 < WM) {
+#pragma unroll
+                for (int s1 = 0; s1 < WM; ++s1)
+                    ahead[s1] = p[(s0 + 1) * PP + s1 * P2];
+            }
+            if constexpr (!kAhead) {
+#pragma unroll
+                for (int s1 = 0; s1 < WM; ++s1)
+                    row[s1] = p[s0 * PP + s1 * P2];
+            }
+            T rx = 0, ry = 0;
+#pragma unroll
+            for (int s1 = 0; s1 < WM; ++s1) {
+                rx = fma(cur.w1[s1], row[s1].x, rx);
+                ry = fma(cur.w1[s1], row[s1].y, ry);
+            }
+            ax = fma(cur.w0[s0], rx, ax);
+            ay = fma(cur.w0[s0], ry, ay);
+            if (kAhead && s0 + 1 < WM) {
+#pragma unroll
+                for (int s1 = 0; s1 < WM; ++s1)
+                    row[s1] = ahead[s1];
+            }
+        }
+        ax *= cur.w2;
+        ay *= cur.w2;
+        ax = row16_sum(ax);
+        ay = row16_sum(ay);
+        if constexpr (G == 32) {  // the two rows of a 32-lane group
+            ax += __shfl_xor(ax, 16, 32);
+            ay += __shfl_xor(ay, 16, 32);
+        }
+        if (i < len && s2 == 0)
+            f[nd.perm[first + i]] = C{ax, ay};
+        cur = nxt;
+    }
+}
+
+// Tile entries from `from` on, staged by all threads of the workgroup (eight loads in
+// flight per thread).
+template <typename T, bool P2>
+__device__ __forceinline__ void stage_rest3(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile, int from)
+{
+    using C = Cplx<T>;
+    constexpr int K = 8;
+    const TileMap<3, P2> map(g, bc);
+    const int Ptot = g.Ptot;
+    for (int base = from; base < Ptot; base += K * kI3Threads) {
+        C v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = base + threadIdx.x + k * kI3Threads;
+            v[k] = grid[map.src(g, idx < Ptot ? idx : 0)];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = base + threadIdx.x + k * kI3Threads;
+            if (idx < Ptot)
+                tile[idx] = v[k];
+        }
+    }
+}
+
+// One step of the loading waves: the padded tile of work item cn is loaded into registers
+// (entries ptid + k kI3Half, k < count), the workgroup meets at a barrier (the current item's
+// sums are done with the tile), and the entries are written to LDS, the rest of the tile
+// staged by all threads, and the workgroup meets again.  Grids of fewer than 2^28 cells
+// index the grid with 32-bit offsets; larger ones keep half as many entries.
+template <typename T, bool P2, bool O32>
+__device__ __forceinline__ void loader_step(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ grid,
+                                            Cplx<T> *tile, int cn, int nchunks, int ptid)
+{
+    using C = Cplx<T>;
+    constexpr int K = O32 ? i3_keep<T>() : i3_keep<T>() / 2;
+    T vx[K], vy[K];  // real arrays, so that they are kept in registers
+    int bc[3] = {0, 0, 0};
+    const bool more = cn < nchunks;
+    if (more) {
+        bin_coords<T, 3>(g, nd.chunk_bin[cn], bc);
+        const TileMap<3, P2> map(g, bc);
+        const int Ptot = g.Ptot;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = ptid + k * kI3Half;
+            const int e = idx < Ptot ? idx : 0;
+            const C a = O32 ? grid[map.src32(g, e)] : grid[map.src(g, e)];
+            vx[k] = a.x;
+            vy[k] = a.y;
+        }
+    }
+    __syncthreads();  // the item's sums are done with the tile
+    if (more) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = ptid + k * kI3Half;
+            if (idx < g.Ptot)
+                tile[idx] = C{vx[k], vy[k]};
+        }
+        if (g.Ptot > K * kI3Half)
+            stage_rest3<T, P2>(g, bc, grid, tile, K * kI3Half);
+    }
+    __syncthreads();
+}
+
+template <typename T, int WM>
+__global__ __launch_bounds__(kI3Threads) void k_interp3(Geom g, Nodes nd, const Cplx<T> *__restrict__ grid,
+                                                         Cplx<T> *__restrict__ f)
+{
+    using C = Cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *tile = reinterpret_cast<C *>(smem_raw);
+    const int nchunks = nd.counters[0];
+    const int nwg = min((int)gridDim.x, nchunks);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    const bool loader = threadIdx.x >= kI3Half;  // waves 4-7
+    const int ptid = (int)threadIdx.x - kI3Half;
+    // entries kept per loading thread: i3_keep with 32-bit offsets, half otherwise
+    const bool o32 = (int64_t)g.n[0] * g.n[1] * g.n[2] < ((int64_t)1 << 28);
+    const int keep = (o32 ? i3_keep<T>() : i3_keep<T>() / 2) * kI3Half;
+    int c = xcd_local_id(blockIdx.x, nwg);
+    {
+        int bc[3];
+        bin_coords<T, 3>(g, nd.chunk_bin[c], bc);
+        if (g.p2)
+            stage_rest3<T, true>(g, bc, grid, tile, 0);
+        else
+            stage_rest3<T, false>(g, bc, grid, tile, 0);
+    }
+    __syncthreads();
+    // The two kinds of waves run separate loops with the same barriers, so that the kept
+    // tile and the interpolation registers are never live together.
+    if (loader) {
+        for (; c < nchunks; c += nwg) {
+            if (o32) {
+                if (g.p2)
+                    loader_step<T, true, true>(g, nd, grid, tile, c + nwg, nchunks, ptid);
+                else
+                    loader_step<T, false, true>(g, nd, grid, tile, c + nwg, nchunks, ptid);
+            } else {
+                if (g.p2)
+                    loader_step<T, true, false>(g, nd, grid, tile, c + nwg, nchunks, ptid);
+                else
+                    loader_step<T, false, false>(g, nd, grid, tile, c + nwg, nchunks, ptid);
+            }
+        }
+    } else {
+        for (; c < nchunks; c += nwg) {
+            const int cn = c + nwg;
+            interp3_item<T, WM>(g, nd, f, c, tile);
+            __syncthreads();
+            if (cn < nchunks && g.Ptot > keep) {
+                int bcn[3];
+                bin_coords<T, 3>(g, nd.chunk_bin[cn], bcn);
+                if (g.p2)
+                    stage_rest3<T, true>(g, bcn, grid, tile, keep);
+                else
+                    stage_rest3<T, false>(g, bcn, grid, tile, keep);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <typename T, int D, int WM> constexpr auto pick_interp() { return k_interp_nodes<T, D, WM>; }
 
 template <typename T, int D>
@@ -291,6 +568,31 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
                         hipStream_t s)
 {
     using C = Cplx<T>;
+    // 3-D by lane groups, except complex128 stencils of 22 or more points, whose registers
+    // do not fit eight waves (those take the kernel with one node per thread)
+    if (D == 3 && !(sizeof(T) == 8 && g.WM >= 22)) {
+        // persistent workgroups of eight waves: as many as are resident at once (registers
+        // and LDS), never more than the work items
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+#define CALL3(W_)                                                                                      \
+        {                                                                                              \
+            auto kf = k_interp3<T, W_>;                                                                \
+            (void)hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            int per_cu = 0;                                                                            \
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kf, kI3Threads, lds) != \
+                    hipSuccess || per_cu < 1)                                                          \
+                per_cu = 1;                                                                            \
+            const int wgs = std::max(1, std::min(blocks, cus * per_cu));                               \
+            hipLaunchKernelGGL(kf, dim3(wgs), dim3(kI3Threads), lds, s, g, nd, static_cast<const C *>(grid), \
+                               static_cast<C *>(f));                                                   \
+        }
+        NFFT_WM_SWITCH(g.WM, CALL3)
+#undef CALL3
+        return hipGetLastError();
+    }
 #define CALL(W_)                                                                                       \
     {                                                                                                  \
         auto kf = pick_interp<T, D, W_>();                                                                  \

@@ -33,49 +33,73 @@ template <typename T> __device__ __forceinline__ Cplx<T> lds_entry(const Cplx<T>
     }
 }
 
-// Stage the padded tile of bin `bc` into LDS (complex, row-major P_0 x ... x P_{d-1}).
-// A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < K: all K loads
-// (entries past the tile read entry 0) are issued before the first LDS store, so their
-// latencies overlap.  K = 12 for complex64 covers a 2-D tile of up to 3072 entries (m = 8
-// and 32 x 32 bins: 49 x 49) in one round of loads.  Grid indices wrap with a mask when
-// every n_t is a power of two (P2), else with a remainder; a tile may wrap more than once
-// when it is longer than the grid.
-template <typename T, int D, bool P2>
-__device__ __forceinline__ void stage_tile_w(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
-{
-    using C = Cplx<T>;
-    constexpr int K = sizeof(T) == 4 ? 12 : 8;
+// Grid index of entry idx of the padded tile of bin bc (row-major P_0 x ... x P_{d-1}):
+// origin b B - m per dimension, indices mod n (a mask when every n_t is a power of two, P2,
+// else a remainder; a tile may wrap more than once when it is longer than the grid).
+template <int D, bool P2> struct TileMap {
     int o[kMaxDim];
+    __device__ __forceinline__ TileMap(const Geom &g, const int *bc)
+    {
 #pragma unroll
-    for (int t = 0; t < D; ++t)
-        o[t] = (bc[t] << g.lgB[t]) - g.m + g.n[t];  // + n keeps it non-negative
-    const int Ptot = g.Ptot;
-    auto wrap = [&](int i, int t) -> int { return P2 ? (i & (g.n[t] - 1)) : i % g.n[t]; };
-    auto src = [&](int idx) -> int64_t {
+        for (int t = 0; t < D; ++t)
+            o[t] = (bc[t] << g.lgB[t]) - g.m + g.n[t];  // + n keeps it non-negative
+    }
+    __device__ __forceinline__ int wrap(const Geom &g, int i, int t) const
+    {
+        return P2 ? (i & (g.n[t] - 1)) : i % g.n[t];
+    }
+    // the same index in 32 bits, for grids of fewer than 2^32 cells
+    __device__ __forceinline__ uint32_t src32(const Geom &g, int idx) const
+    {
+        const int P12 = g.P[1] * g.P[2];
+        const int i0 = idx / P12;
+        const int rem = idx - i0 * P12;
+        const int i1 = rem / g.P[2];
+        const int i2 = rem - i1 * g.P[2];
+        const uint32_t r0 = (uint32_t)wrap(g, o[0] + i0, 0);
+        const uint32_t r1 = (uint32_t)wrap(g, o[1] + i1, 1);
+        return (r0 * (uint32_t)g.n[1] + r1) * (uint32_t)g.n[2] + (uint32_t)wrap(g, o[2] + i2, 2);
+    }
+    __device__ __forceinline__ int64_t src(const Geom &g, int idx) const
+    {
         if constexpr (D == 1) {
-            return wrap(o[0] + idx, 0);
+            return wrap(g, o[0] + idx, 0);
         } else if constexpr (D == 2) {
             const int i0 = idx / g.P[1];
             const int i1 = idx - i0 * g.P[1];
-            const int64_t r0 = wrap(o[0] + i0, 0);
-            return r0 * g.n[1] + wrap(o[1] + i1, 1);
+            const int64_t r0 = wrap(g, o[0] + i0, 0);
+            return r0 * g.n[1] + wrap(g, o[1] + i1, 1);
         } else {
             const int P12 = g.P[1] * g.P[2];
             const int i0 = idx / P12;
             const int rem = idx - i0 * P12;
             const int i1 = rem / g.P[2];
             const int i2 = rem - i1 * g.P[2];
-            const int64_t r0 = wrap(o[0] + i0, 0);
-            const int64_t r1 = wrap(o[1] + i1, 1);
-            return (r0 * g.n[1] + r1) * g.n[2] + wrap(o[2] + i2, 2);
+            const int64_t r0 = wrap(g, o[0] + i0, 0);
+            const int64_t r1 = wrap(g, o[1] + i1, 1);
+            return (r0 * g.n[1] + r1) * g.n[2] + wrap(g, o[2] + i2, 2);
         }
-    };
+    }
+};
+
+// Stage the padded tile of bin `bc` into LDS (complex, row-major P_0 x ... x P_{d-1}).
+// A thread takes tile entries idx = base + threadIdx.x + k kBlock, k < K: all K loads
+// (entries past the tile read entry 0) are issued before the first LDS store, so their
+// latencies overlap.  K = 12 for complex64 covers a 2-D tile of up to 3072 entries (m = 8
+// and 32 x 32 bins: 49 x 49) in one round of loads.
+template <typename T, int D, bool P2>
+__device__ __forceinline__ void stage_tile_w(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
+{
+    using C = Cplx<T>;
+    constexpr int K = sizeof(T) == 4 ? 12 : 8;
+    const TileMap<D, P2> map(g, bc);
+    const int Ptot = g.Ptot;
     for (int base = 0; base < Ptot; base += K * kBlock) {
         C v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int idx = base + threadIdx.x + k * kBlock;
-            v[k] = grid[src(idx < Ptot ? idx : 0)];
+            v[k] = grid[map.src(g, idx < Ptot ? idx : 0)];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {

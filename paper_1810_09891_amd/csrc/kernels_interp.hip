@@ -350,29 +350,26 @@ __device__ __forceinline__ void interp3_item(const Geom &g, const Nodes &nd, Cpl
     const int P1 = g.P[1], P2 = g.P[2];
     const int s2c = s2 < WM ? s2 : WM - 1;  // lanes past the stencil read a valid entry, weight 0
     const int s2w = s2 < W ? s2 : W - 1;
+    // Node data as loaded (cell indices, factor pairs), consumed only in the round that
+    // uses it, so that the loads of the next round stay in flight during this one.
     struct NodeData {
-        int off;  // tile offset of the stencil origin plus the lane's column
-        T w0[WM], w1[WM];  // factors of dimensions 0 and 1 (zero past W)
-        T w2;              // factor of the lane's column (zero past W)
+        int u0, u1, u2;
+        Pair<T> w0[WM / 2], w1[WM / 2];
+        T w2;
     };
     auto load = [&](int i, NodeData &q) {
         const int node = first + (i < len ? i : len - 1);
-        const int u0 = nd.u[0][node] & ((1 << g.lgB[0]) - 1);
-        const int u1 = nd.u[1][node] & ((1 << g.lgB[1]) - 1);
-        const int u2 = nd.u[2][node] & ((1 << g.lgB[2]) - 1);
-        q.off = (u0 * P1 + u1) * P2 + u2 + s2c;
+        q.u0 = nd.u[0][node];
+        q.u1 = nd.u[1][node];
+        q.u2 = nd.u[2][node];
         // aligned pairs (W and the record length 3W are even; reads stay inside the record)
         const Pair<T> *p2 = reinterpret_cast<const Pair<T> *>(psi + (int64_t)node * dW);
 #pragma unroll
         for (int s = 0; s < WM / 2; ++s) {
-            const Pair<T> a = p2[s], b = p2[W / 2 + s];
-            q.w0[2 * s] = 2 * s < W ? a.x : T(0);
-            q.w0[2 * s + 1] = 2 * s + 1 < W ? a.y : T(0);
-            q.w1[2 * s] = 2 * s < W ? b.x : T(0);
-            q.w1[2 * s + 1] = 2 * s + 1 < W ? b.y : T(0);
+            q.w0[s] = p2[s];
+            q.w1[s] = p2[W / 2 + s];
         }
-        const T w2 = psi[(int64_t)node * dW + 2 * W + s2w];
-        q.w2 = s2 < W ? w2 : T(0);
+        q.w2 = psi[(int64_t)node * dW + 2 * W + s2w];
     };
     NodeData cur, nxt;
     if (len > 0)
@@ -381,11 +378,22 @@ __device__ __forceinline__ void interp3_item(const Geom &g, const Nodes &nd, Cpl
         const int i = base + grp;
         if (base + NG < len)
             load(i + NG, nxt);
+        T w0[WM], w1[WM];  // factors of dimensions 0 and 1, zero past W
+#pragma unroll
+        for (int s = 0; s < WM / 2; ++s) {
+            w0[2 * s] = 2 * s < W ? cur.w0[s].x : T(0);
+            w0[2 * s + 1] = 2 * s + 1 < W ? cur.w0[s].y : T(0);
+            w1[2 * s] = 2 * s < W ? cur.w1[s].x : T(0);
+            w1[2 * s + 1] = 2 * s + 1 < W ? cur.w1[s].y : T(0);
+        }
+        const T w2 = s2 < W ? cur.w2 : T(0);
+        const int off = ((cur.u0 & ((1 << g.lgB[0]) - 1)) * P1 + (cur.u1 & ((1 << g.lgB[1]) - 1))) * P2 +
+                        (cur.u2 & ((1 << g.lgB[2]) - 1)) + s2c;
         // Planes are read one ahead of their sums where the registers allow: the WM reads of
         // plane s0 + 1 are issued before plane s0 is summed.  Planes past W carry weight zero
         // and stay inside the tile.
         constexpr bool kAhead = sizeof(T) == 8 ? WM <= 14 : WM <= 10;
-        const C *p = tile + cur.off;
+        const C *p = tile + off;
         const int PP = P1 * P2;
         C row[WM];
         if constexpr (kAhead) {
@@ -410,19 +418,19 @@ __device__ __forceinline__ void interp3_item(const Geom &g, const Nodes &nd, Cpl
             T rx = 0, ry = 0;
 #pragma unroll
             for (int s1 = 0; s1 < WM; ++s1) {
-                rx = fma(cur.w1[s1], row[s1].x, rx);
-                ry = fma(cur.w1[s1], row[s1].y, ry);
+                rx = fma(w1[s1], row[s1].x, rx);
+                ry = fma(w1[s1], row[s1].y, ry);
             }
-            ax = fma(cur.w0[s0], rx, ax);
-            ay = fma(cur.w0[s0], ry, ay);
+            ax = fma(w0[s0], rx, ax);
+            ay = fma(w0[s0], ry, ay);
             if (kAhead && s0 + 1 < WM) {
 #pragma unroll
                 for (int s1 = 0; s1 < WM; ++s1)
                     row[s1] = ahead[s1];
             }
         }
-        ax *= cur.w2;
-        ay *= cur.w2;
+        ax *= w2;
+        ay *= w2;
         ax = row16_sum(ax);
         ay = row16_sum(ay);
         if constexpr (G == 32) {  // the two rows of a 32-lane group
@@ -436,7 +444,9 @@ __device__ __forceinline__ void interp3_item(const Geom &g, const Nodes &nd, Cpl
 }
 
 // Tile entries from `from` on, staged by all threads of the workgroup (eight loads in
-// flight per thread).
+// flight per thread).  Stores past the tile go to the dummy entry after it, so that every
+// store is unconditional and the loads are not sunk into per-entry branches (which would
+// serialise them).
 template <typename T, bool P2>
 __device__ __forceinline__ void stage_rest3(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile, int from)
 {
@@ -445,17 +455,18 @@ __device__ __forceinline__ void stage_rest3(const Geom &g, const int *bc, const 
     const TileMap<3, P2> map(g, bc);
     const int Ptot = g.Ptot;
     for (int base = from; base < Ptot; base += K * kI3Threads) {
-        C v[K];
+        T vx[K], vy[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int idx = base + threadIdx.x + k * kI3Threads;
-            v[k] = grid[map.src(g, idx < Ptot ? idx : 0)];
+            const C a = grid[map.src(g, idx < Ptot ? idx : 0)];
+            vx[k] = a.x;
+            vy[k] = a.y;
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int idx = base + threadIdx.x + k * kI3Threads;
-            if (idx < Ptot)
-                tile[idx] = v[k];
+            tile[idx < Ptot ? idx : Ptot] = C{vx[k], vy[k]};
         }
     }
 }
@@ -492,8 +503,7 @@ __device__ __forceinline__ void loader_step(const Geom &g, const Nodes &nd, cons
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int idx = ptid + k * kI3Half;
-            if (idx < g.Ptot)
-                tile[idx] = C{vx[k], vy[k]};
+            tile[idx < g.Ptot ? idx : g.Ptot] = C{vx[k], vy[k]};  // past the tile: the dummy entry
         }
         if (g.Ptot > K * kI3Half)
             stage_rest3<T, P2>(g, bc, grid, tile, K * kI3Half);
@@ -606,10 +616,11 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 }
 }  // namespace
 
-// the padded tile, and for d = 2 the 4 x 64 partial sums of the nodes past the first 256
+// the padded tile, for d = 2 the 4 x 64 partial sums of the nodes past the first 256, for
+// d = 3 one dummy entry after the tile (the target of stores past it)
 size_t interp_lds_bytes(const Geom &g, bool dbl)
 {
-    return ((size_t)g.Ptot + (g.d == 2 ? 256 : 0)) * (dbl ? 16 : 8);
+    return ((size_t)g.Ptot + (g.d == 2 ? 256 : 0) + (g.d == 3 ? 1 : 0)) * (dbl ? 16 : 8);
 }
 // spreading tiles per workgroup: four (1-D); two (2-D) or one (3-D) followed by one dummy
 // slot per thread

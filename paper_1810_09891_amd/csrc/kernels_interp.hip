@@ -304,9 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_interp_batch(const PlanDev *__restri
 // of one item overlap the sums of the previous one.  Workgroups are persistent.
 constexpr int kI3Threads = 512;
 constexpr int kI3Half = 256;
-// tile entries a loading thread keeps in registers (complex64 stays within 128 registers,
-// so that two workgroups of eight waves share a compute unit)
-template <typename T> constexpr int i3_keep() { return sizeof(T) == 8 ? 24 : 16; }
+// tile entries a loading thread keeps in registers: a whole tile of 21^3 entries (m = 6 and
+// 8^3 bins) and, in complex128, any tile that fits the LDS; complex64 stays within 128
+// registers, so that two workgroups of eight waves share a compute unit
+template <typename T> constexpr int i3_keep() { return sizeof(T) == 8 ? 40 : 37; }
 
 // Data-parallel-primitive lane moves within rows of 16 lanes (no LDS): quad permutations,
 // the half-row mirror (lane i <-> 7 - i within each 8) and the row mirror (i <-> 15 - i).
@@ -489,11 +490,19 @@ __device__ __forceinline__ void loader_step(const Geom &g, const Nodes &nd, cons
         bin_coords<T, 3>(g, nd.chunk_bin[cn], bc);
         const TileMap<3, P2> map(g, bc);
         const int Ptot = g.Ptot;
+        // The tile coordinates of a thread's entries are the same for every item; an empty
+        // asm statement hides that, so that they are recomputed here rather than kept in K
+        // times three registers across the loop (it emits no instruction).
+        int pt = ptid;
+        asm volatile("" : "+v"(pt));
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int idx = ptid + k * kI3Half;
+            const int idx = pt + k * kI3Half;
             const int e = idx < Ptot ? idx : 0;
-            const C a = O32 ? grid[map.src32(g, e)] : grid[map.src(g, e)];
+            // 32-bit byte offsets from the uniform grid base (one address register per load)
+            const C a = O32 ? *reinterpret_cast<const C *>(reinterpret_cast<const char *>(grid) +
+                                                            map.src32(g, e) * (uint32_t)sizeof(C))
+                            : grid[map.src(g, e)];
             vx[k] = a.x;
             vy[k] = a.y;
         }

@@ -415,13 +415,49 @@ def bench_batch(torch, steps, warmup, check):
     ms_b = cuda_time(torch, batched, steps, warmup)
     ms_s = cuda_time(torch, sequential, steps, warmup)
     Mtot = int(sum(s["M"] for s in specs))
+
+    # the same plans with measured bin edges and work-item caps (nfft_plan_tune per plan
+    # shape, one cache for all), batched and autotuned again
+    from paper_1810_09891_amd import tune_plan_params
+    with tempfile.TemporaryDirectory() as td:
+        t0 = time.perf_counter()
+        tplans, chosen = [], []
+        for s in specs:
+            x = torch.as_tensor(s["x"]).cuda()
+            prm, _ = tune_plan_params(s["N"], s["M"], x, m=6, dtype=C64, cache=os.path.join(td, "plans.txt"))
+            p = Plan(s["N"], s["M"], m=6, dtype=C64, params=prm)
+            p.set_nodes(x)
+            tplans.append(p)
+            chosen.append(prm)
+        plan_tune_s = time.perf_counter() - t0
+        bt = Batch(tplans, tune_cache=os.path.join(td, "tune.txt"))
+        bt.autotune()
+    outs_ft = [torch.empty(s["M"], dtype=C64, device="cuda") for s in specs]
+    outs_ht = [torch.empty(s["N"], dtype=C64, device="cuda") for s in specs]
+
+    def batched_tuned():
+        bt.trafo(fh, outs_ft)
+        bt.adjoint(fv, outs_ht)
+
+    ms_t = cuda_time(torch, batched_tuned, steps, warmup)
+    defaults = [{"bin": tuple(int(p.info.bin[t]) for t in range(2)), "chunk_cap": int(p.info.chunk_cap)}
+                for p in plans]
     r = {"workload": "64 plans d=2, N_i from {64,128,256,512}^2, M_i log-uniform in [1e3,2e5] "
                      "(total M=%d, total grid points=%d), complex64, m=6" %
                      (Mtot, int(sum(4 * np.prod(s["N"]) for s in specs))),
          "ms_per_step": ms_b, "points_per_s": Mtot / (ms_b * 1e-3),
          "sequential_ms_per_step": ms_s, "sequential_points_per_s": Mtot / (ms_s * 1e-3),
-         "speedup_vs_sequential": ms_s / ms_b, "autotune_s": tune_s, "params": params}
+         "speedup_vs_sequential": ms_s / ms_b, "autotune_s": tune_s, "params": params,
+         "tuned_plan_params": {
+             "what": "bin edges and work-item cap measured per plan shape (nfft_plan_tune), then batched",
+             "ms_per_step": ms_t, "points_per_s": Mtot / (ms_t * 1e-3), "plan_tune_s": plan_tune_s,
+             "speedup_vs_default_params": ms_b / ms_t,
+             "plans_changed": int(sum(c != dflt for c, dflt in zip(chosen, defaults))),
+             "chosen": sorted({(c["bin"], c["chunk_cap"]) for c in chosen})}}
     if check:
+        batched_tuned()
+        ft = [o.cpu().numpy() for o in outs_ft]
+        ht = [o.cpu().numpy() for o in outs_ht]
         batched()
         fb = [o.cpu().numpy() for o in outs_f]
         hb = [o.cpu().numpy() for o in outs_h]
@@ -430,6 +466,8 @@ def bench_batch(torch, steps, warmup, check):
         hs = [o.cpu().numpy() for o in outs_h]
         r["max_e2_batched_vs_per_plan"] = max(max(e2(a, c) for a, c in zip(fs, fb)),
                                              max(e2(a, c) for a, c in zip(hs, hb)))
+        r["tuned_plan_params"]["max_e2_vs_default_params"] = max(max(e2(a, c) for a, c in zip(fb, ft)),
+                                                                 max(e2(a, c) for a, c in zip(hb, ht)))
         order = np.argsort([s["M"] for s in specs])
         worst = 0.0
         for i in order[:3]:
@@ -438,6 +476,7 @@ def bench_batch(torch, steps, warmup, check):
                         e2(O.nfft_adjoint(s["x"], s["f"], s["N"], None, 6), hb[i]))
         r["max_e2_vs_oracle_3_smallest_plans"] = worst
     b.close()
+    bt.close()
     return r
 
 

@@ -16,9 +16,9 @@
  *    marked [host] are host memory read before the call returns.  No transform, node
  *    or step entry point allocates or frees device memory: all scratch lives in a
  *    caller-provided workspace (nfft_workspace_bytes / nfft_set_workspace, and
- *    nfft_batch_workspace_bytes / nfft_batch_set_workspace for batches).  The one
- *    exception is the tuning call nfft_batch_autotune, which allocates and frees its
- *    temporary stand-in inputs.
+ *    nfft_batch_workspace_bytes / nfft_batch_set_workspace for batches).  The
+ *    exceptions are the tuning calls nfft_batch_autotune and nfft_plan_tune, which
+ *    allocate and free their temporary stand-in inputs and candidate workspaces.
  *  * Results are bitwise reproducible from run to run for a given device, plan, workspace
  *    layout and input (see NFFT_DETERMINISTIC).
  *  * Every call that does device work enqueues it on the given stream and returns
@@ -144,6 +144,43 @@ typedef struct {
  * Host only: no device work, no device memory.  *out receives the plan. */
 int nfft_plan_create(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
                      nfft_dtype dtype, uint32_t flags);
+
+/* Work decomposition of a plan's window steps (Sec. 3.1: the precomputation choices of
+ * Table 3.2 and the measured tuning of Table 3.3 are the paper's counterparts).
+ *   bin[t]     bin edge in grid cells per dimension: nodes are sorted into bins of
+ *              bin[0] x ... x bin[d-1] cells and the window kernels stage one padded tile
+ *              per bin.  Powers of two no longer than n_t; 0 in bin[0] selects the
+ *              default rule (largest edges up to 512 / 32 x 32 / 8 x 8 x 8 whose tiles fit
+ *              the LDS).  Entries past d are ignored.
+ *   chunk_cap  maximum nodes per work item, a power of two in [32, 1024]; 0 selects the
+ *              default (M / 512 rounded down to a power of two, within [128, 1024]). */
+typedef struct {
+    int32_t bin[3];
+    int32_t chunk_cap;
+} nfft_plan_params;
+
+/* nfft_plan_create with a given work decomposition (params may be NULL: the defaults).
+ * Errors as nfft_plan_create, plus NFFT_ERR_ARG for edges or caps outside the ranges above
+ * and NFFT_ERR_UNSUPPORTED when the requested tiles do not fit the LDS.  Results do not
+ * depend on params beyond rounding (every choice computes the same sums). Host only. */
+int nfft_plan_create_params(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
+                            nfft_dtype dtype, uint32_t flags, const nfft_plan_params *params);
+
+/* Measured choice of the work decomposition for a plan shape and node set (the analogue of
+ * FFTW's measured plans and wisdom that Sec. 3.1 uses for the FFT).  Candidates: chunk
+ * caps 128 ... 1024 with the default bins, then bin edges halved or doubled per dimension
+ * with the best cap; each is timed as nfft_set_nodes once and three nfft_trafo +
+ * nfft_adjoint pairs on `stream`, and the fastest wins.
+ *   x       [device] M x d FP64 nodes (as for nfft_set_nodes).
+ *   cache   [host] path of a text file, or NULL: a shape already in the file (key: d, n,
+ *           floor(log2 M), m, precision, window) is answered from it without timing, and a
+ *           new result is appended.
+ *   out     [host] receives the chosen parameters; best_ms (may be NULL) the measured time
+ *           of one transform pair with them (0 when answered from the cache).
+ * This call allocates and frees device memory (the candidate plans' workspaces and
+ * stand-in data) and synchronises the stream; it is a set-up step, not a transform. */
+int nfft_plan_tune(int d, const int64_t *N, int64_t M, const int64_t *n, int m, nfft_dtype dtype, uint32_t flags,
+                   const double *x, const char *cache, hipStream_t stream, nfft_plan_params *out, double *best_ms);
 
 /* Destroy a plan.  Host only; frees nothing the caller owns (not the workspace). */
 int nfft_plan_destroy(nfft_plan p);

@@ -6,7 +6,7 @@ hand-written HIP kernels for gfx950 behind a C ABI (include/nfft_mi355x.h).
     f = p.trafo(fhat)        # NFFT
     h = p.adjoint(f)         # adjoint NFFT
 """
-from .nfft import Batch, NNPlan, Plan, default_n, fastsum, gaussian_coefficients  # noqa: F401
+from .nfft import Batch, NNPlan, Plan, default_n, fastsum, gaussian_coefficients, tune_plan_params  # noqa: F401
 from .autograd import differentiable_plan, nfft  # noqa: F401
 from ._lib import (NFFT_DETERMINISTIC, NFFT_KEEP_GRID, NFFT_SORT_NODES, NFFT_WINDOW_BSPLINE, NFFT_WINDOW_GAUSSIAN,  # noqa: F401
                    NFFT_WINDOW_SINC, NfftError, load)

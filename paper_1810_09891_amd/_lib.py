@@ -31,8 +31,8 @@ STATUS = {
 
 # every exported entry point of include/nfft_mi355x.h
 ABI_SYMBOLS = [
-    "nfft_plan_create", "nfft_plan_destroy", "nfft_plan_get_info", "nfft_workspace_bytes",
-    "nfft_set_workspace", "nfft_set_nodes", "nfft_nodes_finite", "nfft_trafo", "nfft_adjoint", "nfft_fastsum", "ndft_trafo",
+    "nfft_plan_create", "nfft_plan_create_params", "nfft_plan_tune", "nfft_plan_destroy", "nfft_plan_get_info",
+    "nfft_workspace_bytes", "nfft_set_workspace", "nfft_set_nodes", "nfft_nodes_finite", "nfft_trafo", "nfft_adjoint", "nfft_fastsum", "ndft_trafo",
     "ndft_adjoint", "nfft_grad_x", "nfft_step_grid", "nfft_step_interp", "nfft_step_spread",
     "nfft_step_coeffs", "nfft_profile_enable", "nfft_profile_read", "nfft_batch_create",
     "nfft_batch_get_info", "nfft_batch_workspace_bytes", "nfft_batch_set_workspace",
@@ -46,6 +46,11 @@ class NfftError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
         super().__init__("%s failed: %s (%d)" % (what, STATUS.get(status, "?"), status))
+
+
+class PlanParams(ctypes.Structure):
+    """nfft_plan_params: bin edges per dimension and the work-item cap (0: defaults)."""
+    _fields_ = [("bin", ctypes.c_int32 * 3), ("chunk_cap", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -116,6 +121,10 @@ def load():
     sig = {
         "nfft_plan_create": [ctypes.POINTER(P), I, ctypes.POINTER(I64), I64, ctypes.POINTER(I64), I, I,
                              ctypes.c_uint32],
+        "nfft_plan_create_params": [ctypes.POINTER(P), I, ctypes.POINTER(I64), I64, ctypes.POINTER(I64), I, I,
+                                    ctypes.c_uint32, ctypes.POINTER(PlanParams)],
+        "nfft_plan_tune": [I, ctypes.POINTER(I64), I64, ctypes.POINTER(I64), I, I, ctypes.c_uint32, P,
+                           ctypes.c_char_p, P, ctypes.POINTER(PlanParams), ctypes.POINTER(ctypes.c_double)],
         "nfft_plan_destroy": [P],
         "nfft_plan_get_info": [P, ctypes.POINTER(PlanInfo)],
         "nfft_workspace_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],

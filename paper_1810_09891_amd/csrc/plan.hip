@@ -50,7 +50,9 @@ int ilog2(int64_t v)
 
 namespace nfft {
 
-static int choose_bins(nfft_plan_s *p)
+// Bin edges: the requested ones (req[t] > 0: powers of two no longer than the grid, checked
+// against the LDS), else the rule below.
+static int choose_bins(nfft_plan_s *p, const int32_t *req)
 {
     const int d = p->d;
     const size_t cs = p->dbl ? 16 : 8;
@@ -92,7 +94,15 @@ static int choose_bins(nfft_plan_s *p)
             extra = 0;
         }
     }
-    while (ntiles * lds_of(B) + extra > budget) {
+    const bool requested = req && req[0] > 0;
+    if (requested) {
+        for (int t = 0; t < d; ++t) {
+            if (req[t] < 1 || (req[t] & (req[t] - 1)) || req[t] > (1 << ilog2(p->n[t])))
+                return NFFT_ERR_ARG;
+            B[t] = req[t];
+        }
+    }
+    while (!requested && ntiles * lds_of(B) + extra > budget) {
         int best = -1;
         for (int t = 0; t < d; ++t)
             if (B[t] > minB && B[t] > 1 && (best < 0 || B[t] > B[best]))
@@ -459,7 +469,7 @@ static void layout_workspace(nfft_plan_s *p)
 }
 
 static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
-                       nfft_dtype dtype, uint32_t flags)
+                       nfft_dtype dtype, uint32_t flags, const nfft_plan_params *params)
 {
     if (!out || !N || d < 1 || d > kMaxDim || M < 1 || M > (int64_t)0x7fffffff)
         return NFFT_ERR_ARG;
@@ -522,7 +532,12 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
         g.n[t] = (int)p->n[t];
         g.p2 = g.p2 && is_pow2(p->n[t]);
     }
-    int st = choose_bins(p);
+    if (params && params->chunk_cap != 0 &&
+        (params->chunk_cap < 32 || params->chunk_cap > 1024 || (params->chunk_cap & (params->chunk_cap - 1)))) {
+        delete p;
+        return NFFT_ERR_ARG;
+    }
+    int st = choose_bins(p, params ? params->bin : nullptr);
     if (st != NFFT_OK) {
         delete p;
         return st;
@@ -533,6 +548,8 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
     p->chunk_cap = 128;
     while (p->chunk_cap < 1024 && (int64_t)p->chunk_cap * 2 * 512 <= M)
         p->chunk_cap *= 2;
+    if (params && params->chunk_cap > 0)
+        p->chunk_cap = params->chunk_cap;
     p->max_chunks = (int)(g.nbins + (M + p->chunk_cap - 1) / p->chunk_cap);
     setup_owner(p);
     build_tables(p);
@@ -758,7 +775,19 @@ int nfft_plan_create(nfft_plan *out, int d, const int64_t *N, int64_t M, const i
     if (!out)
         return NFFT_ERR_ARG;
     nfft_plan_s *p = nullptr;
-    int st = create_plan(&p, d, N, M, n, m, dtype, flags);
+    int st = create_plan(&p, d, N, M, n, m, dtype, flags, nullptr);
+    if (st == NFFT_OK)
+        *out = p;
+    return st;
+}
+
+int nfft_plan_create_params(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
+                            nfft_dtype dtype, uint32_t flags, const nfft_plan_params *params)
+{
+    if (!out)
+        return NFFT_ERR_ARG;
+    nfft_plan_s *p = nullptr;
+    int st = create_plan(&p, d, N, M, n, m, dtype, flags, params);
     if (st == NFFT_OK)
         *out = p;
     return st;

@@ -8,6 +8,7 @@ provides device memory (tensors, including the plan's workspace) and the stream 
 library enqueues on.
 """
 import ctypes
+import os
 
 import torch
 
@@ -37,6 +38,40 @@ def default_n(N):
     return tuple(out)
 
 
+def _plan_params(params):
+    """nfft_plan_params from a dict {"bin": (B0[, B1[, B2]]), "chunk_cap": C} (missing: 0)."""
+    pp = _lib.PlanParams()
+    b = tuple(params.get("bin", ())) + (0, 0, 0)
+    for t in range(3):
+        pp.bin[t] = int(b[t]) if b[0] else 0
+    pp.chunk_cap = int(params.get("chunk_cap", 0))
+    return pp
+
+
+def tune_plan_params(N, M, x, n=None, m=8, dtype=torch.complex64, flags=0, window="kaiser-bessel", cache=None):
+    """Measured bin edges and work-item cap for this plan shape and node set (nfft_plan_tune).
+
+    x: (M, d) float64 device tensor.  Returns ({"bin": (...), "chunk_cap": C}, ms) where ms is
+    the measured time of one trafo + adjoint pair with them (0.0 when read from `cache`).
+    Allocates temporary device memory; synchronises the current stream."""
+    lib = _lib.load()
+    if window not in _lib.WINDOW_FLAGS:
+        raise ValueError("window must be one of %s" % sorted(_lib.WINDOW_FLAGS))
+    N = tuple(int(v) for v in N)
+    d = len(N)
+    if x.dtype != torch.float64 or not x.is_cuda or tuple(x.shape) != (int(M), d):
+        raise ValueError("x must be a (M, d) float64 device tensor")
+    x = x.contiguous()
+    Na = (ctypes.c_int64 * d)(*N)
+    na = None if n is None else (ctypes.c_int64 * d)(*[int(v) for v in n])
+    out = _lib.PlanParams()
+    ms = ctypes.c_double(0.0)
+    check(lib.nfft_plan_tune(d, Na, int(M), na, int(m), _CDTYPE[dtype], int(flags) | _lib.WINDOW_FLAGS[window],
+                             _ptr(x), None if cache is None else os.fsencode(cache), _stream(x.device),
+                             ctypes.byref(out), ctypes.byref(ms)), "nfft_plan_tune")
+    return {"bin": tuple(int(out.bin[t]) for t in range(d)), "chunk_cap": int(out.chunk_cap)}, float(ms.value)
+
+
 class Plan:
     """NFFT plan for d-variate transforms with bandwidths N, M nodes, FFT lengths n and
     window size m, computing in complex64 or complex128, with the Kaiser-Bessel window
@@ -46,7 +81,8 @@ class Plan:
     (M, d) float64, values are (M,).  All tensors live on ``device``.
     """
 
-    def __init__(self, N, M, n=None, m=8, dtype=torch.complex64, flags=0, device="cuda", window="kaiser-bessel"):
+    def __init__(self, N, M, n=None, m=8, dtype=torch.complex64, flags=0, device="cuda", window="kaiser-bessel",
+                 params=None):
         lib = _lib.load()
         if window not in _lib.WINDOW_FLAGS:
             raise ValueError("window must be one of %s" % sorted(_lib.WINDOW_FLAGS))
@@ -61,8 +97,13 @@ class Plan:
         Na = (ctypes.c_int64 * self.d)(*self.N)
         na = None if n is None else (ctypes.c_int64 * self.d)(*[int(v) for v in n])
         h = ctypes.c_void_p()
-        check(lib.nfft_plan_create(ctypes.byref(h), self.d, Na, self.M, na, int(m), _CDTYPE[dtype], int(flags)),
-              "nfft_plan_create")
+        if params is None:
+            check(lib.nfft_plan_create(ctypes.byref(h), self.d, Na, self.M, na, int(m), _CDTYPE[dtype], int(flags)),
+                  "nfft_plan_create")
+        else:
+            pp = _plan_params(params)
+            check(lib.nfft_plan_create_params(ctypes.byref(h), self.d, Na, self.M, na, int(m), _CDTYPE[dtype],
+                                              int(flags), ctypes.byref(pp)), "nfft_plan_create_params")
         self._h = h
         self._lib = lib
         info = _lib.PlanInfo()

@@ -336,7 +336,7 @@ def test_nnfft_automatic_frequency_grid(lib, N, m):
 
 def test_deterministic_flag_accepted(lib):
     """NFFT_DETERMINISTIC (always on) is accepted and reported back; the header states
-    that only nfft_batch_autotune allocates device memory."""
+    that only the tuning calls allocate device memory."""
     st, h = create(lib, (64, 64), 1000, None, 6, 1, _lib.NFFT_DETERMINISTIC | _lib.NFFT_KEEP_GRID)
     assert st == OK
     info = _lib.PlanInfo()
@@ -345,7 +345,7 @@ def test_deterministic_flag_accepted(lib):
     assert lib.nfft_plan_destroy(h) == OK
     txt = open(HEADER).read()
     assert "NFFT_DETERMINISTIC = 1u << 5" in txt
-    assert "exception is the tuning call nfft_batch_autotune" in txt
+    assert "exceptions are the tuning calls nfft_batch_autotune and nfft_plan_tune" in txt.replace("\n *    ", " ")
 
 
 def test_noalloc_batch_rejects_tables_beyond_the_static_scratch(lib):
@@ -371,3 +371,54 @@ def test_noalloc_batch_rejects_tables_beyond_the_static_scratch(lib):
     assert lib.nfft_batch_destroy(b) == OK
     for h in plans:
         assert lib.nfft_plan_destroy(h) == OK
+
+
+def create_params(lib, N, M, n, m, dtype, bins, cap):
+    d = len(N)
+    h = ctypes.c_void_p()
+    Na = (ctypes.c_int64 * d)(*N)
+    na = None if n is None else (ctypes.c_int64 * d)(*n)
+    pp = _lib.PlanParams()
+    for t in range(3):
+        pp.bin[t] = bins[t] if t < len(bins) else 0
+    pp.chunk_cap = cap
+    st = lib.nfft_plan_create_params(ctypes.byref(h), d, Na, M, na, m, dtype, 0, ctypes.byref(pp))
+    return st, h
+
+
+@pytest.mark.parametrize(
+    "N,n,m,dtype,bins,cap,expect",
+    [
+        ((64, 64), (128, 128), 6, 1, (16, 32), 256, OK),
+        ((64, 64), (128, 128), 6, 1, (0,), 0, OK),  # defaults
+        ((64, 64), (128, 128), 6, 1, (16, 24), 256, ARG),  # not a power of two
+        ((64, 64), (128, 128), 6, 1, (256, 32), 256, ARG),  # longer than the grid
+        ((64, 64), (128, 128), 6, 1, (16, 32), 48, ARG),  # cap not a power of two
+        ((64, 64), (128, 128), 6, 1, (16, 32), 2048, ARG),  # cap past 1024
+        ((64, 64), (128, 128), 6, 1, (128, 128), 256, UNSUP),  # tiles beyond the LDS
+        ((32, 32, 32), (64, 64, 64), 6, 2, (4, 8, 8), 512, OK),
+        ((256,), (514,), 8, 2, (256,), 128, OK),
+    ],
+)
+def test_plan_params_validation(lib, N, n, m, dtype, bins, cap, expect):
+    """nfft_plan_create_params takes the requested bin edges and work-item cap, reports them
+    in the plan info, and refuses edges and caps outside the documented ranges."""
+    st, h = create_params(lib, N, 1000, n, m, dtype, bins, cap)
+    assert st == expect
+    if st == OK:
+        info = _lib.PlanInfo()
+        assert lib.nfft_plan_get_info(h, ctypes.byref(info)) == OK
+        if bins[0]:
+            assert tuple(info.bin[t] for t in range(len(N))) == tuple(bins)
+        if cap:
+            assert info.chunk_cap == cap
+        assert lib.nfft_plan_destroy(h) == OK
+
+
+def test_plan_tune_rejects_missing_arguments(lib):
+    """nfft_plan_tune needs nodes and an output (checked before any device work)."""
+    Na = (ctypes.c_int64 * 2)(64, 64)
+    out = _lib.PlanParams()
+    assert lib.nfft_plan_tune(2, Na, 100, None, 6, 1, 0, None, None, None, ctypes.byref(out), None) == ARG
+    assert lib.nfft_plan_tune(2, Na, 100, None, 6, 1, 0, ctypes.c_void_p(256), None, None, None, None) == ARG
+

@@ -170,7 +170,9 @@ int nfft_plan_create_params(nfft_plan *out, int d, const int64_t *N, int64_t M, 
  * FFTW's measured plans and wisdom that Sec. 3.1 uses for the FFT).  Candidates: chunk
  * caps 128 ... 1024 with the default bins, then bin edges halved or doubled per dimension
  * with the best cap; each is timed as nfft_set_nodes once and three nfft_trafo +
- * nfft_adjoint pairs on `stream`, and the fastest wins.
+ * nfft_adjoint pairs on `stream`; a candidate replaces the best so far only when it is
+ * more than 5% faster (short timings vary by a few percent), and shapes whose default
+ * transform pair takes under 0.1 ms (launch latency) keep the defaults.
  *   x       [device] M x d FP64 nodes (as for nfft_set_nodes).
  *   cache   [host] path of a text file, or NULL: a shape already in the file (key: d, n,
  *           floor(log2 M), m, precision, window) is answered from it without timing, and a

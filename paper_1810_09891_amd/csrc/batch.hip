@@ -447,11 +447,13 @@ int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const 
     if (tune_cache)
         b->cache = tune_cache;
     // group by kernel template parameters, largest M first, at most kMaxBatch per launch
-    // (the last key holds the output-tile flag and, in bit 1, a grid that is not a power of two)
+    // (the last key holds the output-tile flag, in bit 1 a grid that is not a power of two,
+    // in bit 2 spreading in registers, so that plans whose bins do not allow it do not move
+    // a whole group to the tile kernel)
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by_kind;
     for (int i = 0; i < count; ++i)
         by_kind[std::make_tuple(plans[i]->d, plans[i]->WM, plans[i]->dbl ? 1 : 0,
-                                plans[i]->geom.own + (plans[i]->geom.p2 ? 0 : 2))]
+                                plans[i]->geom.own + (plans[i]->geom.p2 ? 0 : 2) + (plans[i]->spos_used ? 4 : 0))]
             .push_back(i);
     for (auto &kv : by_kind) {
         std::vector<int> v = kv.second;

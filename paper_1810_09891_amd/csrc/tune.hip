@@ -120,6 +120,11 @@ double time_candidate(int d, const int64_t *N, int64_t M, const int64_t *n, int 
 
 }  // namespace
 
+// a candidate replaces the best so far only when it is faster by more than the run-to-run
+// spread of short timings (about 3% here), so that noise does not pick a decomposition
+constexpr double kMargin = 0.95;
+constexpr double kMinTuneMs = 0.1;
+
 extern "C" {
 
 int nfft_plan_tune(int d, const int64_t *N, int64_t M, const int64_t *n, int m, nfft_dtype dtype, uint32_t flags,
@@ -150,8 +155,10 @@ int nfft_plan_tune(int d, const int64_t *N, int64_t M, const int64_t *n, int m, 
     double best_t = time_candidate(d, N, M, n, m, dtype, flags, def, x, s, cst);
     if (cst == NFFT_ERR_HIP)
         return cst;
-    // work-item caps with the default bins
-    for (int cap = 128; cap <= 1024; cap *= 2) {
+    // work-item caps with the default bins (plans whose transform pair takes less than
+    // kMinTuneMs keep the defaults: their time is launch latency, which no decomposition
+    // changes, and the differences measured are noise)
+    for (int cap = 128; cap <= 1024 && best_t >= kMinTuneMs; cap *= 2) {
         if (cap == def.chunk_cap)
             continue;
         nfft_plan_params c = def;
@@ -159,7 +166,7 @@ int nfft_plan_tune(int d, const int64_t *N, int64_t M, const int64_t *n, int m, 
         const double t = time_candidate(d, N, M, n, m, dtype, flags, c, x, s, cst);
         if (cst == NFFT_ERR_HIP)
             return cst;
-        if (t < best_t) {
+        if (t < kMargin * best_t) {
             best_t = t;
             best = c;
         }
@@ -183,11 +190,13 @@ int nfft_plan_tune(int d, const int64_t *N, int64_t M, const int64_t *n, int m, 
             c.bin[t] = def.bin[t] / 2;
         bins.push_back(c);
     }
+    if (!(best_t >= kMinTuneMs))
+        bins.clear();
     for (const nfft_plan_params &c : bins) {
         const double t = time_candidate(d, N, M, n, m, dtype, flags, c, x, s, cst);
         if (cst == NFFT_ERR_HIP)
             return cst;
-        if (t < best_t) {
+        if (t < kMargin * best_t) {
             best_t = t;
             best = c;
         }

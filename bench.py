@@ -113,7 +113,7 @@ def valu_seconds(d, M, m, dbl):
 
 
 # rocprofv3 kernel names of the library's launch labels, in order of preference
-ROCPROF_NAME = {"interp": ("k_interp_nodes",),
+ROCPROF_NAME = {"interp": ("k_interp3", "k_interp_nodes"),
                 "spread_tiles": ("k_spread_cols", "k_spread_tiles"), "spread_own": ("k_spread_own",),
                 "spread_fold": ("k_fold",), "grad_x": ("k_grad_x",)}
 

@@ -373,8 +373,11 @@ __global__ __launch_bounds__(kBlock) void k_own_gather(Nodes nd, const Cplx<T> *
         fs[p] = f[nd.perm[p]];
 }
 
-// Waves per SIMD the window kernels by tiles aim at (register budget 512 / waves).
-template <typename T, int W> constexpr int own_waves() { return sizeof(T) == 4 && W <= 14 ? 3 : 2; }
+// Waves per SIMD the spreading kernel aims at (register budget 512 / waves).  The walk is
+// latency-bound, so occupancy pays for a few spilled registers: measured at m = 6 (3-D
+// radial, 2,097,152 nodes), complex64 3.89 / 3.72 / 3.73 ms at 3 / 4 / 4 waves (the last
+// with complex128 also at 4), complex128 4.84 / 4.30 / 4.37 ms at 2 / 3 / 4 waves.
+template <typename T, int W> constexpr int own_waves() { return W > 14 ? 2 : (sizeof(T) == 4 ? 4 : 3); }
 
 template <typename T, int T0, int W>
 __global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_spread_own(Geom g, Nodes nd, const Cplx<T> *__restrict__ fs,

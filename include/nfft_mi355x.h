@@ -88,14 +88,23 @@ typedef enum {
  *    that callers can state the requirement.  Every floating-point sum of the library has
  *    a fixed order: no atomics touch floating-point data, the nodes of a bin are kept in
  *    caller-index order (so a bin's split into work items is fixed), and the partial
- *    results of the spreading step are folded in a fixed order. */
+ *    results of the spreading step are folded in a fixed order.
+ *  NFFT_PRE_LIN_PSI: the window factors that nfft_set_nodes precomputes, and the factors and
+ *    derivatives of nfft_grad_x, come from lookup tables (Sec. 3.1, Table 3.2: PRE_LIN_PSI)
+ *    instead of the closed form: per dimension and stencil point, 4097 samples in the offset
+ *    delta in [0, 1] (evaluated in FP64 at set-up), linearly interpolated.  The
+ *    interpolation adds a relative error of about 1e-8 to each factor (second differences
+ *    of the window over steps of 1/4096); results are within 1e-7 of the exact transform for
+ *    the windows and sizes tested, so complex128 plans with this flag do not meet 1e-12.
+ *    The tables take 2 (2m+2) 4097 reals per dimension of the workspace. */
 enum {
     NFFT_SORT_NODES = 1u << 0,
     NFFT_KEEP_GRID = 1u << 1,
     NFFT_WINDOW_GAUSSIAN = 1u << 2,
     NFFT_WINDOW_BSPLINE = 1u << 3,
     NFFT_WINDOW_SINC = 1u << 4,
-    NFFT_DETERMINISTIC = 1u << 5
+    NFFT_DETERMINISTIC = 1u << 5,
+    NFFT_PRE_LIN_PSI = 1u << 6
 };
 
 /* Read-only description of a plan (filled by nfft_plan_get_info). */

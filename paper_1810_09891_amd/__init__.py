@@ -8,5 +8,5 @@ hand-written HIP kernels for gfx950 behind a C ABI (include/nfft_mi355x.h).
 """
 from .nfft import Batch, NNPlan, Plan, default_n, fastsum, gaussian_coefficients, tune_plan_params  # noqa: F401
 from .autograd import differentiable_plan, nfft  # noqa: F401
-from ._lib import (NFFT_DETERMINISTIC, NFFT_KEEP_GRID, NFFT_SORT_NODES, NFFT_WINDOW_BSPLINE, NFFT_WINDOW_GAUSSIAN,  # noqa: F401
+from ._lib import (NFFT_DETERMINISTIC, NFFT_KEEP_GRID, NFFT_PRE_LIN_PSI, NFFT_SORT_NODES, NFFT_WINDOW_BSPLINE, NFFT_WINDOW_GAUSSIAN,  # noqa: F401
                    NFFT_WINDOW_SINC, NfftError, load)

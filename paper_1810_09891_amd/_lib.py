@@ -14,6 +14,7 @@ NFFT_C128 = 2
 NFFT_SORT_NODES = 1 << 0
 NFFT_KEEP_GRID = 1 << 1
 NFFT_DETERMINISTIC = 1 << 5  # always on: results are bitwise reproducible
+NFFT_PRE_LIN_PSI = 1 << 6  # window factors from lookup tables (Table 3.2, PRE_LIN_PSI)
 NFFT_WINDOW_GAUSSIAN = 1 << 2
 NFFT_WINDOW_BSPLINE = 1 << 3
 NFFT_WINDOW_SINC = 1 << 4

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 dl[t] = static_cast<const T *>(nd.delta[t])[node];
             }
             T wl[WM], dwl[WM];
-            window_row_d<T, WM, AllW>(dl[D - 1], g, D - 1, wl, dwl);
+            window_row_d<T, WM, AllW>(dl[D - 1], g, nd, D - 1, wl, dwl);
             C acc[kMaxDim];
 #pragma unroll
             for (int t = 0; t < D; ++t)
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 }
             } else if constexpr (D == 2) {
                 for (int s0 = 0; s0 < g.W; ++s0) {
-                    const T w0 = win_point<T, AllW>(g, 0, dl[0], s0);
-                    const T dw0 = win_point_d<T, AllW>(g, 0, dl[0], s0);
+                    const T w0 = win_value<T, AllW>(g, nd, 0, dl[0], s0);
+                    const T dw0 = win_value_d<T, AllW>(g, nd, 0, dl[0], s0);
                     const C *row = tile + (ul[0] + s0) * g.P[1] + ul[1];
                     T rx = 0, ry = 0, dx = 0, dy = 0;
 #pragma unroll
@@ -75,11 +75,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_x(Geom g, Nodes nd, const Cplx<
                 }
             } else {
                 T wmid[WM], dwmid[WM];
-                window_row_d<T, WM, AllW>(dl[1], g, 1, wmid, dwmid);
+                window_row_d<T, WM, AllW>(dl[1], g, nd, 1, wmid, dwmid);
                 const int P1 = g.P[1], P2 = g.P[2];
                 for (int s0 = 0; s0 < g.W; ++s0) {
-                    const T w0 = win_point<T, AllW>(g, 0, dl[0], s0);
-                    const T dw0 = win_point_d<T, AllW>(g, 0, dl[0], s0);
+                    const T w0 = win_value<T, AllW>(g, nd, 0, dl[0], s0);
+                    const T dw0 = win_value_d<T, AllW>(g, nd, 0, dl[0], s0);
                     const C *plane = tile + ((ul[0] + s0) * P1 + ul[1]) * P2 + ul[2];
                     T px = 0, py = 0, qx = 0, qy = 0, hx = 0, hy = 0;
 #pragma unroll

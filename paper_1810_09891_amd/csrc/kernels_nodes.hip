@@ -233,7 +233,22 @@ template <typename T, bool AllW> __global__ __launch_bounds__(kBlock) void k_nod
     int s = r - t * W;
     T delta = static_cast<const T *>(nd.delta[t])[node];
     // a non-finite node (offset NaN) gets NaN factors, so that its results are NaN too
-    static_cast<T *>(nd.psi)[q] = isnan(delta) ? delta : win_point<T, AllW>(g, t, delta, s);
+    static_cast<T *>(nd.psi)[q] = isnan(delta) ? delta : win_value<T, AllW>(g, nd, t, delta, s);
+}
+
+// The lookup tables of dimension t (plans with NFFT_PRE_LIN_PSI): entry s (kLinK + 1) + i holds
+// the factor and its derivative at stencil point s for delta = i / kLinK, evaluated in FP64
+// and rounded once.
+template <typename T> __global__ __launch_bounds__(kBlock) void k_fill_lin(Geom g, int t, T *tab, T *dtab)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)g.W * (kLinK + 1))
+        return;
+    const int s = (int)(e / (kLinK + 1));
+    const int i = (int)(e - (int64_t)s * (kLinK + 1));
+    const double delta = (double)i / kLinK;
+    tab[e] = (T)win_point<double, true>(g, t, delta, s);
+    dtab[e] = (T)win_point_d<double, true>(g, t, delta, s);
 }
 
 // One thread per bin writes the bin's work items.
@@ -482,6 +497,18 @@ hipError_t launch_node_scatter(const Geom &g, const Nodes &nd, bool dbl, hipStre
         auto kf = window_needs_all(g) ? k_node_psi<float, true> : k_node_psi<float, false>;
         hipLaunchKernelGGL(kf, dim3(blocks_for(nf)), block, 0, s, g, nd);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_lin(const Geom &g, int t, bool dbl, void *tab, void *dtab, hipStream_t s)
+{
+    const int64_t n = (int64_t)g.W * (kLinK + 1);
+    if (dbl)
+        hipLaunchKernelGGL(k_fill_lin<double>, dim3(blocks_for(n)), dim3(kBlock), 0, s, g, t,
+                           static_cast<double *>(tab), static_cast<double *>(dtab));
+    else
+        hipLaunchKernelGGL(k_fill_lin<float>, dim3(blocks_for(n)), dim3(kBlock), 0, s, g, t,
+                           static_cast<float *>(tab), static_cast<float *>(dtab));
     return hipGetLastError();
 }
 

@@ -143,5 +143,6 @@ hipError_t launch_ndft(const NdftArgs &a, bool dbl, bool adjoint, hipStream_t s)
 // ------------------------------------------------------------------ utilities
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_lin(const Geom &g, int t, bool dbl, void *tab, void *dtab, hipStream_t s);
 
 }  // namespace nfft

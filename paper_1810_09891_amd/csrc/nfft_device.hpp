@@ -264,6 +264,7 @@ struct Geom {
     int WM;            // compiled stencil width (>= W)
     int n[kMaxDim];    // grid lengths (1 for unused dimensions); even, not necessarily powers of two
     int p2;            // 1 when every n_t is a power of two (indices wrap with a mask)
+    int lin;           // 1: window factors from the lookup tables (Nodes::lin), not the closed form
     int lgB[kMaxDim];  // log2 of the bin edge per dimension
     int nb[kMaxDim];   // bins per dimension
     int P[kMaxDim];    // padded tile edge B + WM - 1
@@ -348,9 +349,38 @@ struct Nodes {
     int32_t *item_lo;      // [max items] its slice [lo, hi) of the tile's node list
     int32_t *item_hi;
     const double *x;       // caller node array (only used while setting nodes)
+    // window lookup tables (Geom::lin): per dimension, per stencil point s, kLinK + 1 samples
+    // of the factor (lin) and of its derivative (lin_d) at delta = i / kLinK (float or double)
+    const void *lin[kMaxDim];
+    const void *lin_d[kMaxDim];
     int64_t M;
     int chunk_cap;
     int max_chunks;
 };
+
+// Window factors from the lookup tables of the PRE_LIN_PSI strategy (Table 3.2): linear
+// interpolation in the offset delta between the kLinK + 1 samples of stencil point s.
+constexpr int kLinK = 4096;
+template <typename T> __device__ __forceinline__ T lin_lookup(const void *tab, int s, T delta)
+{
+    const T y = delta * T(kLinK);
+    int i = (int)y;
+    i = i < 0 ? 0 : (i > kLinK - 1 ? kLinK - 1 : i);
+    const T f = y - T(i);
+    const T *row = static_cast<const T *>(tab) + (int64_t)s * (kLinK + 1);
+    const T a = row[i], b = row[i + 1];
+    return a + f * (b - a);
+}
+// Factor and derivative of dimension t at stencil point s: the closed form, or the tables.
+template <typename T, bool AllW = true>
+__device__ __forceinline__ T win_value(const Geom &g, const Nodes &nd, int t, T delta, int s)
+{
+    return g.lin ? lin_lookup<T>(nd.lin[t], s, delta) : win_point<T, AllW>(g, t, delta, s);
+}
+template <typename T, bool AllW = true>
+__device__ __forceinline__ T win_value_d(const Geom &g, const Nodes &nd, int t, T delta, int s)
+{
+    return g.lin ? lin_lookup<T>(nd.lin_d[t], s, delta) : win_point_d<T, AllW>(g, t, delta, s);
+}
 
 }  // namespace nfft

@@ -445,6 +445,11 @@ static void layout_workspace(nfft_plan_s *p)
     // window factors, padded so that reads of WM (>= 2m+2) factors past the last node's
     // record stay inside the workspace
     p->off_psi = take(rs * ((size_t)M * p->d * (size_t)(2 * p->m + 2) + 64));
+    for (int t = 0; t < p->d; ++t) {
+        const size_t ntab = p->geom.lin ? (size_t)(2 * p->m + 2) * (kLinK + 1) : 0;
+        p->off_lin[t] = take(rs * ntab);
+        p->off_lin_d[t] = take(rs * ntab);
+    }
     // one padded tile per work item for the tile spreading kernels; owner-computes plans
     // need tile lists, work items and one partial tile per item instead
     p->off_scratch = take(p->geom.own ? 0 : cs * (size_t)p->geom.Ptot * (size_t)p->max_chunks);
@@ -527,6 +532,7 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
     g.W = 2 * m + 2;
     g.WM = wm_bucket(m);
     p->WM = g.WM;
+    g.lin = (flags & NFFT_PRE_LIN_PSI) ? 1 : 0;
     g.p2 = 1;
     for (int t = 0; t < kMaxDim; ++t) {
         g.n[t] = (int)p->n[t];
@@ -593,6 +599,10 @@ Nodes plan_node_view(nfft_plan_s *p)
     nd.chunk_len = reinterpret_cast<int32_t *>(ws + p->off_chunk_len);
     nd.counters = reinterpret_cast<int32_t *>(ws + p->off_counters);
     nd.psi = ws + p->off_psi;
+    for (int t = 0; t < kMaxDim; ++t) {
+        nd.lin[t] = (p->geom.lin && t < p->d) ? ws + p->off_lin[t] : nullptr;
+        nd.lin_d[t] = (p->geom.lin && t < p->d) ? ws + p->off_lin_d[t] : nullptr;
+    }
     nd.spos = p->spos_used ? reinterpret_cast<int32_t *>(ws + p->off_spos) : nullptr;
     if (p->geom.own) {
         nd.tile_count = reinterpret_cast<int32_t *>(ws + p->off_tile_count);
@@ -745,6 +755,10 @@ static int ensure_tables(nfft_plan_s *p, hipStream_t s)
     if (p->geom.own && hipMemcpyAsync(ws + p->off_tile_order, p->tile_order.data(), 4 * p->tile_order.size(),
                                       hipMemcpyHostToDevice, s) != hipSuccess)
         return NFFT_ERR_HIP;
+    if (p->geom.lin)
+        for (int t = 0; t < p->d; ++t)
+            if (launch_fill_lin(p->geom, t, p->dbl, ws + p->off_lin[t], ws + p->off_lin_d[t], s) != hipSuccess)
+                return NFFT_ERR_HIP;
     // the host tables stay alive in the plan; wait so a later destroy cannot race the copy
     if (hipStreamSynchronize(s) != hipSuccess)
         return NFFT_ERR_HIP;

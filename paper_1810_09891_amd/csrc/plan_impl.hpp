@@ -42,6 +42,7 @@ struct nfft_plan_s {
     size_t off_bin_count = 0, off_bin_start = 0, off_bin_chunk = 0;
     size_t off_chunk_bin = 0, off_chunk_first = 0, off_chunk_len = 0;
     size_t off_counters = 0, off_xcopy = 0, off_scratch = 0, off_psi = 0;
+    size_t off_lin[nfft::kMaxDim] = {0, 0, 0}, off_lin_d[nfft::kMaxDim] = {0, 0, 0};  // NFFT_PRE_LIN_PSI tables
     size_t off_spos = 0;  // only when 2-D spreading runs in registers (spos_used)
     bool spos_used = false;
     // owner-computes 3-D spreading (geom.own): tile lists, work items, partial-tile slots

@@ -129,12 +129,12 @@ __device__ __forceinline__ void window_row(T delta, const Geom &g, int t, T *w)
 }
 
 template <typename T, int WM, bool AllW = true>
-__device__ __forceinline__ void window_row_d(T delta, const Geom &g, int t, T *w, T *dw)
+__device__ __forceinline__ void window_row_d(T delta, const Geom &g, const Nodes &nd, int t, T *w, T *dw)
 {
 #pragma unroll
     for (int s = 0; s < WM; ++s) {
-        w[s] = s < g.W ? win_point<T, AllW>(g, t, delta, s) : T(0);
-        dw[s] = s < g.W ? win_point_d<T, AllW>(g, t, delta, s) : T(0);
+        w[s] = s < g.W ? win_value<T, AllW>(g, nd, t, delta, s) : T(0);
+        dw[s] = s < g.W ? win_value_d<T, AllW>(g, nd, t, delta, s) : T(0);
     }
 }
 

@@ -422,3 +422,18 @@ def test_plan_tune_rejects_missing_arguments(lib):
     assert lib.nfft_plan_tune(2, Na, 100, None, 6, 1, 0, None, None, None, ctypes.byref(out), None) == ARG
     assert lib.nfft_plan_tune(2, Na, 100, None, 6, 1, 0, ctypes.c_void_p(256), None, None, None, None) == ARG
 
+
+
+def test_lin_psi_flag_reserves_its_tables(lib):
+    """NFFT_PRE_LIN_PSI is accepted, reported, and its tables (2 (2m+2) 4097 reals per
+    dimension) are part of the workspace."""
+    sizes = []
+    for flags in (0, _lib.NFFT_PRE_LIN_PSI):
+        st, h = create(lib, (32, 32), 500, None, 6, 2, flags)
+        assert st == OK
+        info = _lib.PlanInfo()
+        assert lib.nfft_plan_get_info(h, ctypes.byref(info)) == OK
+        assert (info.flags & _lib.NFFT_PRE_LIN_PSI) == flags
+        sizes.append(info.workspace_bytes)
+        assert lib.nfft_plan_destroy(h) == OK
+    assert sizes[1] - sizes[0] >= 2 * 2 * 14 * 4097 * 8

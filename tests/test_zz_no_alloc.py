@@ -61,3 +61,32 @@ def test_noalloc_batch_trafo_matches_batch_trafo(dtype):
             assert parity_err(O.nfft_trafo(c["x"], c["fhat"], p.n, p.m), a) < TOL[dtype]
     for h in raw:
         assert lib.nfft_batch_destroy(h) == 0
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_noalloc_batch_with_mixed_radix_grids(dtype):
+    """Plans whose grids are not powers of two (their own launch groups, mixed-radix FFT
+    passes) through the allocation-free entry point, against nfft_batch_trafo."""
+    lib = _lib.load()
+    specs = [((64, 44), (130, 90), 2500), ((100,), (126,), 900), ((24, 24, 24), (48, 48, 48), 1200),
+             ((32, 32), (64, 64), 1000)]
+    plans, cases = [], []
+    for i, (N, n, M) in enumerate(specs):
+        c = W.small_case(len(N), N, M, seed=760 + i)
+        p = Plan(N, M, n=n, m=6, dtype=dtype)
+        p.set_nodes(dev(c["x"], torch.float64))
+        plans.append(p)
+        cases.append(c)
+    h = _raw_batch(lib, plans)
+    announce("noalloc batch mixed radix", dtype)
+    fh = [dev(c["fhat"], dtype) for c in cases]
+    fo = [torch.empty(p.M, dtype=dtype, device="cuda") for p in plans]
+    ip = (ctypes.c_void_p * len(plans))(*[t.data_ptr() for t in fh])
+    op = (ctypes.c_void_p * len(plans))(*[t.data_ptr() for t in fo])
+    st = lib.nfft_batch_trafo_noalloc(h, ip, op, None)
+    assert st == 0, _lib.STATUS.get(st, st)
+    torch.cuda.synchronize()
+    ref = Batch(plans).trafo(fh)
+    for a, b in zip(fo, ref):
+        assert np.array_equal(host(a), host(b))
+    assert lib.nfft_batch_destroy(h) == 0

@@ -106,15 +106,16 @@ def test_batch_every_launch_shape_gives_the_same_result():
 
 
 def test_batch_group_mixing_spreading_kernels():
-    """One launch group (d = 2, m = 4, complex64) with a plan whose bins are too small for
-    the spreading kernel that keeps tile columns in registers (N = 8^2, 16-cell bins) next
-    to plans that would use it alone: the group spreads with the tile kernel, and every plan
-    matches its own transforms and the oracle."""
+    """Plans of one kind (d = 2, m = 4, complex64): one with 32-cell bins, which the
+    spreading kernel that keeps tile columns in registers takes, and two with 16-cell bins
+    (N = 8^2, 8 x 32), which it does not: the batch puts them in separate launch groups, so
+    the first keeps the register kernel, and every plan matches its own transforms and the
+    oracle."""
     announce("batch mixed spreading kernels")
     specs = [((64, 64), 3000, 4, "uniform"), ((8, 8), 300, 4, "uniform"), ((8, 32), 500, 4, "clustered")]
     plans, cases = setup_plans(specs, C64, seed0=140)
     b = Batch(plans)
-    assert b.info.groups == 1
+    assert b.info.groups == 2
     fb, hb = batched(b, cases, C64)
     fp, hp = per_plan(plans, cases, C64)
     for i, (p, c) in enumerate(zip(plans, cases)):

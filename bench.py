@@ -44,8 +44,11 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue rate of one MI355X: 256 CUs x 64 lanes x 2.4 GHz lane-slots per second.  A
 # (node, cell) pair of the window steps is one complex x real multiply-add: two FP64 FMAs
 # (complex128) or two FP32 FMAs (complex64; one packed FMA if packed FP32 were used, which
-# this build does not emit).
+# the library's code does not emit).
 VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+# dense matrix-core peaks of one MI355X (FP64 and FP32 MFMA)
+MFMA_F64_FLOPS = 78.6e12
+MFMA_F32_FLOPS = 157.3e12
 # LDS read ceiling of one MI355X measured with _build/lds_bw (conflict-free
 # 8-byte reads issued as separate ds_read_b64, all 256 CUs; the highest 8-byte read rate it
 # measures): the bound of the interpolation kernel (an 8-byte LDS read per stencil point)
@@ -112,9 +115,15 @@ def valu_seconds(d, M, m, dbl):
     return M * (2 * m + 2) ** d * 2 / VALU_SLOTS_PER_S
 
 
+def mfma_seconds(d, M, m, dbl):
+    """The same multiply-adds on the matrix cores at their dense peak (FP64 78.6 TFLOP/s,
+    FP32 157.3 TFLOP/s): the floor of the 3-D spreading by output tiles."""
+    return M * (2 * m + 2) ** d * 4 / (MFMA_F64_FLOPS if dbl else MFMA_F32_FLOPS)
+
+
 # rocprofv3 kernel names of the library's launch labels, in order of preference
 ROCPROF_NAME = {"interp": ("k_interp3", "k_interp_nodes"),
-                "spread_tiles": ("k_spread_cols", "k_spread_tiles"), "spread_own": ("k_spread_own",),
+                "spread_tiles": ("k_spread_cols", "k_spread_tiles"), "spread_own": ("k_spread_own_mx",),
                 "spread_fold": ("k_fold",), "grad_x": ("k_grad_x",)}
 
 
@@ -598,11 +607,14 @@ def roofline_entry(name, avg_ms, d, N, n, M, m, cbytes, dbl):
         e["hbm_frac"] = round(bts / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         if name in ("interp", "spread_own", "spread_tiles", "grad_x"):
             t_hbm = bts / (HBM_PEAK_GBS * 1e9)
-            t_valu = valu_seconds(d, M, m, dbl)
             e["t_hbm_us"] = round(t_hbm * 1e6, 2)
-            e["t_valu_us"] = round(t_valu * 1e6, 2)
-            e["binding"] = "valu" if t_valu > t_hbm else "hbm"
-            e["binding_frac"] = round(max(t_hbm, t_valu) / (avg_ms * 1e-3), 4)
+            if name == "spread_own":  # runs on the matrix cores
+                t_ar, unit = mfma_seconds(d, M, m, dbl), "mfma"
+            else:
+                t_ar, unit = valu_seconds(d, M, m, dbl), "valu"
+            e["t_%s_us" % unit] = round(t_ar * 1e6, 2)
+            e["binding"] = unit if t_ar > t_hbm else "hbm"
+            e["binding_frac"] = round(max(t_hbm, t_ar) / (avg_ms * 1e-3), 4)
     return e
 
 
@@ -721,13 +733,19 @@ def main():
                 if entry is not None and "bytes_per_launch" in entry:
                     traffic = entry["bytes_per_launch"]
                     break
+    if e.get("binding") == "mfma":
+        # a matrix-core contraction: algorithmic flops per launch against the FP64 MFMA peak
+        flops = M * (2 * 6 + 2) ** 3 * 4
+        achieved = flops / (e["avg_ms"] * 1e-3) / 1e12
+        bound = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_F64_FLOPS / 1e12,
+                 "unit": "TFLOP/s", "frac": round(achieved * 1e12 / MFMA_F64_FLOPS, 4), "algorithmic_flops": flops,
+                 "hbm_GBs": e.get("hbm_GBs"), "hbm_frac": e.get("hbm_frac")}
+    else:
+        bound = {"bound": "hbm", "achieved": e.get("hbm_GBs"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": e.get("hbm_frac")}
     roofline = {
-        "bound": "hbm",
+        **bound,
         "kernel": dom,
-        "achieved": e.get("hbm_GBs"),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": e.get("hbm_frac"),
         "traffic": traffic,
         "algorithmic_bytes": e.get("algorithmic_bytes"),
         "avg_launch_ms": e["avg_ms"],
@@ -735,9 +753,11 @@ def main():
         "binding_frac": e.get("binding_frac"),
         "t_hbm_us": e.get("t_hbm_us"),
         "t_valu_us": e.get("t_valu_us"),
+        "t_mfma_us": e.get("t_mfma_us"),
         "byte_model": "window steps: M (8 d + c) + |I_n| c bytes per launch (FP64 nodes, values, grid once); "
                       "FFT passes: nonzero input + output of the pass",
         "valu_model": "(2m+2)^d (node, cell) pairs x 2 FMA slots / (256 CUs x 64 lanes x 2.4 GHz)",
+        "mfma_model": "(2m+2)^d (node, cell) pairs x 4 flops / dense MFMA peak (FP64 78.6, FP32 157.3 TFLOP/s)",
     }
     out = {
         "metric": METRIC,

@@ -4,29 +4,25 @@
 // no floating-point atomics are needed).
 //
 // The grid is cut into tiles of 16 x 16 x 16 cells.  A workgroup of four waves holds one
-// tile in registers: wave w owns the 8 x 8 block of (dimension 1, dimension 2) columns at
-// (8 (w >> 1), 8 (w & 1)), a lane one column, and the 16 cells of its column along
-// dimension 0 are its accumulators.  A node whose stencil starts at tile-relative cell
-// (o0, o1, o2) adds
-//     f_j psi_1[c1 - o1] psi_2[c2 - o2] * psi_0[r - o0]
-// to row r of column (c1, c2): the lane forms the product of its two column factors and f_j
-// once per node, and the row factors -- the same for every lane -- enter the multiply-adds,
-// one per real part per row.
+// tile in registers: wave w owns the 16 rows (dimension 0) of the 8 x 8 block of
+// (dimension 1, dimension 2) columns at (8 (w >> 1), 8 (w & 1)).  A node whose stencil starts
+// at tile-relative cell (o0, o1, o2) adds the outer product of its row factors
+// psi_0[r - o0] and its column values f_j psi_1[c1 - o1] psi_2[c2 - o2] to the block, so the
+// block is a real (16 x K) by (K x 64 complex) matrix product over the K nodes that reach it,
+// which the matrix cores take four nodes at a time.
 //
 // The node precomputation lists, for every tile, the nodes whose stencils reach it, each
 // entry with its tile offsets and the mask of the waves' blocks it reaches (the bins around
 // the tile in bin order, nodes that reach it only).  A work item is a slice of at most `cap`
 // entries of one tile; items are ordered along a Morton curve of their tiles, so that the
 // items that read one node's window factors run close together.  An item stages its entries
-// in batches (window factors into LDS), and each wave takes a batch's entries row offset by
-// row offset (one ballot per offset), so that every accumulator index is a constant of an
-// unrolled sequence.  A tile with one item writes the grid directly; the items of a split
-// tile (a dense region) write partial tiles to their own slots and a second kernel adds the
-// slots in item order.  In complex64 a cell's contributions are summed in two levels -- at
-// most one batch into a batch accumulator, whose value is then added to the running total --
-// so that the FP32 rounding error of a cell that many nodes reach grows with the number of
-// batches rather than of nodes.  Every sum has a fixed order.
-#include <utility>
+// in batches (window factors into LDS); each wave compacts the batch's entries that reach
+// its block and multiplies them in.  A tile with one item writes the grid directly; the
+// items of a split tile (a dense region) write partial tiles to their own slots and a second
+// kernel adds the slots in item order.  In complex64 a cell's contributions are summed in two
+// levels -- one batch, then the running total -- so that the FP32 rounding error of a cell
+// that many nodes reach grows with the number of batches rather than of nodes.  Every sum
+// has a fixed order.
 
 #include "window_common.hpp"
 
@@ -271,19 +267,19 @@ template <typename T, int W> struct OwnLds {
     int pos[kOwnNB];
 };
 
-// Stage entries q .. q + nb - 1 of the tile's list (ent): packed offsets, sorted positions,
-// window factors, and with `fs` (node values in sorted order) the values.  Every load is
-// issued before the first LDS store; ends with a barrier.
+// Stage entries q, q + stride, ..., q + (nb - 1) stride of the tile's list (ent): packed
+// offsets, sorted positions, window factors, and with `fs` (node values in sorted order) the
+// values.  Every load is issued before the first LDS store; ends with a barrier.
 template <typename T, int W>
 __device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, const int2 *__restrict__ ent, int q,
-                                          int nb, const Cplx<T> *__restrict__ fs)
+                                          int nb, const Cplx<T> *__restrict__ fs, int stride = 1)
 {
     using R = OwnRec<T, W>;
     const T *__restrict__ psi = static_cast<const T *>(nd.psi);
     int2 e{0, 0};
     Cplx<T> fv{T(0), T(0)};
     if ((int)threadIdx.x < nb) {
-        e = ent[q + threadIdx.x];
+        e = ent[q + (int)threadIdx.x * stride];
         if (fs)
             fv = fs[e.x];
     }
@@ -295,7 +291,7 @@ __device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, cons
         const int k = idx / (3 * W);
         const int rr = idx - k * (3 * W);
         const bool ok = k < nb;
-        const int p = ent[q + (ok ? k : 0)].x;
+        const int p = ent[q + (ok ? k : 0) * stride].x;
         v[j] = psi[(int64_t)p * (3 * W) + (ok ? rr : 0)];
         const int t = rr / W;
         const int s = rr - t * W;
@@ -314,55 +310,169 @@ __device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, cons
     __syncthreads();
 }
 
-// The batch walk of one wave: lane k holds the packed entry k of the batch (0 past the
-// batch).  For every row offset O (a template constant) one ballot selects the entries
-// with that offset whose stencil reaches the wave's block, and `body.run<O>(k, o1, o2)`
-// handles them in batch order.
-template <int O, typename Body>
-__device__ __forceinline__ void own_walk_row(int emeta, int wave, Body &body)
+// ------------------------------------------------------------------ spreading on matrix cores
+
+// A wave's 16 x 64 block of a tile (16 rows along dimension 0 by its 8 x 8 columns) is the
+// sum over the nodes k that reach it of the outer product of the node's row factors
+// a_k[i] = psi_0[i - o0_k] and its column values b_k[c] = f_k psi_1[c1 - o1_k] psi_2[c2 - o2_k]:
+// a real 16 x K by K x 64 complex product, K the number of such nodes.  The 16 x 16 x 4 MFMA
+// takes four nodes per step: operand A (16 x 4) holds the row factors (lane l: row l % 16 of
+// node l / 16), operand B (4 x 16) sixteen of the columns (lane l: column l % 16 of node l / 16),
+// and eight products (four column groups, real and imaginary parts) cover the block.  Lane l
+// holds output column l % 16 in four elements r: rows l / 16 + 4 r of the FP64 product and
+// rows 4 (l / 16) + r of the FP32 one (measured on gfx950).
+template <typename T> struct MxVec;
+template <> struct MxVec<double> {
+    typedef double type __attribute__((ext_vector_type(4)));
+    // output row of element r in lane l
+    static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct MxVec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+__device__ __forceinline__ MxVec<double>::type mx_step(double a, double b, MxVec<double>::type c)
 {
-    const bool mine = emeta != 0 && (emeta & 255) - 64 == O && ((emeta >> (24 + wave)) & 1);
-    uint64_t bits = __ballot(mine);
-    while (bits) {
-        const int k = __builtin_ctzll(bits);
-        bits &= bits - 1;
-        const int meta = __builtin_amdgcn_readlane(emeta, k);
-        body.template run<O>(k, ((meta >> 8) & 255) - 64, ((meta >> 16) & 255) - 64);
-    }
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ MxVec<float>::type mx_step(float a, float b, MxVec<float>::type c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int LO, typename Body, int... Is>
-__device__ __forceinline__ void own_walk(std::integer_sequence<int, Is...>, int emeta, int wave, Body &body)
+// The MFMA form of the entry walk: the entries of the batch that reach the wave's block,
+// compacted into `list` (in batch order), four per step.  Column group s of the block holds
+// columns c1 = 8 (wave >> 1) + 2 s + (j >> 3), c2 = 8 (wave & 1) + (j & 7), j = 0 .. 15.
+template <typename T, int W>
+__device__ __forceinline__ void own_mx_batch(const T *__restrict__ psi, const Cplx<T> *__restrict__ val,
+                                             const int *__restrict__ meta, const int *__restrict__ list, int cnt,
+                                             int lane, int wave, typename MxVec<T>::type (&acc)[8])
 {
-    (own_walk_row<LO + Is>(emeta, wave, body), ...);
-}
-
-// ------------------------------------------------------------------ spreading
-
-// Spreading of one entry into the wave's block: acc[O + s] += psi_0[s] (f_j psi_1 psi_2).
-template <typename T, int T0, int W> struct SpreadBody {
-    const T *psi;
-    const Cplx<T> *val;
-    int c1, c2;
-    T (&ax)[T0];
-    T (&ay)[T0];
-    template <int O> __device__ __forceinline__ void run(int k, int o1, int o2)
-    {
-        using R = OwnRec<T, W>;
-        const T *rec = psi + k * R::REC;
-        const T w12 = rec[R::D1 + 8 + c1 - o1] * rec[R::D2 + 8 + c2 - o2];
-        const Cplx<T> fv = val[k];
-        const T wx = fv.x * w12;
-        const T wy = fv.y * w12;
+    using R = OwnRec<T, W>;
+    const int k = lane >> 4, j = lane & 15;
+    const int c1b = (wave >> 1) * 8 + (j >> 3);
+    const int c2 = (wave & 1) * 8 + (j & 7);
+    for (int q = 0; q < cnt; q += 4) {
+        const bool ok = q + k < cnt;
+        const int e = list[ok ? q + k : q];
+        const int em = meta[e];
+        const int o0 = (em & 255) - 64, o1 = ((em >> 8) & 255) - 64, o2 = ((em >> 16) & 255) - 64;
+        const T *rec = psi + e * R::REC;
+        const int s0 = j - o0;  // row j of operand A
+        const T a0 = rec[min(max(s0, 0), W - 1)];
+        const T a = ok && s0 >= 0 && s0 < W ? a0 : T(0);
+        const Cplx<T> fv = val[e];
+        const T w2 = rec[R::D2 + 8 + c2 - o2];
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
-            if (O + s >= 0 && O + s < T0) {
-                ax[O + s] = fma(rec[s], wx, ax[O + s]);
-                ay[O + s] = fma(rec[s], wy, ay[O + s]);
-            }
+        for (int g = 0; g < 4; ++g) {
+            const T w = rec[R::D1 + 8 + c1b + 2 * g - o1] * w2;
+            acc[2 * g] = mx_step(a, fv.x * w, acc[2 * g]);
+            acc[2 * g + 1] = mx_step(a, fv.y * w, acc[2 * g + 1]);
         }
     }
-};
+}
+
+template <typename T, int W> constexpr int own_mx_waves() { return 3; }
+
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock, (own_mx_waves<T, W>())) void k_spread_own_mx(Geom g, Nodes nd,
+                                                                              const Cplx<T> *__restrict__ fs,
+                                                                              Cplx<T> *__restrict__ grid,
+                                                                              Cplx<T> *__restrict__ scratch)
+{
+    using C = Cplx<T>;
+    using V = typename MxVec<T>::type;
+    constexpr int T0 = kOwnTile0, T1 = kOwnTile12, T2 = kOwnTile12;
+    constexpr int TC = T0 * T1 * T2;
+    static_assert(T0 == 16 && T1 == 16 && T2 == 16, "a wave's block is 16 rows by 8 x 8 columns");
+    __shared__ __align__(16) OwnLds<T, W> L;
+    __shared__ int s_list[kOwnWaves][kOwnNB];
+
+    const int nitems = nd.counters[2];
+    const int nwg = min((int)gridDim.x, nitems);
+    if ((int)blockIdx.x >= nwg)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int2 *__restrict__ entries = reinterpret_cast<const int2 *>(nd.entries);
+
+    for (int i = threadIdx.x; i < kOwnNB * OwnRec<T, W>::REC; i += kBlock)
+        L.psi[i] = T(0);
+
+    for (int it = xcd_local_id(blockIdx.x, nwg); it < nitems; it += nwg) {
+        const int tile = nd.item_tile[it];
+        const int lo = nd.item_lo[it], hi = nd.item_hi[it];
+        const int2 *ent = entries + nd.tile_entry[tile];
+        int ti[3];
+        own_tile_coords(g, tile, ti);
+        // complex64 sums a batch's contributions first and adds them to the running total,
+        // so that the rounding error of a cell grows with the number of batches, not nodes
+        constexpr bool kTwoLevel = sizeof(T) == 4;
+        V acc[8], tot[kTwoLevel ? 8 : 1];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            acc[b] = V{T(0), T(0), T(0), T(0)};
+            if constexpr (kTwoLevel)
+                tot[b] = V{T(0), T(0), T(0), T(0)};
+        }
+        // batch b takes entries lo + b, lo + b + nbat, ...: entries in list order are nodes of
+        // neighbouring bins, which reach the same blocks, so that consecutive entries would
+        // give one wave the whole batch while the others wait at the next barrier
+        const int cnt = hi - lo;
+        const int nbat = (cnt + kOwnNB - 1) / kOwnNB;
+        for (int b = 0; b < nbat; ++b) {
+            const int nb = (cnt - b + nbat - 1) / nbat;
+            __syncthreads();  // the previous batch is consumed
+            own_stage<T, W>(nd, L, ent, lo + b, nb, fs, nbat);
+            const int emeta = lane < nb ? L.meta[lane] : 0;
+            const bool mine = emeta != 0 && ((emeta >> (24 + wave)) & 1);
+            const uint64_t bits = __ballot(mine);
+            if (mine)
+                s_list[wave][__popcll(bits & ((1ull << lane) - 1ull))] = lane;
+            // each wave reads only its own list: the LDS operations of one wave complete in
+            // order, so a wave-level fence suffices
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            own_mx_batch<T, W>(L.psi, L.val, L.meta, s_list[wave], __popcll(bits), lane, wave, acc);
+            if constexpr (kTwoLevel) {
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    tot[b] += acc[b];
+                    acc[b] = V{T(0), T(0), T(0), T(0)};
+                }
+            }
+        }
+        if constexpr (kTwoLevel) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                acc[b] = tot[b];
+        }
+        // lane l holds column j = l % 16 of every column group, rows MxVec<T>::row(l, r)
+        const int j = lane & 15;
+        const int c1b = (wave >> 1) * 8 + (j >> 3);
+        const int c2 = (wave & 1) * 8 + (j & 7);
+        const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
+        const int nsplit = own_items_of(g, nd.tile_count[tile]);
+        if (nsplit == 1) {
+            const int64_t row = (int64_t)g.n[1] * g.n[2];
+            const int64_t base = ((int64_t)org0 * g.n[1] + org1 + c1b) * g.n[2] + org2 + c2;
+#pragma unroll
+            for (int gr = 0; gr < 4; ++gr)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    grid[base + MxVec<T>::row(lane, r) * row + 2 * gr * g.n[2]] = C{acc[2 * gr][r], acc[2 * gr + 1][r]};
+        } else {
+            C *slot = scratch + (int64_t)it * TC;
+#pragma unroll
+            for (int gr = 0; gr < 4; ++gr)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    slot[(MxVec<T>::row(lane, r) * T1 + c1b + 2 * gr) * T2 + c2] = C{acc[2 * gr][r], acc[2 * gr + 1][r]};
+        }
+    }
+}
 
 // Node values in sorted order (read once per entry by the spreading kernel).
 template <typename T>
@@ -373,96 +483,10 @@ __global__ __launch_bounds__(kBlock) void k_own_gather(Nodes nd, const Cplx<T> *
         fs[p] = f[nd.perm[p]];
 }
 
-// Waves per SIMD the spreading kernel aims at (register budget 512 / waves).  The walk is
-// latency-bound, so occupancy pays for a few spilled registers: measured at m = 6 (3-D
-// radial, 2,097,152 nodes), complex64 3.89 / 3.72 / 3.73 ms at 3 / 4 / 4 waves (the last
-// with complex128 also at 4), complex128 4.84 / 4.30 / 4.37 ms at 2 / 3 / 4 waves.
-template <typename T, int W> constexpr int own_waves() { return W > 14 ? 2 : (sizeof(T) == 4 ? 4 : 3); }
-
-template <typename T, int T0, int W>
-__global__ __launch_bounds__(kBlock, (own_waves<T, W>())) void k_spread_own(Geom g, Nodes nd, const Cplx<T> *__restrict__ fs,
-                                                        Cplx<T> *__restrict__ grid, Cplx<T> *__restrict__ scratch)
-{
-    using C = Cplx<T>;
-    using R = OwnRec<T, W>;
-    constexpr int T1 = kOwnTile12, T2 = kOwnTile12;
-    constexpr int TC = T0 * T1 * T2;
-    __shared__ __align__(16) OwnLds<T, W> L;
-
-    const int nitems = nd.counters[2];
-    const int nwg = min((int)gridDim.x, nitems);
-    if ((int)blockIdx.x >= nwg)
-        return;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c1 = (wave >> 1) * 8 + (lane >> 3);
-    const int c2 = (wave & 1) * 8 + (lane & 7);
-    const int2 *__restrict__ entries = reinterpret_cast<const int2 *>(nd.entries);
-
-    for (int i = threadIdx.x; i < kOwnNB * R::REC; i += kBlock)
-        L.psi[i] = T(0);
-
-    for (int it = xcd_local_id(blockIdx.x, nwg); it < nitems; it += nwg) {
-        const int tile = nd.item_tile[it];
-        const int lo = nd.item_lo[it], hi = nd.item_hi[it];
-        const int2 *ent = entries + nd.tile_entry[tile];
-        int ti[3];
-        own_tile_coords(g, tile, ti);
-        constexpr bool kTwoLevel = sizeof(T) == 4;
-        T ax[T0], ay[T0];
-        T tx[kTwoLevel ? T0 : 1], ty[kTwoLevel ? T0 : 1];
-#pragma unroll
-        for (int r = 0; r < T0; ++r) {
-            ax[r] = T(0);
-            ay[r] = T(0);
-            if constexpr (kTwoLevel) {
-                tx[r] = T(0);
-                ty[r] = T(0);
-            }
-        }
-        for (int q = lo; q < hi; q += kOwnNB) {
-            const int nb = min(kOwnNB, hi - q);
-            __syncthreads();  // the previous batch is consumed
-            own_stage<T, W>(nd, L, ent, q, nb, fs);
-            const int emeta = lane < nb ? L.meta[lane] : 0;
-            SpreadBody<T, T0, W> body{L.psi, L.val, c1, c2, ax, ay};
-            own_walk<-(W - 1)>(std::make_integer_sequence<int, W - 1 + T0>{}, emeta, wave, body);
-            if constexpr (kTwoLevel) {
-#pragma unroll
-                for (int r = 0; r < T0; ++r) {
-                    tx[r] += ax[r];
-                    ty[r] += ay[r];
-                    ax[r] = T(0);
-                    ay[r] = T(0);
-                }
-            }
-        }
-        if constexpr (kTwoLevel) {
-#pragma unroll
-            for (int r = 0; r < T0; ++r) {
-                ax[r] = tx[r];
-                ay[r] = ty[r];
-            }
-        }
-        const int org0 = ti[0] * T0, org1 = ti[1] * T1, org2 = ti[2] * T2;
-        const int nsplit = own_items_of(g, nd.tile_count[tile]);
-        if (nsplit == 1) {
-            const int64_t base = ((int64_t)org0 * g.n[1] + org1 + c1) * g.n[2] + org2 + c2;
-            const int64_t row = (int64_t)g.n[1] * g.n[2];
-#pragma unroll
-            for (int r = 0; r < T0; ++r)
-                grid[base + r * row] = C{ax[r], ay[r]};
-        } else {
-            C *slot = scratch + (int64_t)it * TC;
-#pragma unroll
-            for (int r = 0; r < T0; ++r)
-                slot[(r * T1 + c1) * T2 + c2] = C{ax[r], ay[r]};
-        }
-    }
-}
-
-// Split tiles: the sum of their items' partial tiles, in item order.  Workgroup (tile, y)
-// takes kBlock cells of the tile; the partial tiles' loads are issued four at a time.
+// Split tiles: the sum of their items' partial tiles, in item order, accumulated in FP64 (a
+// dense complex64 tile has tens of partial tiles, and this level of the sum then adds no
+// FP32 rounding).  Workgroup (tile, y) takes kBlock cells of the tile; the partial tiles'
+// loads are issued four at a time.
 template <typename T, int T0>
 __global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cplx<T> *__restrict__ scratch,
                                                       Cplx<T> *__restrict__ grid)
@@ -482,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cpl
     const int cc1 = (c / T2) % T1;
     const int cc2 = c % T2;
     const C *src = scratch + (int64_t)first * TC + c;
-    C acc = src[0];
+    double ax = src[0].x, ay = src[0].y;
     int i = 1;
     for (; i + 4 <= k; i += 4) {
         C v[4];
@@ -491,16 +515,16 @@ __global__ __launch_bounds__(kBlock) void k_own_fold(Geom g, Nodes nd, const Cpl
             v[q] = src[(int64_t)(i + q) * TC];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            acc.x += v[q].x;
-            acc.y += v[q].y;
+            ax += (double)v[q].x;
+            ay += (double)v[q].y;
         }
     }
     for (; i < k; ++i) {
         const C v = src[(int64_t)i * TC];
-        acc.x += v.x;
-        acc.y += v.y;
+        ax += (double)v.x;
+        ay += (double)v.y;
     }
-    grid[((int64_t)(ti[0] * T0 + r) * g.n[1] + ti[1] * T1 + cc1) * g.n[2] + ti[2] * T2 + cc2] = acc;
+    grid[((int64_t)(ti[0] * T0 + r) * g.n[1] + ti[1] * T1 + cc1) * g.n[2] + ti[2] * T2 + cc2] = C{(T)ax, (T)ay};
 }
 
 inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -527,7 +551,7 @@ hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const voi
         hipLaunchKernelGGL(k_own_gather<double>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, nd,
                            static_cast<const C *>(f), static_cast<C *>(fs));
 #define OWN_CASE(WMV)                                                                                       \
-    hipLaunchKernelGGL((k_spread_own<double, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,      \
+    hipLaunchKernelGGL((k_spread_own_mx<double, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,              \
                        static_cast<const C *>(fs), static_cast<C *>(grid), static_cast<C *>(scratch))
         NFFT_WM_SWITCH(g.WM, OWN_CASE)
 #undef OWN_CASE
@@ -536,7 +560,7 @@ hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const voi
         hipLaunchKernelGGL(k_own_gather<float>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, nd,
                            static_cast<const C *>(f), static_cast<C *>(fs));
 #define OWN_CASE(WMV)                                                                                       \
-    hipLaunchKernelGGL((k_spread_own<float, kOwnTile0, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,       \
+    hipLaunchKernelGGL((k_spread_own_mx<float, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,               \
                        static_cast<const C *>(fs), static_cast<C *>(grid), static_cast<C *>(scratch))
         NFFT_WM_SWITCH(g.WM, OWN_CASE)
 #undef OWN_CASE

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+from error_scale import adjoint_errors
 from gpu_util import TOL, announce, dev, host, parity_err
 from oracle import oracle as O
 from paper_1810_09891_amd import Plan, workloads as W
@@ -133,8 +134,7 @@ def test_spread_by_output_tiles_3d(case, dtype, m):
     N, M, kind = case
     if dtype == C64 and kind == "clustered":
         # complex64 sums in FP32: the rounding error grows with the number of nodes that
-        # reach one cell (here tens of thousands within a few cells), and the deconvolution
-        # of the adjoint amplifies it at high frequencies, more so for wider windows
+        # reach one cell (here tens of thousands within a few cells)
         M = min(M, 30000 if m <= 6 else 15000)
     c = W.small_case(3, N, M, seed=500 + M % 97 + m, kind=kind)
     announce("owner tiles", N, M, kind, dtype, m)
@@ -149,7 +149,18 @@ def test_spread_by_output_tiles_3d(case, dtype, m):
     h1 = host(p.adjoint(fv))
     h2 = host(p.adjoint(fv))
     assert np.array_equal(h1, h2)
-    assert parity_err(O.nfft_adjoint(c["x"], c["f"], N, n, m), h1) < TOL[dtype]
+    ref = O.nfft_adjoint(c["x"], c["f"], N, n, m)
+    if dtype == C128:
+        assert parity_err(ref, h1) < TOL[dtype]
+    else:
+        # the deconvolution weights w_k = 1 / (n phi_hat(k)) of a 3-D grid at n = 2N span
+        # up to 750x (m = 8) between the centre and the corners of I_N, so the plain relative
+        # error of complex64 results is set by the FP32 rounding of a few corner frequencies
+        # and changes several-fold with the summation order; the relative error of
+        # y = F^H B^T f and its element-wise form (error_scale) are the measures in which the
+        # last step is well-conditioned
+        e2, emax = adjoint_errors(c["x"], c["f"], N, n, m, h1, ref=ref)
+        assert e2 < TOL[dtype] and emax < 2e-5, (e2, emax)
 
 
 def test_edge_nodes_and_tiny_grids():

@@ -69,5 +69,11 @@ def test_bench_byte_model():
     assert ab("fft_adj_deconv", 3, (128,) * 3, (256,) * 3, 1, 8) == first
     # VALU issue time of the d = 3 window step: 14^3 pairs x 2 slots per node
     assert abs(bench.valu_seconds(3, 2097152, 6, True) - 2097152 * 2744 * 2 / (256 * 64 * 2.4e9)) < 1e-12
-    e = bench.roofline_entry("spread_own", 1.0, 3, (128,) * 3, (256,) * 3, 2097152, 6, 16, True)
+    e = bench.roofline_entry("interp", 1.0, 3, (128,) * 3, (256,) * 3, 2097152, 6, 16, True)
     assert e["binding"] == "valu" and abs(e["binding_frac"] - 2097152 * 2744 * 2 / (256 * 64 * 2.4e9) / 1e-3) < 1e-3
+    # the 3-D spreading by output tiles runs on the matrix cores: 4 flops per pair at the
+    # dense FP64 (78.6 TFLOP/s) or FP32 (157.3 TFLOP/s) MFMA peak
+    e = bench.roofline_entry("spread_own", 1.0, 3, (128,) * 3, (256,) * 3, 2097152, 6, 16, True)
+    assert e["binding"] == "mfma" and abs(e["binding_frac"] - 2097152 * 2744 * 4 / 78.6e12 / 1e-3) < 1e-4
+    e = bench.roofline_entry("spread_own", 1.0, 3, (128,) * 3, (256,) * 3, 2097152, 6, 8, False)
+    assert abs(e["binding_frac"] - 2097152 * 2744 * 4 / 157.3e12 / 1e-3) < 1e-4

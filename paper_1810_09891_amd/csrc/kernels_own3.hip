@@ -316,9 +316,10 @@ __device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, cons
 // sum over the nodes k that reach it of the outer product of the node's row factors
 // a_k[i] = psi_0[i - o0_k] and its column values b_k[c] = f_k psi_1[c1 - o1_k] psi_2[c2 - o2_k]:
 // a real 16 x K by K x 64 complex product, K the number of such nodes.  The 16 x 16 x 4 MFMA
-// takes four nodes per step: operand A (16 x 4) holds the row factors (lane l: row l % 16 of
-// node l / 16), operand B (4 x 16) sixteen of the columns (lane l: column l % 16 of node l / 16),
-// and eight products (four column groups, real and imaginary parts) cover the block.  Lane l
+// takes four nodes per step: operand A (16 x 4) holds the row factors times the real or the
+// imaginary part of the node values (lane l: row l % 16 of node l / 16), operand B (4 x 16)
+// the column factors of sixteen of the columns (lane l: column l % 16 of node l / 16), and
+// eight products (four column groups, real and imaginary parts) cover the block.  Lane l
 // holds output column l % 16 in four elements r: rows l / 16 + 4 r of the FP64 product and
 // rows 4 (l / 16) + r of the FP32 one (measured on gfx950).
 template <typename T> struct MxVec;
@@ -363,12 +364,15 @@ __device__ __forceinline__ void own_mx_batch(const T *__restrict__ psi, const Cp
         const T a0 = rec[min(max(s0, 0), W - 1)];
         const T a = ok && s0 >= 0 && s0 < W ? a0 : T(0);
         const Cplx<T> fv = val[e];
+        // the node value enters operand A (real and imaginary parts in turn), so operand B is
+        // the real column factor psi_1 psi_2
+        const T ax = a * fv.x, ay = a * fv.y;
         const T w2 = rec[R::D2 + 8 + c2 - o2];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const T w = rec[R::D1 + 8 + c1b + 2 * g - o1] * w2;
-            acc[2 * g] = mx_step(a, fv.x * w, acc[2 * g]);
-            acc[2 * g + 1] = mx_step(a, fv.y * w, acc[2 * g + 1]);
+            acc[2 * g] = mx_step(ax, w, acc[2 * g]);
+            acc[2 * g + 1] = mx_step(ay, w, acc[2 * g + 1]);
         }
     }
 }

@@ -4,6 +4,11 @@ Each ``csrc/*.hip`` file is compiled to an object with hipcc (in parallel) and t
 objects are linked into one shared library that exports the C ABI of
 ``include/nfft_mi355x.h``.  Always rebuilds when called.  (The LDS throughput probe under
 ``calib/`` is measurement tooling and is built by ``profiling.py lds-probe`` instead.)
+
+``build_host_sanitized()`` builds a second copy under ``_build/host_sanitized/`` whose host
+code (plan set-up, workspace layout, batching, tuning caches, argument checks) carries
+AddressSanitizer and UndefinedBehaviorSanitizer; its device code is the ordinary one.  It is
+for host-side tests on the CPU only, loaded with the ASan runtime preloaded.
 """
 import concurrent.futures
 import glob
@@ -65,5 +70,63 @@ def build(verbose=False, jobs=None):
     return LIB
 
 
+HOST_SAN_DIR = os.path.join(ROOT, "_build", "host_sanitized")
+HOST_SAN_LIB = os.path.join(HOST_SAN_DIR, "libnfft_mi355x.so")
+# sanitizers for the host pass only (each flag after -Xarch_host)
+HOST_SAN_FLAGS = ["-Xarch_host", "-O1", "-Xarch_host", "-g", "-Xarch_host", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+
+
+def host_asan_runtime():
+    """The clang ASan runtime that a process loading the host-sanitized library preloads."""
+    hits = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+def build_host_sanitized(jobs=None):
+    """Build ``_build/host_sanitized/libnfft_mi355x.so``; kept when its stamp (a hash of the
+    sources and flags) is current.  Returns the library path."""
+    import hashlib
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*"))) + [os.path.join(ROOT, "include", "nfft_mi355x.h")]
+    h = hashlib.sha256(" ".join(CFLAGS + HOST_SAN_FLAGS).encode())
+    for f in srcs:
+        with open(f, "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    stamp = os.path.join(HOST_SAN_DIR, "stamp")
+    if os.path.exists(HOST_SAN_LIB) and os.path.exists(stamp) and open(stamp).read() == h.hexdigest():
+        return HOST_SAN_LIB
+    os.makedirs(HOST_SAN_DIR, exist_ok=True)
+    hip = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+    def comp(src):
+        obj = os.path.join(HOST_SAN_DIR, os.path.basename(src) + ".o")
+        cmd = [HIPCC] + CFLAGS + HOST_SAN_FLAGS + ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-20000:]))
+        return obj
+
+    jobs = jobs or min(len(hip), os.cpu_count() or 4, 8)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(comp, hip))
+    # the objects carry their device code; the host link adds the shared sanitizer runtimes
+    clangxx = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "lib", "llvm", "bin", "clang++")
+    if not os.path.exists(clangxx):
+        clangxx = "/opt/rocm/lib/llvm/bin/clang++"
+    tmp = HOST_SAN_LIB + ".tmp%d" % os.getpid()
+    cmd = [clangxx, "-shared", "-fPIC", "-fsanitize=address,undefined", "-shared-libsan", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-20000:]))
+    os.replace(tmp, HOST_SAN_LIB)
+    with open(stamp, "w") as fh:
+        fh.write(h.hexdigest())
+    return HOST_SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--host-sanitized" in sys.argv:
+        print(build_host_sanitized())
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -265,7 +265,7 @@ static void plan_fft_pass(nfft_plan_s *p, int t, bool forward, bool first_or_las
         }
         const int inner = (int)p->n[d - 1];
         nl = std::min<int>(inner, std::max(1, maxPts / L));
-        nl = std::min(nl, std::min(256, p->dbl ? 8 : 16));
+        nl = std::min(nl, std::min(256, 16));  // 16 adjacent columns: 128 / 256-byte row segments
         // a power of two that divides n_{d-1} (n_{d-1} is even, so 2 always does)
         {
             int v = 1;

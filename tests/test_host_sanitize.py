@@ -5,7 +5,7 @@
 grouping, the tuning caches' parsing and writing, argument checks); the CPU tests of the C
 ABI and of the host logic then run against that copy in a child process with the ASan
 runtime preloaded, and any sanitizer report fails them.  Leak detection is off: the Python
-interpreter itself holds memory at exit.  The first run builds (a few minutes); later runs
+interpreter itself holds memory at exit.  The first run builds (about a minute); later runs
 reuse the build while the sources are unchanged.
 """
 import os

@@ -163,6 +163,33 @@ def test_spread_by_output_tiles_3d(case, dtype, m):
         assert e2 < TOL[dtype] and emax < 2e-5, (e2, emax)
 
 
+@pytest.mark.parametrize("dtype,m", [(C128, 8), (C64, 10)], ids=["c128m8", "c64m10"])
+def test_spread_by_output_tiles_widest_stencils(dtype, m):
+    """The output-tile spreading at the widest stencils a 3-D plan accepts (2m + 2 = 18
+    points per dimension in complex128, 22 in complex64: the largest factor records in
+    LDS), uniform and clustered nodes, against the oracle: the spread grid, the adjoint and
+    the forward transform."""
+    N, n = (32, 24, 32), (64, 48, 64)
+    for kind, M in (("uniform", 2500), ("clustered", 2500)):
+        announce("owner tiles wide", N, M, kind, dtype, m)
+        c = W.small_case(3, N, M, seed=560 + m, kind=kind)
+        p = make_plan(N, M, m, dtype, n=n)
+        assert p.info.own_tiles > 0
+        p.set_nodes(dev(c["x"], torch.float64))
+        S = float(np.prod([np.exp(np.pi * (2.0 - Nt / nt) * m) for Nt, nt in zip(N, n)]))
+        gs = host(p.step_spread(dev(c["f"], dtype)))
+        assert parity_err(O.nfft_spread(c["x"], c["f"], N, n, m) / S, gs) < TOL[dtype]
+        h = host(p.adjoint(dev(c["f"], dtype)))
+        ref = O.nfft_adjoint(c["x"], c["f"], N, n, m)
+        if dtype == C128:
+            assert parity_err(ref, h) < TOL[dtype]
+        else:
+            e2, emax = adjoint_errors(c["x"], c["f"], N, n, m, h, ref=ref)
+            assert e2 < TOL[dtype] and emax < 2e-5, (e2, emax)
+        f = host(p.trafo(dev(c["fhat"], dtype)))
+        assert parity_err(O.nfft_trafo(c["x"], c["fhat"], n, m), f) < TOL[dtype]
+
+
 def test_edge_nodes_and_tiny_grids():
     """Nodes on the torus edges and outside [-1/2,1/2); grids where the padded tile wraps
     around the grid more than once (n = 16 with m = 6); a single node."""

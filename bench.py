@@ -626,6 +626,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the d=2 steps as captured HIP graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the E_2 checks")
     ap.add_argument("--primary-only", action="store_true", help="only the headline plan")
+    ap.add_argument("--d2-only", action="store_true",
+                    help="only the d=2 N=512^2 complex64 m=8 workload, K steps (for profiling; prints its own line)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -652,6 +654,16 @@ def main():
     C64, C128 = torch.complex64, torch.complex128
     KB, GAUSS = "kaiser-bessel", "gaussian"
     check = not args.no_cpu
+
+    if args.d2_only:
+        w = W.workload("d2", m=8)
+        case = Case(w, 8, C64, torch, KB)
+        t_nodes = case.set_nodes_ms()
+        ms, med, _ = case.time_steps(args.steps, 1, events=False)
+        print(json.dumps({"workload": "d=2 N=(512,512) n=(1024,1024) M=262144 uniform nodes, kaiser-bessel m=8, "
+                                      "complex64, trafo+adjoint", "steps": args.steps, "ms_per_step": ms,
+                          "points_per_s": w["M"] / (ms * 1e-3), "set_nodes_ms": t_nodes}), flush=True)
+        return
 
     # ---------------------------------------------------------------- headline: 3-D radial, c128
     w3 = W.workload("d3r")

@@ -24,12 +24,81 @@ using namespace window;
 
 // ------------------------------------------------------------------ interpolation
 
+// One work item c of a 3-D plan whose padded tile exceeds the LDS (g.islab > 0, at most
+// kBlock nodes per item): the tile is staged g.islab planes at a time, and each thread keeps
+// its node's sum across the slabs, adding the planes of its stencil that each slab holds in
+// plane order -- the same sums in the same order as with the whole tile.
+template <typename T, int WM>
+__device__ __forceinline__ void interp_item_slab(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ grid,
+                                                 Cplx<T> *__restrict__ f, int c, Cplx<T> *tile)
+{
+    using C = Cplx<T>;
+    const T *psi = static_cast<const T *>(nd.psi);
+    const int W = g.W;
+    const int first = nd.chunk_first[c];
+    const int len = nd.chunk_len[c];
+    int bc[kMaxDim];
+    bin_coords<T, 3>(g, nd.chunk_bin[c], bc);
+    const bool has = (int)threadIdx.x < len;
+    const int node = first + (has ? (int)threadIdx.x : 0);
+    int ul[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        ul[t] = nd.u[t][node] & ((1 << g.lgB[t]) - 1);
+    const T *pw = psi + (int64_t)node * 3 * W;  // window factors [3][W] of this node
+    T w1[WM], w2[WM];
+#pragma unroll
+    for (int s = 0; s < WM; ++s) {
+        w1[s] = s < W ? pw[W + s] : T(0);
+        w2[s] = s < W ? pw[2 * W + s] : T(0);
+    }
+    const int P0 = g.P[0], P1 = g.P[1], P2 = g.P[2];
+    T ax = 0, ay = 0;
+    for (int z0 = 0; z0 < P0; z0 += g.islab) {
+        const int S = min(g.islab, P0 - z0);
+        __syncthreads();  // the previous slab is consumed
+        stage_slab<T>(g, bc, z0, S, grid, tile);
+        __syncthreads();
+        if (has) {
+            const int lo = max(0, z0 - ul[0]), hi = min(W, z0 + S - ul[0]);
+            for (int s0 = lo; s0 < hi; ++s0) {
+                const T w0 = pw[s0];
+                const C *plane = tile + ((ul[0] + s0 - z0) * P1 + ul[1]) * P2 + ul[2];
+                T px = 0, py = 0;
+#pragma unroll
+                for (int s1 = 0; s1 < WM; ++s1) {
+                    T rx = 0, ry = 0;
+#pragma unroll
+                    for (int s2 = 0; s2 < WM; ++s2) {
+                        const C v = lds_entry<T>(plane + s1 * P2 + s2);
+                        rx += w2[s2] * v.x;
+                        ry += w2[s2] * v.y;
+                    }
+                    px += w1[s1] * rx;
+                    py += w1[s1] * ry;
+                }
+                ax += w0 * px;
+                ay += w0 * py;
+            }
+        }
+    }
+    if (has)
+        f[nd.perm[node]] = C{ax, ay};
+    __syncthreads();
+}
+
 // One work item c of a plan: stage the bin's padded tile, then interpolate its nodes.
 template <typename T, int D, int WM>
 __device__ __forceinline__ void interp_item(const Geom &g, const Nodes &nd, const Cplx<T> *__restrict__ grid,
                                             Cplx<T> *__restrict__ f, int c, Cplx<T> *tile)
 {
     using C = Cplx<T>;
+    if constexpr (D == 3) {
+        if (g.islab > 0) {
+            interp_item_slab<T, WM>(g, nd, grid, f, c, tile);
+            return;
+        }
+    }
     const T *psi = static_cast<const T *>(nd.psi);
     const int W = g.W;
     const int dW = D * W;
@@ -588,8 +657,9 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 {
     using C = Cplx<T>;
     // 3-D by lane groups, except complex128 stencils of 22 or more points, whose registers
-    // do not fit eight waves (those take the kernel with one node per thread)
-    if (D == 3 && !(sizeof(T) == 8 && g.WM >= 22)) {
+    // do not fit eight waves, and plans staged in slabs (those take the kernel with one node
+    // per thread)
+    if (D == 3 && g.islab == 0 && !(sizeof(T) == 8 && g.WM >= 22)) {
         // persistent workgroups of eight waves: as many as are resident at once (registers
         // and LDS), never more than the work items
         int dev = 0, cus = 0;
@@ -629,6 +699,8 @@ hipError_t interp_typed(const Geom &g, const Nodes &nd, const void *grid, void *
 // d = 3 one dummy entry after the tile (the target of stores past it)
 size_t interp_lds_bytes(const Geom &g, bool dbl)
 {
+    if (g.islab > 0)
+        return (size_t)g.islab * g.P[1] * g.P[2] * (dbl ? 16 : 8);
     return ((size_t)g.Ptot + (g.d == 2 ? 256 : 0) + (g.d == 3 ? 1 : 0)) * (dbl ? 16 : 8);
 }
 // spreading tiles per workgroup: four (1-D); two (2-D) or one (3-D) followed by one dummy

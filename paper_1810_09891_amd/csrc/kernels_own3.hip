@@ -270,10 +270,13 @@ template <typename T, int W> struct OwnLds {
 // Stage entries q, q + stride, ..., q + (nb - 1) stride of the tile's list (ent): packed
 // offsets, sorted positions, window factors, and with `fs` (node values in sorted order) the
 // values.  Every load is issued before the first LDS store; ends with a barrier.
-template <typename T, int W>
+// The factor table holds WR <= W factors per dimension (the plan's stencil, W the compiled
+// width; WR = 0: the runtime width wr, for odd m); the record entries past it stay zero.
+template <typename T, int W, int WR>
 __device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, const int2 *__restrict__ ent, int q,
-                                          int nb, const Cplx<T> *__restrict__ fs, int stride = 1)
+                                          int nb, const Cplx<T> *__restrict__ fs, int stride, int wr_rt)
 {
+    const int wr = WR > 0 ? WR : wr_rt;
     using R = OwnRec<T, W>;
     const T *__restrict__ psi = static_cast<const T *>(nd.psi);
     int2 e{0, 0};
@@ -288,13 +291,13 @@ __device__ __forceinline__ void own_stage(const Nodes &nd, OwnLds<T, W> &L, cons
 #pragma unroll
     for (int j = 0; j < R::NL; ++j) {
         const int idx = threadIdx.x + j * kBlock;
-        const int k = idx / (3 * W);
-        const int rr = idx - k * (3 * W);
+        const int k = idx / (3 * wr);
+        const int rr = idx - k * (3 * wr);
         const bool ok = k < nb;
         const int p = ent[q + (ok ? k : 0) * stride].x;
-        v[j] = psi[(int64_t)p * (3 * W) + (ok ? rr : 0)];
-        const int t = rr / W;
-        const int s = rr - t * W;
+        v[j] = psi[(int64_t)p * (3 * wr) + (ok ? rr : 0)];
+        const int t = rr / wr;
+        const int s = rr - t * wr;
         dst[j] = ok ? k * R::REC + (t == 0 ? s : (t == 1 ? R::D1 + 8 + s : R::D2 + 8 + s)) : -1;
     }
     if ((int)threadIdx.x < nb) {
@@ -379,7 +382,10 @@ __device__ __forceinline__ void own_mx_batch(const T *__restrict__ psi, const Cp
 
 template <typename T, int W> constexpr int own_mx_waves() { return 3; }
 
-template <typename T, int W>
+// NARROW: the plan's stencil is narrower than the compiled width W (odd m), its factor table
+// holds g.W < W factors per dimension (a separate instantiation, so that the staging of the
+// common case keeps its compile-time divisions and register budget)
+template <typename T, int W, bool NARROW>
 __global__ __launch_bounds__(kBlock, (own_mx_waves<T, W>())) void k_spread_own_mx(Geom g, Nodes nd,
                                                                               const Cplx<T> *__restrict__ fs,
                                                                               Cplx<T> *__restrict__ grid,
@@ -428,7 +434,7 @@ __global__ __launch_bounds__(kBlock, (own_mx_waves<T, W>())) void k_spread_own_m
         for (int b = 0; b < nbat; ++b) {
             const int nb = (cnt - b + nbat - 1) / nbat;
             __syncthreads();  // the previous batch is consumed
-            own_stage<T, W>(nd, L, ent, lo + b, nb, fs, nbat);
+            own_stage<T, W, NARROW ? 0 : W>(nd, L, ent, lo + b, nb, fs, nbat, g.W);
             const int emeta = lane < nb ? L.meta[lane] : 0;
             const bool mine = emeta != 0 && ((emeta >> (24 + wave)) & 1);
             const uint64_t bits = __ballot(mine);
@@ -547,7 +553,7 @@ hipError_t launch_own_items(const Geom &g, const Nodes &nd, hipStream_t s)
 hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const void *f, void *fs, void *grid,
                              void *scratch, int max_items, hipStream_t s)
 {
-    if (g.d != 3 || !g.own || g.W != g.WM || g.oT[0] != kOwnTile0)
+    if (g.d != 3 || !g.own || g.W > g.WM || g.oT[0] != kOwnTile0)
         return hipErrorInvalidValue;
     const int blocks = max_items > 0 ? max_items : 1;
     if (dbl) {
@@ -555,8 +561,9 @@ hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const voi
         hipLaunchKernelGGL(k_own_gather<double>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, nd,
                            static_cast<const C *>(f), static_cast<C *>(fs));
 #define OWN_CASE(WMV)                                                                                       \
-    hipLaunchKernelGGL((k_spread_own_mx<double, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,              \
-                       static_cast<const C *>(fs), static_cast<C *>(grid), static_cast<C *>(scratch))
+    hipLaunchKernelGGL((g.W == g.WM ? k_spread_own_mx<double, WMV, false> : k_spread_own_mx<double, WMV, true>), \
+                       dim3(blocks), dim3(kBlock), 0, s, g, nd, static_cast<const C *>(fs), static_cast<C *>(grid), \
+                       static_cast<C *>(scratch))
         NFFT_WM_SWITCH(g.WM, OWN_CASE)
 #undef OWN_CASE
     } else {
@@ -564,8 +571,9 @@ hipError_t launch_spread_own(const Geom &g, const Nodes &nd, bool dbl, const voi
         hipLaunchKernelGGL(k_own_gather<float>, dim3(blocks_for(nd.M)), dim3(kBlock), 0, s, nd,
                            static_cast<const C *>(f), static_cast<C *>(fs));
 #define OWN_CASE(WMV)                                                                                       \
-    hipLaunchKernelGGL((k_spread_own_mx<float, WMV>), dim3(blocks), dim3(kBlock), 0, s, g, nd,               \
-                       static_cast<const C *>(fs), static_cast<C *>(grid), static_cast<C *>(scratch))
+    hipLaunchKernelGGL((g.W == g.WM ? k_spread_own_mx<float, WMV, false> : k_spread_own_mx<float, WMV, true>), \
+                       dim3(blocks), dim3(kBlock), 0, s, g, nd, static_cast<const C *>(fs), static_cast<C *>(grid), \
+                       static_cast<C *>(scratch))
         NFFT_WM_SWITCH(g.WM, OWN_CASE)
 #undef OWN_CASE
     }

@@ -287,6 +287,9 @@ struct Geom {
     int okn[kMaxDim];
     int oall[kMaxDim];
     int ocap;           // node-list entries per work item
+    // 3-D plans whose smallest padded tile exceeds the LDS: planes of the tile staged per
+    // interpolation slab (0: the whole tile at once)
+    int islab;
 };
 
 // Window factor of dimension t at stencil point s of a node with offset delta, and its

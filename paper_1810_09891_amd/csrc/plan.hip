@@ -85,14 +85,12 @@ static int choose_bins(nfft_plan_s *p, const int32_t *req)
     size_t extra = d >= 2 ? (size_t)kBlock * cs : 0;
     // 3-D plans that spread by output tiles (see setup_owner) keep no padded tile there: the
     // bins need only fit the interpolation kernel's one tile
-    if (d == 3 && 2 * p->m + 2 == p->WM) {
-        bool own = true;
-        for (int t = 0; t < d; ++t)
-            own = own && p->n[t] % kOwnTile12 == 0 && p->n[t] >= kOwnTile12 + p->WM - 1;
-        if (own) {
-            budget = kLdsMax - 1024;
-            extra = 0;
-        }
+    bool own3 = d == 3;
+    for (int t = 0; t < d && own3; ++t)
+        own3 = p->n[t] % kOwnTile12 == 0 && p->n[t] >= kOwnTile12 + p->WM - 1;
+    if (own3) {
+        budget = kLdsMax - 1024;
+        extra = 0;
     }
     const bool requested = req && req[0] > 0;
     if (requested) {
@@ -111,9 +109,24 @@ static int choose_bins(nfft_plan_s *p, const int32_t *req)
             break;
         B[best] /= 2;
     }
-    if (ntiles * lds_of(B) + extra > kLdsMax - 1024)
-        return NFFT_ERR_UNSUPPORTED;
+    // When even the smallest tile does not fit, 3-D plans that spread by output tiles stage
+    // their interpolation tile in slabs of planes along dimension 0 (8 x 8 x 8 bins, work
+    // items of at most kBlock nodes); other plans are refused.
+    int islab = 0;
+    size_t window_lds = lds_of(B);
+    if (ntiles * lds_of(B) + extra > kLdsMax - 1024) {
+        if (requested || !own3)
+            return NFFT_ERR_UNSUPPORTED;
+        for (int t = 0; t < d; ++t)
+            B[t] = 1 << ilog2(std::min<int64_t>(8, p->n[t]));
+        const size_t plane = cs * (size_t)(B[1] + p->WM - 1) * (size_t)(B[2] + p->WM - 1);
+        islab = (int)std::min<size_t>((kLdsMax - 1024) / plane, (size_t)(B[0] + p->WM - 1));
+        if (islab < 1)
+            return NFFT_ERR_UNSUPPORTED;
+        window_lds = plane * (size_t)islab;
+    }
     Geom &g = p->geom;
+    g.islab = islab;
     g.Ptot = 1;
     g.nbins = 1;
     for (int t = 0; t < kMaxDim; ++t) {
@@ -137,7 +150,7 @@ static int choose_bins(nfft_plan_s *p, const int32_t *req)
         if (pairs > 2)
             g.fold2 = 0;
     }
-    p->lds_window = lds_of(B);
+    p->lds_window = window_lds;
     return NFFT_OK;
 }
 
@@ -150,7 +163,7 @@ static void setup_owner(nfft_plan_s *p)
     Geom &g = p->geom;
     g.own = 0;
     p->own_max_items = 0;
-    if (p->d != 3 || g.W != g.WM)
+    if (p->d != 3 || g.W > g.WM)
         return;
     const int T[3] = {kOwnTile0, kOwnTile12, kOwnTile12};
     int okb[3], okn[3], oall[3];
@@ -556,8 +569,20 @@ static int create_plan(nfft_plan_s **out, int d, const int64_t *N, int64_t M, co
         p->chunk_cap *= 2;
     if (params && params->chunk_cap > 0)
         p->chunk_cap = params->chunk_cap;
+    if (g.islab > 0) {
+        // one node per thread across the slabs
+        if (p->chunk_cap > kBlock && params && params->chunk_cap > 0) {
+            delete p;
+            return NFFT_ERR_UNSUPPORTED;
+        }
+        p->chunk_cap = std::min(p->chunk_cap, kBlock);
+    }
     p->max_chunks = (int)(g.nbins + (M + p->chunk_cap - 1) / p->chunk_cap);
     setup_owner(p);
+    if (g.islab > 0 && !g.own) {  // the spreading tile would not fit either
+        delete p;
+        return NFFT_ERR_UNSUPPORTED;
+    }
     build_tables(p);
     // FFT passes
     p->fwd_passes.clear();
@@ -1080,6 +1105,8 @@ int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t s)
         return NFFT_ERR_ARG;
     if (!(p->flags & NFFT_KEEP_GRID) || !p->grid_valid)
         return NFFT_ERR_STATE;
+    if (p->geom.islab > 0)  // its gather keeps the whole padded tile in LDS
+        return NFFT_ERR_UNSUPPORTED;
     Nodes nd = plan_node_view(p);
     const void *grid = static_cast<char *>(p->ws) + p->off_grid;
     LAUNCH(p, s, "grad_x",

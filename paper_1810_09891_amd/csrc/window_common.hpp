@@ -110,6 +110,43 @@ __device__ __forceinline__ void stage_tile_w(const Geom &g, const int *bc, const
     }
 }
 
+// Planes z0 .. z0 + S - 1 (dimension 0) of the padded 3-D tile of bin `bc`, as the same
+// loads and stores as stage_tile_w over S P_1 P_2 entries.
+template <typename T, bool P2>
+__device__ __forceinline__ void stage_slab_w(const Geom &g, const int *bc, int z0, int S, const Cplx<T> *grid,
+                                             Cplx<T> *tile)
+{
+    using C = Cplx<T>;
+    constexpr int K = sizeof(T) == 4 ? 12 : 8;
+    TileMap<3, P2> map(g, bc);
+    map.o[0] += z0;
+    const int cnt = S * g.P[1] * g.P[2];
+    for (int base = 0; base < cnt; base += K * kBlock) {
+        C v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = base + threadIdx.x + k * kBlock;
+            v[k] = grid[map.src(g, idx < cnt ? idx : 0)];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = base + threadIdx.x + k * kBlock;
+            if (idx < cnt)
+                tile[idx] = v[k];
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_slab(const Geom &g, const int *bc, int z0, int S, const Cplx<T> *grid,
+                                           Cplx<T> *tile)
+{
+    if (g.p2)
+        stage_slab_w<T, true>(g, bc, z0, S, grid, tile);
+    else
+        stage_slab_w<T, false>(g, bc, z0, S, grid, tile);
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void stage_tile(const Geom &g, const int *bc, const Cplx<T> *grid, Cplx<T> *tile)
 {

@@ -83,13 +83,16 @@ def test_plan_validation(lib, N, M, n, m, expect):
         ((16, 16, 16), (32, 32, 32), 12, 1, UNSUP),  # 29^3 complex64 tile exceeds the LDS
         ((2048,), (4096,), 12, 2, OK),  # longest line and widest stencil
         ((2048, 8), (4096, 32), 12, 1, OK),
-        # 3-D on a grid with output-tile spreading: the widest accepted stencils are 2m + 2 =
-        # 18 (complex128) and 22 (complex64); one more point each and the smallest padded
-        # interpolation tile, (2m + 2)^3 entries, no longer fits
-        ((32, 24, 32), (64, 48, 64), 8, 2, OK),
-        ((32, 24, 32), (64, 48, 64), 9, 2, UNSUP),
-        ((32, 24, 32), (64, 48, 64), 10, 1, OK),
-        ((32, 24, 32), (64, 48, 64), 11, 1, UNSUP),
+        # 3-D: past complex128 m = 8 and complex64 m = 10 the smallest padded interpolation
+        # tile no longer fits; grids that spread by output tiles (n_t multiples of 16) stage
+        # it in slabs and take every m up to 12, other grids refuse
+        ((32, 24, 32), (64, 48, 64), 9, 2, OK),
+        ((32, 24, 32), (64, 48, 64), 12, 2, OK),
+        ((32, 24, 32), (64, 48, 64), 12, 1, OK),
+        ((20, 20, 20), (40, 40, 40), 8, 2, OK),
+        ((20, 20, 20), (40, 40, 40), 9, 2, UNSUP),
+        ((20, 20, 20), (40, 40, 40), 10, 1, OK),
+        ((20, 20, 20), (40, 40, 40), 11, 1, UNSUP),
     ],
 )
 def test_lds_limits(lib, N, n, m, dtype, expect):

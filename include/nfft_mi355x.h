@@ -152,7 +152,7 @@ typedef struct {
  *          smallest tile does not fit (complex128 m >= 9, complex64 m >= 11) are accepted
  *          when every n_t is a multiple of 16 with n_t >= 16 + 2m + 1 (spreading by output
  *          tiles): their interpolation stages the tile in slabs of planes, and such plans do
- *          not take nfft_grad_x or nfft_batch_create (NFFT_ERR_UNSUPPORTED).
+ *          not take nfft_grad_x (NFFT_ERR_UNSUPPORTED).
  *   dtype  NFFT_C64 or NFFT_C128.
  * Host only: no device work, no device memory.  *out receives the plan. */
 int nfft_plan_create(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,

@@ -435,9 +435,6 @@ int nfft_batch_create(nfft_batch *out, int count, const nfft_plan *plans, const 
                 return NFFT_ERR_ARG;
     }
     for (int i = 0; i < count; ++i)
-        if (plans[i]->geom.islab > 0)  // interpolation staged in slabs: per-plan calls only
-            return NFFT_ERR_UNSUPPORTED;
-    for (int i = 0; i < count; ++i)
         if (!plans[i]->ws)
             return NFFT_ERR_WORKSPACE;
     nfft_batch_s *b = new (std::nothrow) nfft_batch_s();

@@ -55,7 +55,7 @@ def test_wide_and_odd_stencils_3d(dtype, m, kind, M):
     assert e2 < TOL[dtype] and emax < EMAX[dtype], (e2, emax)
 
 
-def test_slab_plans_refuse_gradient_and_batching():
+def test_slab_plans_refuse_the_node_gradient():
     N, M, m = N3, 500, 10
     c = W.small_case(3, N, M, seed=599)
     p = Plan(N, M, n=n3, m=m, dtype=C128, flags=NFFT_KEEP_GRID)
@@ -64,10 +64,33 @@ def test_slab_plans_refuse_gradient_and_batching():
     with pytest.raises(NfftError) as e:
         p.grad_x(dev(c["f"], C128))
     assert e.value.status == -5
-    with pytest.raises(NfftError) as e:
-        Batch([p])
-    assert e.value.status == -5
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [C128, C64], ids=["c128", "c64"])
+def test_batch_with_slab_plans(dtype):
+    """Slab plans (and a narrower-stencil plan of the same compiled width) in one batch: each
+    batched result equals the per-plan call."""
+    ms = (9, 10) if dtype == C128 else (11, 12)
+    specs = [(N3, n3, 2000, ms[0]), (N3, n3, 1500, ms[1]), ((16, 16, 16), (32, 32, 32), 900, 4)]
+    announce("batch slab plans", dtype)
+    plans, cases = [], []
+    for i, (N, n, M, m) in enumerate(specs):
+        c = W.small_case(3, N, M, seed=610 + i)
+        p = Plan(N, M, n=n, m=m, dtype=dtype)
+        p.set_nodes(dev(c["x"], torch.float64))
+        plans.append(p)
+        cases.append(c)
+    fs = [host(p.trafo(dev(c["fhat"], dtype))) for p, c in zip(plans, cases)]
+    hs = [host(p.adjoint(dev(c["f"], dtype))) for p, c in zip(plans, cases)]
+    b = Batch(plans)
+    bf = [host(v) for v in b.trafo([dev(c["fhat"], dtype) for c in cases])]
+    bh = [host(v) for v in b.adjoint([dev(c["f"], dtype) for c in cases])]
+    same = 1e-14 if dtype == C128 else 1e-6
+    for i in range(len(specs)):
+        assert rel_l2(fs[i], bf[i]) <= same, i
+        assert rel_l2(hs[i], bh[i]) <= same, i
+    b.close()
 
 
 def test_fig_4_4_window_sweep_d3():

@@ -151,8 +151,7 @@ typedef struct {
  *          tile fits the LDS of one workgroup (else NFFT_ERR_UNSUPPORTED).  3-D plans whose
  *          smallest tile does not fit (complex128 m >= 9, complex64 m >= 11) are accepted
  *          when every n_t is a multiple of 16 with n_t >= 16 + 2m + 1 (spreading by output
- *          tiles): their interpolation stages the tile in slabs of planes, and such plans do
- *          not take nfft_grad_x (NFFT_ERR_UNSUPPORTED).
+ *          tiles): their interpolation and node gradient stage the tile in slabs of planes.
  *   dtype  NFFT_C64 or NFFT_C128.
  * Host only: no device work, no device memory.  *out receives the plan. */
 int nfft_plan_create(nfft_plan *out, int d, const int64_t *N, int64_t M, const int64_t *n, int m,
@@ -267,8 +266,7 @@ int ndft_adjoint(nfft_plan p, const void *f, void *hhat, hipStream_t stream);
  * Algorithm 2.1 step 3 (d/dx_t phi(n_t x_t - l_t) = n_t phi'(.)).  grad_x [device,
  * M x d] is float for NFFT_C64 plans and double for NFFT_C128 plans.  Needs
  * NFFT_KEEP_GRID and a preceding nfft_trafo on the same nodes (its grid is used);
- * else NFFT_ERR_STATE.  NFFT_ERR_UNSUPPORTED for 3-D plans whose interpolation tile is
- * staged in slabs (see m at nfft_plan_create). */
+ * else NFFT_ERR_STATE. */
 int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t stream);
 
 /* ---------------------------------------------------------------- single steps */

@@ -1105,8 +1105,6 @@ int nfft_grad_x(nfft_plan p, const void *v, void *grad_x, hipStream_t s)
         return NFFT_ERR_ARG;
     if (!(p->flags & NFFT_KEEP_GRID) || !p->grid_valid)
         return NFFT_ERR_STATE;
-    if (p->geom.islab > 0)  // its gather keeps the whole padded tile in LDS
-        return NFFT_ERR_UNSUPPORTED;
     Nodes nd = plan_node_view(p);
     const void *grid = static_cast<char *>(p->ws) + p->off_grid;
     LAUNCH(p, s, "grad_x",

@@ -317,6 +317,56 @@ def bench_d1(torch, steps, warmup, check):
     return r
 
 
+# Fig. 4.5 (d = 3) of the paper: its forward transform times in ms (and precomputation
+# times) for the test polynomial f_3, N = 32^3, M = 65536, n = 2N, against the window size m
+PAPER_FIG45_D3 = {"trafo_ms": {2: 39.57, 3: 80.42, 4: 191.90, 5: 311.19, 6: 468.07, 7: 657.49, 8: 896.82,
+                               9: 1182.30, 10: 1529.24},
+                  "precompute_ms": {2: 60.00, 3: 76.88, 4: 93.51, 5: 109.09, 6: 114.44, 7: 124.89, 8: 138.31,
+                                    9: 153.43, 10: 163.47}}
+
+
+def bench_window_sweep_d3(torch, steps, warmup, check):
+    """The paper's d = 3 window-size sweep (Fig. 4.4(a) errors, Fig. 4.5 times): test
+    polynomial f_3, N = 32^3, M = 65536 uniform nodes, n = 2N, complex128, m = 2 .. 10.  m >= 9
+    stage the interpolation tile in slabs.  Per m: forward-only and forward+adjoint time, node
+    precomputation, and E_2 against the GPU's direct sums."""
+    import numpy as np
+
+    from paper_1810_09891_amd import workloads as W
+
+    w = dict(W.paper_workload(3))
+    w["n"] = tuple(2 * v for v in w["N"])
+    r = np.random.default_rng(4545)
+    w["f"] = r.standard_normal(w["M"]) + 1j * r.standard_normal(w["M"])
+    per_m = {}
+    ref = None
+    for m in range(2, 11):
+        case = Case(w, m, torch.complex128, torch)
+        t_nodes = case.set_nodes_ms()
+        ms, _, _ = case.time_steps(steps, warmup, False)
+        p = case.plan
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(case.stream)
+        for _ in range(steps):
+            p.trafo(case.fhat, out=case.out_f)
+        b.record(case.stream)
+        torch.cuda.synchronize()
+        e = {"trafo_ms": a.elapsed_time(b) / steps, "trafo_adjoint_ms": ms, "set_nodes_ms": t_nodes}
+        if check:
+            if ref is None:
+                ref = p.ndft_trafo(case.fhat).cpu().numpy()
+            e["e2_trafo_vs_ndft"] = e2(ref, case.out_f.cpu().numpy())
+        e["paper_trafo_ms"] = PAPER_FIG45_D3["trafo_ms"][m]
+        per_m[str(m)] = e
+        del case, p
+        torch.cuda.empty_cache()
+    return {"workload": "paper test polynomial f_3: d=3 N=(32,32,32) n=(64,64,64) M=65536 uniform, complex128, "
+                        "m=2..10 (m >= 9: interpolation in slabs)",
+            "per_m": per_m, "ms_per_step": per_m["8"]["trafo_adjoint_ms"],
+            "points_per_s": w["M"] / (per_m["8"]["trafo_adjoint_ms"] * 1e-3),
+            "paper_context": "Fig. 4.5 (d = 3): forward transform times of the paper's CPU runs, per m"}
+
+
 D3_WORKLOAD = ("d=3 N=(128,128,128) n=(256,256,256) M=2097152 on 4096 radial spokes of 512 points "
                "(density clustered at the origin), Kaiser-Bessel m=6, %s, trafo+adjoint")
 
@@ -721,7 +771,8 @@ def main():
         for name, fn, st in (("d1_256_c128_m8", bench_d1, 200), ("batch64_c64_m6", bench_batch, 20),
                              ("grad_radial_256_c64_m6", bench_grad, 20),
                              ("fastsum_gauss_128_c64_m6", bench_fastsum, 50),
-                             ("nnfft_d2_256_c64_m8", bench_nnfft, 50)):
+                             ("nnfft_d2_256_c64_m8", bench_nnfft, 50),
+                             ("window_sweep_d3_32_c128", bench_window_sweep_d3, 20)):
             t0 = time.perf_counter()
             extra[name] = fn(torch, st, 3, check)
             log("%s: %.4f ms/step, %.3e points/s (%.1f s)" %
